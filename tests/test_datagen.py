@@ -1,0 +1,37 @@
+"""The synthetic inputs have the shapes and structure stated for each workload."""
+import numpy as np
+
+from paper_1307_3519_amd import datagen
+
+
+def test_small_workload_structure():
+    w = datagen.make_workload(1)
+    x, g = w["expr"], w["geno"]
+    assert x.shape == (1000, 102) and x.dtype == np.float32
+    assert g.shape == (2000, 102) and g.dtype == np.int8
+    assert set(np.unique(g)) <= {0, 1, 2}
+    # ~10% of SNPs miss one genotype class at K=102 (df = 1)
+    present = np.stack([(g == c).any(axis=1) for c in range(3)], 1).sum(1)
+    assert 0.075 <= np.mean(present == 2) <= 0.11
+    # ties: every row has repeated values
+    n_unique = np.array([len(np.unique(r)) for r in x])
+    assert np.all(n_unique <= 102 - 1) and np.mean(n_unique) >= 102 - 5.5
+    # determinism
+    w2 = datagen.make_workload(1)
+    assert np.array_equal(w2["expr"], x) and np.array_equal(w2["geno"], g)
+
+
+def test_planted_and_missing_and_perms():
+    w = datagen.make_workload(2, T=300, M=4000, n_plant=50)
+    assert w["planted"].shape == (50, 3)
+    assert len(np.unique(w["planted"][:, 0])) == 50
+    for t, m, _ in w["planted"]:
+        assert min((w["geno"][m] == c).sum() for c in range(3)) >= 2
+    w = datagen.make_workload(4, T=10, M=10, P=7)
+    assert w["perms"].shape == (7, 102)
+    for p in w["perms"]:
+        assert np.array_equal(np.sort(p), np.arange(102))
+    cs = datagen.make_cohorts(M=500, T_scale=0.01)
+    assert [c["K"] for c in cs] == list(datagen.COHORT_K)
+    frac = np.mean(np.concatenate([(c["geno"] == -1).ravel() for c in cs]))
+    assert 0.015 < frac < 0.025
