@@ -205,13 +205,14 @@ static void pair_from_sums(oracle_pair* o) {
 static void pair_stat(const float* x, const int8_t* g, int32_t K,
                       const int32_t* a2_full, int64_t ts_full, int32_t kobs_full,
                       uint8_t* keep, int32_t* a2_tmp, oracle_pair* o) {
+    /* a genotype is a code 0..2; anything else (-1 by convention) is missing */
     int missing = 0;
-    for (int k = 0; k < K; k++) missing |= (g[k] < 0);
+    for (int k = 0; k < K; k++) missing |= (g[k] < 0 || g[k] > 2);
     const int32_t* a2 = a2_full;
     o->tiesum = ts_full;
     o->kobs = kobs_full;
     if (missing) {
-        for (int k = 0; k < K; k++) keep[k] = (uint8_t)(g[k] >= 0);
+        for (int k = 0; k < K; k++) keep[k] = (uint8_t)(g[k] >= 0 && g[k] <= 2);
         rank_row(x, keep, K, a2_tmp, &o->tiesum, &o->kobs);
         a2 = a2_tmp;
     }

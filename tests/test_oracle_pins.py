@@ -274,6 +274,9 @@ def test_missing_genotype_equals_kept_samples():
         assert o["H"] == pytest.approx(H, rel=tol, abs=1e-12)
         sub = oracle.one_pair(x[t][keep], g[t][keep])
         assert sub["H"] == o["H"] and sub["tiesum"] == o["tiesum"]
+        # any code outside 0..2 is missing, not only -1
+        g2 = g[t].copy(); g2[g2 < 0] = 7
+        assert oracle.one_pair(x[t], g2)["H"] == o["H"]
 
 
 # ---------------------------------------------------------------- rounding
