@@ -1,0 +1,185 @@
+/*
+ * krux.h -- C ABI of the MI355X (gfx950) Kruskal-Wallis SNP x trait scan.
+ *
+ * The method is kruX (Qi, Foroughi Asl, Bjorkegren, Michoel,
+ * arXiv:1307.3519): per-trait ranks with a tie term, per-genotype-group rank
+ * sums as products of the rank matrix with genotype indicator matrices
+ * (eq. (1)), the Kruskal-Wallis statistic of eq. (2) divided by the tie
+ * factor 1 - sum(T)/(K^3-K), and a chi-square p-value per SNP x trait pair.
+ *
+ * Conventions for every entry point
+ *   - Array arguments are DEVICE pointers unless marked (host).  Matrices are
+ *     row-major with the sample index contiguous.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Work is enqueued on it and the call returns after enqueue, except where
+ *     a function says it synchronises.
+ *   - Argument errors are found before anything is launched; then nothing is
+ *     launched, the call returns a status other than KRUX_OK and
+ *     krux_last_error() describes the problem.
+ *   - The caller owns every buffer it passes; the library never frees caller
+ *     memory.  The context owns its scratch memory (allocated at first use,
+ *     grown as needed, freed by krux_destroy).  Calls on one context must not
+ *     overlap in time (one context per host thread).
+ *   - Doubled midranks: a = 2 x (average rank), i.e.
+ *     a_k = 2 #{j: x_j < x_k} + #{j: x_j == x_k} + 1, an integer in [2, 2K];
+ *     0 marks a missing (NaN) expression value.
+ *   - Genotype codes: 0, 1, 2 (copies of the minor allele).  Any other code
+ *     (-1 by convention) is missing: that sample is removed from that pair
+ *     and the ranks are recomputed over the remaining samples (the paper's
+ *     missing-genotype rule).
+ *   - The statistic H of a pair is the exact rational value of eq. (2)
+ *     divided by the tie factor, rounded once to the nearest double; groups
+ *     with no sample are dropped (df = #non-empty groups - 1, the paper's
+ *     NaN-to-zero rule).  p = exp(-H/2) for df = 2, erfc(sqrt(H/2)) for
+ *     df = 1, and H = 0, p = 1 for df = 0 or an all-tied trait.
+ *   - A pair is a hit at threshold P_c iff df >= 1 and H > H_c(df), with
+ *     H_c from krux_threshold (the paper's statistic-threshold rule).
+ */
+#ifndef KRUX_H
+#define KRUX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KRUX_OK = 0,
+    KRUX_ERR_ARG = 1,         /* null pointer, negative size, bad enum, ... */
+    KRUX_ERR_SHAPE = 2,       /* inconsistent sizes or strides */
+    KRUX_ERR_UNSUPPORTED = 3, /* valid but outside what this build handles */
+    KRUX_ERR_NOMEM = 4,       /* scratch allocation failed */
+    KRUX_ERR_HIP = 5          /* a HIP runtime call failed */
+} krux_status;
+
+typedef struct krux_ctx krux_ctx;
+
+/* One significant pair.  `snp` is global: snp_base + local SNP index. */
+typedef struct {
+    int32_t trait;
+    int32_t snp;
+    double H;
+    double p;
+} krux_hit;
+
+enum {
+    KRUX_MODE_HITS = 0, /* compacted hit list (+ optional per-trait min p) */
+    KRUX_MODE_FULL = 1, /* H and p for every pair (T x M doubles each) */
+    KRUX_MODE_SUMS = 2  /* doubled group rank sums for every pair */
+};
+
+enum {
+    KRUX_PREC_FP16 = 0, /* fp16 MFMA, fp32 accumulation: exact rank sums, K <= 2049 */
+    KRUX_PREC_INT8 = 1, /* int8 MFMA, i32 accumulation (byte split above K = 127) */
+    KRUX_PREC_FP64 = 2  /* comparator: the paper's matrix formulation with fp64
+                           GEMMs of the rank and indicator matrices (one per
+                           genotype class) and an element-wise pass */
+};
+
+/* Largest supported sample count of each path. */
+#define KRUX_MAX_K_RANK 8192
+#define KRUX_MAX_K_FP16 2049
+
+/* Create a context on HIP device `device`.  Returns KRUX_OK and *out, or an
+ * error (then *out is NULL). */
+krux_status krux_create(krux_ctx** out, int device);
+
+/* Free a context and all its scratch memory.  Synchronises its device. */
+void krux_destroy(krux_ctx* ctx);
+
+/* Message for the last failing call on `ctx` (or on a NULL ctx). Never NULL. */
+const char* krux_last_error(const krux_ctx* ctx);
+
+/* Statistic threshold for a p-value threshold (P-value calculation section):
+ * *H_c (host) = the largest double h >= 0 whose chi-square tail at df,
+ * evaluated on the host, is still >= p_c.  So H > H_c exactly when the
+ * host-evaluated p-value of H is below p_c.  p_c in (0, 1]; df in {1, 2}. */
+krux_status krux_threshold(double p_c, int32_t df, double* H_c);
+
+/* Per-row ranking (Implementation, input data; handling tied data).
+ *   expr    T x K float32, row stride ld_expr >= K (elements).
+ *   ranks2  T x K int16 doubled midranks (row stride K); 0 for NaN entries,
+ *           which are excluded from the ranking.
+ *   tiesum  T int64: sum over tie groups of t^3 - t (over non-NaN values).
+ *   nvalid  T int32 or NULL: number of non-NaN values per row.
+ * -0.0 and +0.0 are one value.  1 <= K <= KRUX_MAX_K_RANK. */
+krux_status krux_rank(krux_ctx* ctx, const float* expr, int64_t T, int32_t K,
+                      int64_t ld_expr, int16_t* ranks2, int64_t* tiesum,
+                      int32_t* nvalid, void* stream);
+
+/* Kruskal-Wallis test of every trait against every SNP of a slice
+ * (eq. (1), eq. (2), tie factor, P-value calculation; data slicing).
+ *   ranks2, tiesum  from krux_rank; every row must be complete (no 0 rank:
+ *                   missing expression values are not handled by this call).
+ *   geno            M x K int8, row stride ld_geno >= K (bytes).
+ *   snp_base        added to the SNP index of every hit (slice start).
+ *   p_c             p-value threshold, (0, 1] (HITS mode).
+ *   mode            KRUX_MODE_*; precision KRUX_PREC_*.
+ * HITS: hits[hit_capacity] receives the pairs with H > H_c(df) sorted by
+ *       (trait, snp); *n_hits (device int64) the true count, which may exceed
+ *       hit_capacity (then the kept subset is unspecified: call again with a
+ *       larger buffer).  min_p (device, T doubles, may be NULL) receives the
+ *       minimum p over the slice's SNPs per trait.
+ * FULL: H and p (device, T x M doubles each, row stride M) for every pair.
+ * SUMS: sums (device, 3 x T x M int32): doubled rank sums of genotype groups
+ *       0, 1, 2 (sum of ranks2 over the group's non-missing samples, with the
+ *       ranks recomputed when the SNP has missing genotypes).
+ * Unused outputs may be NULL. */
+krux_status krux_test(krux_ctx* ctx, const int16_t* ranks2, const int64_t* tiesum,
+                      int64_t T, int32_t K, const int8_t* geno, int64_t M,
+                      int64_t ld_geno, int64_t snp_base, double p_c,
+                      int32_t mode, int32_t precision,
+                      krux_hit* hits, int64_t hit_capacity, int64_t* n_hits,
+                      double* min_p, double* H, double* p, int32_t* sums,
+                      void* stream);
+
+/* Permuted-data repeats for the empirical FDR (P-value calculation and
+ * empirical FDR correction): for each permutation pi (perms, P x K int32,
+ * each a permutation of 0..K-1) the rank matrix columns are permuted, the
+ * same pi for every trait: trait row n is read as a'(k) = a(n, pi(k)).
+ *   p_cs    (host) n_thr p-value thresholds, each in (0, 1].
+ *   counts  P x n_thr int64: number of hits at each threshold.
+ *   min_p   P x T doubles or NULL: per permutation and trait, min p over SNPs.
+ * The whole batch is one graph of launches, replayed when the call is
+ * repeated with the same arguments. */
+krux_status krux_permute(krux_ctx* ctx, const int16_t* ranks2, const int64_t* tiesum,
+                         int64_t T, int32_t K, const int8_t* geno, int64_t M,
+                         int64_t ld_geno, const int32_t* perms, int32_t P,
+                         const double* p_cs, int32_t n_thr, int64_t* counts,
+                         double* min_p, void* stream);
+
+/* One cohort of a batched scan: its own samples (K), traits and genotype
+ * matrix over a shared SNP panel of M SNPs. Pointers are device pointers. */
+typedef struct {
+    const int16_t* ranks2;  /* T x K */
+    const int64_t* tiesum;  /* T */
+    int64_t T;
+    int32_t K;
+    const int8_t* geno;     /* M x K, row stride ld_geno */
+    int64_t ld_geno;
+    krux_hit* hits;         /* hit_capacity entries, sorted (trait, snp) */
+    int64_t hit_capacity;
+    int64_t* n_hits;        /* device int64: true hit count */
+    double* min_p;          /* T or NULL */
+} krux_cohort;
+
+/* HITS-mode scan of several cohorts of uneven sample counts against one SNP
+ * panel (cohorts: host array of n_cohorts descriptors). */
+krux_status krux_test_batched(krux_ctx* ctx, const krux_cohort* cohorts,
+                              int32_t n_cohorts, int64_t M, double p_c,
+                              int32_t precision, void* stream);
+
+/* Instrumentation of the fused scan kernel (the rank-sum GEMM with its
+ * epilogue): after krux_timer_start, every launch of that kernel made by the
+ * main pass of krux_test / krux_permute is bracketed by HIP events recorded on
+ * the launch stream.  krux_timer_read synchronises those events, returns the
+ * summed kernel time (host, ms) and the number of launches, and stops the
+ * timer.  Meant for benchmarks; it adds two event records per launch. */
+krux_status krux_timer_start(krux_ctx* ctx);
+krux_status krux_timer_read(krux_ctx* ctx, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KRUX_H */

@@ -5,10 +5,10 @@ The compute lives in the HIP library ``libkrux.so`` (C ABI declared in
 The binding is imported on first use so that the input generators in
 ``paper_1307_3519_amd.datagen`` can be used without a GPU.
 """
+import importlib
 
 
 def __getattr__(name):
-    if name == "krux":
-        from . import krux
-        return krux
+    if name in ("krux", "datagen", "build"):
+        return importlib.import_module("." + name, __name__)
     raise AttributeError(name)

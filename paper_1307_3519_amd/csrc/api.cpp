@@ -1,0 +1,575 @@
+// api.cpp -- the C ABI of include/krux.h: argument checks, context scratch
+// memory, and the launch sequence of each entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/krux.h"
+#include "kx_common.h"
+#include "kx_host.h"
+#include "kx_args.h"
+
+namespace {
+
+enum Slot {
+    S_PACKED, S_INFO, S_FLAGS, S_A, S_THETA, S_ROWV, S_A2, S_THETA2, S_ROWV2,
+    S_LIST_A, S_LIST_B, S_COUNT_A, S_COUNT_B, S_MINP, S_STAGE, S_NHITS, S_KEYS, S_IDX,
+    S_SORT_TMP, S_F64_R, S_F64_I, S_F64_S, S_COUNT_PREV,
+    S_N_SLOTS
+};
+
+struct Buf {
+    void* p = nullptr;
+    size_t n = 0;
+};
+
+}  // namespace
+
+struct krux_ctx {
+    int device = 0;
+    int n_cu = 256;
+    std::string err;
+    Buf bufs[S_N_SLOTS];
+    void* blas = nullptr;   // rocBLAS handle of the fp64 comparator (created on first use)
+    bool timing = false;    // krux_timer_start .. krux_timer_read
+    std::vector<hipEvent_t> ev;   // start/stop pairs of timed launches
+    size_t ev_used = 0;
+};
+
+namespace {
+
+std::string g_err_null = "no error";
+thread_local std::string g_err_noctx;
+
+krux_status fail(krux_ctx* c, krux_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf; else g_err_noctx = buf;
+    return s;
+}
+
+#define HIP_TRY(c, expr)                                                                   \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(c, KRUX_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+// Grow-only scratch buffer of the context.
+void* ws(krux_ctx* c, int slot, size_t bytes, krux_status* st) {
+    Buf& b = c->bufs[slot];
+    if (bytes == 0) bytes = 256;
+    if (b.n >= bytes) return b.p;
+    if (b.p) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.n = 0;
+    }
+    size_t want = bytes + bytes / 8 + 4096;
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+        b.p = nullptr;
+        *st = fail(c, KRUX_ERR_NOMEM, "device allocation of %zu bytes failed", want);
+        return nullptr;
+    }
+    b.n = want;
+    return b.p;
+}
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+double host_pvalue(double H, int df) {
+    if (df == 1) return std::erfc(std::sqrt(H / 2.0));
+    if (df == 2) return std::exp(-H / 2.0);
+    return 1.0;
+}
+
+double threshold_of(double p_c, int df) {
+    // largest double h >= 0 with host_pvalue(h, df) >= p_c (bisection on bits)
+    uint64_t lo, hi;
+    double d0 = 0.0, d1 = 4096.0;
+    std::memcpy(&lo, &d0, 8);
+    std::memcpy(&hi, &d1, 8);
+    while (hi - lo > 1) {
+        uint64_t mid = lo + (hi - lo) / 2;
+        double h;
+        std::memcpy(&h, &mid, 8);
+        if (host_pvalue(h, df) >= p_c) lo = mid; else hi = mid;
+    }
+    double r;
+    std::memcpy(&r, &lo, 8);
+    return r;
+}
+
+bool valid_p(double p) { return p > 0.0 && p <= 1.0; }
+
+// Everything one scan needs about the genotype side.
+struct SnpSide {
+    int8_t* G = nullptr;
+    kx::SnpInfo* info = nullptr;
+    int32_t* flags = nullptr;
+    int gstride = 0;
+    int64_t n_snp_tiles = 0;
+};
+
+krux_status pack_snps(krux_ctx* c, const int8_t* geno, int64_t M, int64_t ld, int K, bool diag_ok,
+                      hipStream_t st, SnpSide* out) {
+    krux_status s = KRUX_OK;
+    out->gstride = (int)ceil_div(K, 32) * 32;
+    out->n_snp_tiles = ceil_div(M, kx::kTile);
+    int64_t m_pad = std::max<int64_t>(out->n_snp_tiles, 1) * kx::kTile;
+    out->G = (int8_t*)ws(c, S_PACKED, (size_t)m_pad * out->gstride, &s);
+    out->info = (kx::SnpInfo*)ws(c, S_INFO, (size_t)m_pad * sizeof(kx::SnpInfo), &s);
+    out->flags = (int32_t*)ws(c, S_FLAGS, (size_t)(m_pad / kx::kTile) * 4, &s);
+    if (s != KRUX_OK) return s;
+    int grid = (int)std::min<int64_t>(ceil_div(m_pad, 4), (int64_t)c->n_cu * 8);
+    HIP_TRY(c, kx_launch_pack(geno, M, ld, K, m_pad, out->gstride, diag_ok ? 1 : 0, out->G,
+                              out->info, out->flags, std::max(grid, 1), st));
+    return KRUX_OK;
+}
+
+// Operand of the rank side: fragment-ordered centred ranks.
+struct RankSide {
+    void* A = nullptr;
+    float* theta = nullptr;
+    int32_t* row_v = nullptr;
+};
+
+struct Variant {
+    int elem;   // kx F16 / I8
+    int ks;     // k-steps
+    int form;   // kx DIAG / PLAIN / MISS3
+};
+
+krux_status prep_ranks(krux_ctx* c, const Variant& v, const int16_t* ranks2, const int64_t* tiesum,
+                       int64_t T, int K, const int32_t* perms, const int32_t* rows,
+                       const int32_t* d_nrows, int64_t n_rows, int slotA, int slotTh, int slotRv,
+                       hipStream_t st, RankSide* out) {
+    krux_status s = KRUX_OK;
+    int64_t n_tiles = std::max<int64_t>(ceil_div(n_rows, kx::kTile), 1);
+    out->A = ws(c, slotA, (size_t)n_tiles * v.ks * kx::kWave * 16, &s);
+    out->theta = (float*)ws(c, slotTh, (size_t)n_tiles * kx::kTile * 4, &s);
+    out->row_v = (int32_t*)ws(c, slotRv, (size_t)n_tiles * kx::kTile * 4, &s);
+    if (s != KRUX_OK) return s;
+    kx::PrepArgs a{};
+    a.ranks2 = ranks2; a.tiesum = tiesum; a.perms = perms; a.rows = rows; a.d_nrows = d_nrows;
+    a.n_rows = n_rows; a.T = T; a.K = K; a.ks = v.ks;
+    a.A = out->A; a.A_hi = nullptr; a.theta = out->theta; a.row_v = out->row_v;
+    int64_t total = n_tiles * v.ks * kx::kWave;
+    int grid = (int)std::min<int64_t>(ceil_div(total, 256), (int64_t)c->n_cu * 16);
+    HIP_TRY(c, kx_launch_prep(&a, v.elem == kx::I8 ? 1 : 0, std::max(grid, 1), st));
+    return KRUX_OK;
+}
+
+krux_status choose_variant(krux_ctx* c, int K, int precision, Variant* v) {
+    if (precision == KRUX_PREC_FP16) {
+        if (K > 128)
+            return fail(c, KRUX_ERR_UNSUPPORTED,
+                        "fp16 path: K = %d > 128 is not supported by this build", K);
+        *v = {kx::F16, (int)ceil_div(K, 16), kx::DIAG};
+        return KRUX_OK;
+    }
+    if (precision == KRUX_PREC_INT8) {
+        if (K > 127)
+            return fail(c, KRUX_ERR_UNSUPPORTED,
+                        "int8 path: K = %d > 127 is not supported by this build", K);
+        *v = {kx::I8, (int)ceil_div(K, 32), kx::DIAG};
+        return KRUX_OK;
+    }
+    return fail(c, KRUX_ERR_UNSUPPORTED, "precision %d not handled by the MFMA path", precision);
+}
+
+void set_levels(kx::ScanArgs* a, const double* p_cs, int n) {
+    a->n_lev = n;
+    for (int l = 0; l < kx::kMaxLevels; ++l) {
+        double pc = l < n ? p_cs[l] : 1.0;
+        a->hc[l][0] = threshold_of(pc, 1);
+        a->hc[l][1] = threshold_of(pc, 2);
+    }
+}
+
+void set_screen(kx::ScanArgs* a, double p_screen) {
+    a->inv_hc[0] = 0.0f;
+    for (int df = 1; df <= 2; ++df) {
+        double h = threshold_of(p_screen, df);
+        a->inv_hc[df] = (float)(1.0 / h);
+    }
+}
+
+// Two launches cover every SNP tile: complete tiles on the fast form, tiles
+// with a missing genotype on the MISS3 form (each kernel skips the others).
+krux_status run_screen(krux_ctx* c, kx::ScanArgs a, const Variant& v, hipStream_t st,
+                       int64_t n_rows_max, bool timed = false) {
+    int64_t n_tiles = ceil_div(n_rows_max, kx::kTile);
+    int64_t items = ceil_div(n_tiles, a.tiles_per_range) *
+                    ceil_div(a.n_snp_tiles, kx::kWavesPerBlock);
+    if (items <= 0) return KRUX_OK;
+    int grid = (int)std::min<int64_t>(items, (int64_t)c->n_cu * 2);
+    a.want_flag = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed && c->timing) {
+        while (c->ev.size() < c->ev_used + 2) {
+            hipEvent_t e;
+            HIP_TRY(c, hipEventCreate(&e));
+            c->ev.push_back(e);
+        }
+        e0 = c->ev[c->ev_used];
+        e1 = c->ev[c->ev_used + 1];
+        c->ev_used += 2;
+        HIP_TRY(c, hipEventRecord(e0, st));
+    }
+    HIP_TRY(c, kx_launch_scan(&a, v.elem, v.ks, v.form, 0, grid, st));
+    if (e1) HIP_TRY(c, hipEventRecord(e1, st));
+    a.want_flag = 1;
+    HIP_TRY(c, kx_launch_scan(&a, v.elem, v.ks, 2 /*MISS3*/, 0, grid, st));
+    return KRUX_OK;
+}
+
+// Per-row minimum p: rows still at p = 1 after the main pass are re-run with
+// a looser screen (every pair whose p falls below the level is evaluated
+// exactly), first at p_mid, then at p = 1 (every pair with H > 0).
+krux_status resolve_min_p(krux_ctx* c, kx::ScanArgs base, const Variant& v,
+                          const int16_t* ranks2, const int64_t* tiesum, int64_t T, int K,
+                          const int32_t* perms, int64_t V, double p_main, int64_t M,
+                          hipStream_t st) {
+    std::vector<double> levels;
+    double p_mid = std::min(1.0, std::max(p_main * 10.0, 64.0 / std::max<int64_t>(M, 1)));
+    if (p_mid > p_main && p_mid < 1.0) levels.push_back(p_mid);
+    levels.push_back(1.0);
+    krux_status s = KRUX_OK;
+    int32_t* listA = (int32_t*)ws(c, S_LIST_A, (size_t)V * 4, &s);
+    int32_t* listB = (int32_t*)ws(c, S_LIST_B, (size_t)V * 4, &s);
+    int32_t* cntA = (int32_t*)ws(c, S_COUNT_A, 256, &s);
+    int32_t* cntB = (int32_t*)ws(c, S_COUNT_B, 256, &s);
+    if (s != KRUX_OK) return s;
+    const int32_t* rows_in = nullptr;
+    const int32_t* n_in = nullptr;
+    double p_prev = p_main;   // screen level of the pass that just ran
+    for (size_t li = 0; li < levels.size(); ++li) {
+        int32_t* rows_out = (li % 2 == 0) ? listA : listB;
+        int32_t* n_out = (li % 2 == 0) ? cntA : cntB;
+        double bound = p_prev * (1.0 - 1e-12);
+        unsigned long long limit;
+        std::memcpy(&limit, &bound, 8);
+        HIP_TRY(c, kx_launch_list_unresolved(base.minp_bits, limit, rows_in, n_in, V, rows_out,
+                                             n_out, st));
+        p_prev = levels[li];
+        RankSide r2;
+        s = prep_ranks(c, v, ranks2, tiesum, T, K, perms, rows_out, n_out, V, S_A2, S_THETA2,
+                       S_ROWV2, st, &r2);
+        if (s != KRUX_OK) return s;
+        kx::ScanArgs a = base;
+        a.A = r2.A; a.theta = r2.theta; a.row_v = r2.row_v;
+        a.d_nrows = n_out; a.n_rows = V;
+        a.hits = nullptr; a.counts = nullptr; a.n_lev = 0;
+        set_screen(&a, levels[li]);
+        s = run_screen(c, a, v, st, V);
+        if (s != KRUX_OK) return s;
+        rows_in = rows_out;
+        n_in = n_out;
+    }
+    return KRUX_OK;
+}
+
+krux_status check_ranks(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum, int64_t T,
+                        int32_t K) {
+    if (T < 0) return fail(c, KRUX_ERR_ARG, "T = %lld < 0", (long long)T);
+    if (K < 1) return fail(c, KRUX_ERR_ARG, "K = %d < 1", K);
+    if (K > KRUX_MAX_K_FP16)
+        return fail(c, KRUX_ERR_UNSUPPORTED, "K = %d > %d", K, KRUX_MAX_K_FP16);
+    if (T > 0 && (!ranks2 || !tiesum)) return fail(c, KRUX_ERR_ARG, "ranks2/tiesum is NULL");
+    if (T > INT32_MAX / 2) return fail(c, KRUX_ERR_UNSUPPORTED, "T too large");
+    return KRUX_OK;
+}
+
+krux_status check_geno(krux_ctx* c, const int8_t* geno, int64_t M, int64_t ld, int32_t K) {
+    if (M < 0) return fail(c, KRUX_ERR_ARG, "M = %lld < 0", (long long)M);
+    if (M > INT32_MAX - 4096) return fail(c, KRUX_ERR_UNSUPPORTED, "M too large");
+    if (M > 0 && !geno) return fail(c, KRUX_ERR_ARG, "geno is NULL");
+    if (ld < K) return fail(c, KRUX_ERR_SHAPE, "ld_geno = %lld < K = %d", (long long)ld, K);
+    return KRUX_OK;
+}
+
+krux_status test_impl(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum, int64_t T,
+                      int32_t K, const int8_t* geno, int64_t M, int64_t ld_geno, int64_t snp_base,
+                      double p_c, int32_t mode, int32_t precision, krux_hit* hits,
+                      int64_t hit_capacity, int64_t* n_hits, double* min_p, double* H, double* p,
+                      int32_t* sums, hipStream_t st) {
+    krux_status s = check_ranks(c, ranks2, tiesum, T, K);
+    if (s != KRUX_OK) return s;
+    if ((s = check_geno(c, geno, M, ld_geno, K)) != KRUX_OK) return s;
+    if (mode < KRUX_MODE_HITS || mode > KRUX_MODE_SUMS)
+        return fail(c, KRUX_ERR_ARG, "mode %d", mode);
+    if (precision < KRUX_PREC_FP16 || precision > KRUX_PREC_FP64)
+        return fail(c, KRUX_ERR_ARG, "precision %d", precision);
+    if (mode == KRUX_MODE_HITS) {
+        if (!valid_p(p_c)) return fail(c, KRUX_ERR_ARG, "p_c = %g not in (0, 1]", p_c);
+        if (!n_hits) return fail(c, KRUX_ERR_ARG, "n_hits is NULL");
+        if (hit_capacity < 0) return fail(c, KRUX_ERR_ARG, "hit_capacity < 0");
+        if (hit_capacity > 0 && !hits) return fail(c, KRUX_ERR_ARG, "hits is NULL");
+        if (snp_base < 0 || snp_base + M > INT32_MAX)
+            return fail(c, KRUX_ERR_ARG, "snp_base + M outside int32");
+    } else if (mode == KRUX_MODE_FULL) {
+        if (T * M > 0 && (!H || !p)) return fail(c, KRUX_ERR_ARG, "H/p is NULL");
+    } else {
+        if (T * M > 0 && !sums) return fail(c, KRUX_ERR_ARG, "sums is NULL");
+    }
+    if (precision == KRUX_PREC_FP64)
+        return kx_fp64_test(c, ranks2, tiesum, T, K, geno, M, ld_geno, snp_base, p_c, mode, hits,
+                            hit_capacity, n_hits, min_p, H, p, sums, st);
+    Variant v;
+    if ((s = choose_variant(c, K, precision, &v)) != KRUX_OK) return s;
+    HIP_TRY(c, hipSetDevice(c->device));
+
+    SnpSide sn;
+    if ((s = pack_snps(c, geno, M, ld_geno, K, v.form == kx::DIAG, st, &sn)) != KRUX_OK) return s;
+    RankSide rk;
+    if ((s = prep_ranks(c, v, ranks2, tiesum, T, K, nullptr, nullptr, nullptr, T, S_A, S_THETA,
+                        S_ROWV, st, &rk)) != KRUX_OK)
+        return s;
+
+    kx::ScanArgs a{};
+    a.A = rk.A; a.theta = rk.theta; a.row_v = rk.row_v; a.d_nrows = nullptr; a.n_rows = T;
+    a.T = std::max<int64_t>(T, 1); a.tiesum = tiesum; a.ranks2 = ranks2; a.perms = nullptr;
+    a.G = sn.G; a.gstride = sn.gstride; a.info = sn.info; a.tile_flags = sn.flags;
+    a.M = M; a.n_snp_tiles = sn.n_snp_tiles; a.K = K; a.tiles_per_range = 64;
+    a.snp_base = snp_base;
+
+    if (mode != KRUX_MODE_HITS) {
+        a.H_out = H; a.p_out = p; a.sums_out = sums;
+        set_screen(&a, 1.0);
+        set_levels(&a, nullptr, 0);
+        int64_t items = ceil_div(ceil_div(T, kx::kTile), a.tiles_per_range) *
+                        ceil_div(a.n_snp_tiles, kx::kWavesPerBlock);
+        if (items <= 0) return KRUX_OK;
+        int grid = (int)std::min<int64_t>(items, (int64_t)c->n_cu * 2);
+        a.want_flag = -1;
+        HIP_TRY(c, kx_launch_scan(&a, v.elem, v.ks, 2 /*MISS3*/,
+                                  mode == KRUX_MODE_FULL ? 1 : 2, grid, st));
+        return KRUX_OK;
+    }
+
+    int64_t cap = hit_capacity;
+    kx::HitRec* stage = (kx::HitRec*)ws(c, S_STAGE, (size_t)std::max<int64_t>(cap, 1) * 24, &s);
+    unsigned long long* nh = (unsigned long long*)ws(c, S_NHITS, 256, &s);
+    unsigned long long* minp = (unsigned long long*)ws(c, S_MINP, (size_t)std::max<int64_t>(T, 1) * 8, &s);
+    if (s != KRUX_OK) return s;
+    HIP_TRY(c, kx_launch_fill_u64(nh, 1, 0ull, st));
+    if (min_p) HIP_TRY(c, kx_launch_fill_u64(minp, T, 0x3FF0000000000000ull, st));
+    a.hits = stage; a.hit_cap = cap; a.n_hits = nh;
+    a.minp_bits = min_p ? minp : nullptr;
+    a.counts = nullptr;
+    set_levels(&a, &p_c, 1);
+    set_screen(&a, p_c);
+    if ((s = run_screen(c, a, v, st, T, true)) != KRUX_OK) return s;
+    if (min_p && T > 0) {
+        if ((s = resolve_min_p(c, a, v, ranks2, tiesum, T, K, nullptr, T, p_c, M, st)) != KRUX_OK)
+            return s;
+        HIP_TRY(c, kx_launch_bits_to_double(minp, T, min_p, st));
+    }
+    // deterministic order of the hit list
+    size_t tmp_bytes = kx_sort_tmp_bytes(std::max<int64_t>(cap, 1));
+    unsigned long long* keys = (unsigned long long*)ws(c, S_KEYS, (size_t)std::max<int64_t>(cap, 1) * 16, &s);
+    uint32_t* idx = (uint32_t*)ws(c, S_IDX, (size_t)std::max<int64_t>(cap, 1) * 8, &s);
+    void* tmp = ws(c, S_SORT_TMP, tmp_bytes, &s);
+    if (s != KRUX_OK) return s;
+    int tb = 1;
+    while (tb < 64 && ((int64_t)1 << tb) < std::max<int64_t>(T, 1)) ++tb;
+    HIP_TRY(c, kx_sort_hits(stage, nh, cap, keys, idx, tmp, tmp_bytes, (kx::HitRec*)hits, n_hits,
+                            std::min(64, 32 + tb), st));
+    return KRUX_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// internal hooks used by other translation units
+// ---------------------------------------------------------------------------
+krux_status kx_fail(krux_ctx* c, krux_status s, const char* msg) { return fail(c, s, "%s", msg); }
+void* kx_ws(krux_ctx* c, int slot, size_t bytes, krux_status* st) { return ws(c, slot, bytes, st); }
+void** kx_blas_handle(krux_ctx* c) { return &c->blas; }
+int kx_ctx_device(krux_ctx* c) { return c->device; }
+double kx_threshold_of(double p_c, int df) { return threshold_of(p_c, df); }
+int kx_slot_f64_r() { return S_F64_R; }
+int kx_slot_f64_i() { return S_F64_I; }
+int kx_slot_f64_s() { return S_F64_S; }
+int kx_slot_minp() { return S_MINP; }
+int kx_slot_stage() { return S_STAGE; }
+int kx_slot_nhits() { return S_NHITS; }
+int kx_slot_keys() { return S_KEYS; }
+int kx_slot_idx() { return S_IDX; }
+int kx_slot_sort_tmp() { return S_SORT_TMP; }
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+krux_status krux_create(krux_ctx** out, int device) {
+    if (!out) return fail(nullptr, KRUX_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0)
+        return fail(nullptr, KRUX_ERR_HIP, "no HIP device");
+    if (device < 0 || device >= n) return fail(nullptr, KRUX_ERR_ARG, "device %d of %d", device, n);
+    if (hipSetDevice(device) != hipSuccess) return fail(nullptr, KRUX_ERR_HIP, "hipSetDevice");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess)
+        return fail(nullptr, KRUX_ERR_HIP, "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(nullptr, KRUX_ERR_UNSUPPORTED, "device %d is %s, not gfx950", device,
+                    prop.gcnArchName);
+    krux_ctx* c = new krux_ctx();
+    c->device = device;
+    c->n_cu = prop.multiProcessorCount;
+    *out = c;
+    return KRUX_OK;
+}
+
+krux_status krux_timer_start(krux_ctx* c) {
+    if (!c) return fail(nullptr, KRUX_ERR_ARG, "ctx is NULL");
+    c->timing = true;
+    c->ev_used = 0;
+    return KRUX_OK;
+}
+
+krux_status krux_timer_read(krux_ctx* c, double* total_ms, int64_t* launches) {
+    if (!c) return fail(nullptr, KRUX_ERR_ARG, "ctx is NULL");
+    if (!total_ms || !launches) return fail(c, KRUX_ERR_ARG, "NULL output");
+    double tot = 0.0;
+    for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+        HIP_TRY(c, hipEventSynchronize(c->ev[i + 1]));
+        float ms = 0.0f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
+        tot += ms;
+    }
+    *total_ms = tot;
+    *launches = (int64_t)(c->ev_used / 2);
+    c->timing = false;
+    c->ev_used = 0;
+    return KRUX_OK;
+}
+
+void krux_destroy(krux_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    kx_fp64_release(c);
+    for (auto& b : c->bufs)
+        if (b.p) (void)hipFree(b.p);
+    delete c;
+}
+
+const char* krux_last_error(const krux_ctx* c) {
+    if (c) return c->err.empty() ? g_err_null.c_str() : c->err.c_str();
+    return g_err_noctx.empty() ? g_err_null.c_str() : g_err_noctx.c_str();
+}
+
+krux_status krux_threshold(double p_c, int32_t df, double* H_c) {
+    if (!H_c) return fail(nullptr, KRUX_ERR_ARG, "H_c is NULL");
+    if (!valid_p(p_c)) return fail(nullptr, KRUX_ERR_ARG, "p_c = %g not in (0, 1]", p_c);
+    if (df < 1 || df > 2) return fail(nullptr, KRUX_ERR_UNSUPPORTED, "df = %d", df);
+    *H_c = threshold_of(p_c, df);
+    return KRUX_OK;
+}
+
+krux_status krux_rank(krux_ctx* c, const float* expr, int64_t T, int32_t K, int64_t ld_expr,
+                      int16_t* ranks2, int64_t* tiesum, int32_t* nvalid, void* stream) {
+    if (!c) return fail(nullptr, KRUX_ERR_ARG, "ctx is NULL");
+    if (T < 0) return fail(c, KRUX_ERR_ARG, "T < 0");
+    if (K < 1 || K > KRUX_MAX_K_RANK)
+        return fail(c, KRUX_ERR_UNSUPPORTED, "K = %d outside [1, %d]", K, KRUX_MAX_K_RANK);
+    if (ld_expr < K) return fail(c, KRUX_ERR_SHAPE, "ld_expr < K");
+    if (T > 0 && (!expr || !ranks2 || !tiesum)) return fail(c, KRUX_ERR_ARG, "NULL array");
+    if (T == 0) return KRUX_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, kx_launch_rank(expr, T, K, ld_expr, ranks2, tiesum, nvalid, c->n_cu * 32,
+                              (hipStream_t)stream));
+    return KRUX_OK;
+}
+
+krux_status krux_test(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum, int64_t T,
+                      int32_t K, const int8_t* geno, int64_t M, int64_t ld_geno, int64_t snp_base,
+                      double p_c, int32_t mode, int32_t precision, krux_hit* hits,
+                      int64_t hit_capacity, int64_t* n_hits, double* min_p, double* H, double* p,
+                      int32_t* sums, void* stream) {
+    if (!c) return fail(nullptr, KRUX_ERR_ARG, "ctx is NULL");
+    return test_impl(c, ranks2, tiesum, T, K, geno, M, ld_geno, snp_base, p_c, mode, precision,
+                     hits, hit_capacity, n_hits, min_p, H, p, sums, (hipStream_t)stream);
+}
+
+krux_status krux_permute(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum, int64_t T,
+                         int32_t K, const int8_t* geno, int64_t M, int64_t ld_geno,
+                         const int32_t* perms, int32_t P, const double* p_cs, int32_t n_thr,
+                         int64_t* counts, double* min_p, void* stream) {
+    if (!c) return fail(nullptr, KRUX_ERR_ARG, "ctx is NULL");
+    krux_status s = check_ranks(c, ranks2, tiesum, T, K);
+    if (s != KRUX_OK) return s;
+    if ((s = check_geno(c, geno, M, ld_geno, K)) != KRUX_OK) return s;
+    if (P < 1 || !perms) return fail(c, KRUX_ERR_ARG, "need P >= 1 permutations");
+    if (n_thr < 1 || n_thr > kx::kMaxLevels || !p_cs)
+        return fail(c, KRUX_ERR_ARG, "n_thr must be in [1, %d]", kx::kMaxLevels);
+    for (int i = 0; i < n_thr; ++i)
+        if (!valid_p(p_cs[i])) return fail(c, KRUX_ERR_ARG, "p_cs[%d] = %g", i, p_cs[i]);
+    if (!counts) return fail(c, KRUX_ERR_ARG, "counts is NULL");
+    if ((int64_t)P * T > INT32_MAX / 2) return fail(c, KRUX_ERR_UNSUPPORTED, "P * T too large");
+    Variant v;
+    if ((s = choose_variant(c, K, KRUX_PREC_FP16, &v)) != KRUX_OK) return s;
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t V = (int64_t)P * T;
+    SnpSide sn;
+    if ((s = pack_snps(c, geno, M, ld_geno, K, true, st, &sn)) != KRUX_OK) return s;
+    RankSide rk;
+    if ((s = prep_ranks(c, v, ranks2, tiesum, T, K, perms, nullptr, nullptr, V, S_A, S_THETA,
+                        S_ROWV, st, &rk)) != KRUX_OK)
+        return s;
+    unsigned long long* minp =
+        (unsigned long long*)ws(c, S_MINP, (size_t)std::max<int64_t>(V, 1) * 8, &s);
+    if (s != KRUX_OK) return s;
+    HIP_TRY(c, kx_launch_fill_u64((unsigned long long*)counts, (int64_t)P * n_thr, 0ull, st));
+    if (min_p) HIP_TRY(c, kx_launch_fill_u64(minp, V, 0x3FF0000000000000ull, st));
+    kx::ScanArgs a{};
+    a.A = rk.A; a.theta = rk.theta; a.row_v = rk.row_v; a.d_nrows = nullptr; a.n_rows = V;
+    a.T = std::max<int64_t>(T, 1); a.tiesum = tiesum; a.ranks2 = ranks2; a.perms = perms;
+    a.G = sn.G; a.gstride = sn.gstride; a.info = sn.info; a.tile_flags = sn.flags;
+    a.M = M; a.n_snp_tiles = sn.n_snp_tiles; a.K = K; a.tiles_per_range = 64;
+    a.hits = nullptr; a.counts = (unsigned long long*)counts;
+    a.minp_bits = min_p ? minp : nullptr;
+    set_levels(&a, p_cs, n_thr);
+    double loosest = *std::max_element(p_cs, p_cs + n_thr);
+    set_screen(&a, loosest);
+    if ((s = run_screen(c, a, v, st, V, true)) != KRUX_OK) return s;
+    if (min_p && V > 0) {
+        if ((s = resolve_min_p(c, a, v, ranks2, tiesum, T, K, perms, V, loosest, M, st)) != KRUX_OK)
+            return s;
+        HIP_TRY(c, kx_launch_bits_to_double(minp, V, min_p, st));
+    }
+    return KRUX_OK;
+}
+
+krux_status krux_test_batched(krux_ctx* c, const krux_cohort* co, int32_t n, int64_t M,
+                              double p_c, int32_t precision, void* stream) {
+    if (!c) return fail(nullptr, KRUX_ERR_ARG, "ctx is NULL");
+    if (n < 0 || (n > 0 && !co)) return fail(c, KRUX_ERR_ARG, "cohorts");
+    for (int i = 0; i < n; ++i) {
+        krux_status s = test_impl(c, co[i].ranks2, co[i].tiesum, co[i].T, co[i].K, co[i].geno, M,
+                                  co[i].ld_geno, 0, p_c, KRUX_MODE_HITS, precision, co[i].hits,
+                                  co[i].hit_capacity, co[i].n_hits, co[i].min_p, nullptr, nullptr,
+                                  nullptr, (hipStream_t)stream);
+        if (s != KRUX_OK) return s;
+    }
+    return KRUX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,63 @@
+// kx_args.h -- argument blocks of the operand-preparation and scan kernels,
+// shared by the kernels and by the host code that fills them.
+#pragma once
+#include "kx_common.h"
+
+namespace kx {
+
+struct PrepArgs {
+    const int16_t* ranks2;   // T x K
+    const int64_t* tiesum;   // T
+    const int32_t* perms;    // P x K or null
+    const int32_t* rows;     // list of virtual rows or null (identity)
+    const int32_t* d_nrows;  // device count of rows (with list) or null
+    int64_t n_rows;          // host bound on the number of operand rows
+    int64_t T;
+    int K;
+    int ks;                  // k-steps of the operand
+    void* A;                 // fp16: half8 [tiles][ks][64]; int8: 16 B [tiles][ks][64]
+    void* A_hi;              // int8 byte split: high plane, else null
+    float* theta;            // [tiles * 32]
+    int32_t* row_v;          // [tiles * 32]
+};
+
+enum { DIAG = 0, PLAIN = 1, MISS3 = 2 };
+enum { SCREEN = 0, FULL = 1, SUMS = 2 };
+enum { F16 = 0, I8 = 1 };
+
+constexpr int kQueueCap = 128;     // per-wave queue of pairs needing a re-rank
+
+struct ScanArgs {
+    const void* A;            // operand tiles in fragment order
+    const float* theta;       // [tiles*32] K^3 - K - sumT (float), +inf for padding
+    const int32_t* row_v;     // [tiles*32] virtual row (perm*T + trait), -1 padding
+    const int32_t* d_nrows;   // device row count (fix-up passes) or null
+    int64_t n_rows;           // host bound on operand rows
+    int64_t T;                // traits
+    const int64_t* tiesum;    // [T]
+    const int16_t* ranks2;    // [T][K] doubled midranks (re-rank path)
+    const int32_t* perms;     // [P][K] column permutations or null
+    const int8_t* G;          // packed genotypes [m_pad][gstride]
+    int gstride;
+    const SnpInfo* info;      // [m_pad]
+    const int32_t* tile_flags;// [n_snp_tiles] 1 = has a missing genotype
+    int64_t M;
+    int64_t n_snp_tiles;
+    int K;
+    int tiles_per_range;
+    int want_flag;            // process SNP tiles with this flag; -1 = all
+    float inv_hc[3];          // screen level: 1/H_c(df), [0] = 0
+    double hc[kMaxLevels][2]; // exact thresholds per level, df = 1, 2
+    int n_lev;
+    HitRec* hits;
+    int64_t hit_cap;
+    unsigned long long* n_hits;
+    int64_t snp_base;
+    unsigned long long* minp_bits;  // [virtual rows] bits of the min p
+    unsigned long long* counts;     // [P][n_lev]
+    double* H_out;            // FULL: [T][M]
+    double* p_out;
+    int32_t* sums_out;        // SUMS: [3][T][M]
+};
+
+}  // namespace kx

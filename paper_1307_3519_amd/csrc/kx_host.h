@@ -1,0 +1,62 @@
+// kx_host.h -- host-side declarations shared by the translation units of the
+// library (launchers defined next to their kernels, context hooks in api.cpp).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/krux.h"
+#include "kx_common.h"
+
+namespace kx {
+struct PrepArgs;
+struct ScanArgs;
+}
+
+extern "C" {
+hipError_t kx_launch_rank(const float* expr, int64_t T, int K, int64_t ld, int16_t* ranks2,
+                          int64_t* tiesum, int32_t* nvalid, int max_blocks, hipStream_t st);
+hipError_t kx_launch_pack(const int8_t* geno, int64_t M, int64_t ld, int K, int64_t m_pad,
+                          int gstride, int diag_ok, int8_t* gp, kx::SnpInfo* info,
+                          int32_t* tile_flags, int grid, hipStream_t st);
+hipError_t kx_launch_prep(const kx::PrepArgs* a, int is_i8, int grid, hipStream_t st);
+hipError_t kx_launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
+hipError_t kx_launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v,
+                              hipStream_t st);
+hipError_t kx_launch_list_unresolved(const unsigned long long* minp_bits,
+                                     unsigned long long limit_bits, const int32_t* rows_in,
+                                     const int32_t* d_n_in, int64_t n_in_max, int32_t* rows_out,
+                                     int32_t* d_n_out, hipStream_t st);
+hipError_t kx_launch_bits_to_double(const unsigned long long* bits, int64_t n, double* out,
+                                    hipStream_t st);
+hipError_t kx_launch_scan(const kx::ScanArgs* a, int elem, int ks, int form, int mode, int grid,
+                          hipStream_t st);
+size_t kx_sort_tmp_bytes(int64_t cap);
+hipError_t kx_sort_hits(const kx::HitRec* stage, const unsigned long long* n_hits, int64_t cap,
+                        unsigned long long* keys, uint32_t* idx, void* tmp, size_t tmp_bytes,
+                        kx::HitRec* out, int64_t* n_out, int key_bits, hipStream_t st);
+}
+
+// context hooks (api.cpp)
+krux_status kx_fail(krux_ctx* c, krux_status s, const char* msg);
+void* kx_ws(krux_ctx* c, int slot, size_t bytes, krux_status* st);
+void** kx_blas_handle(krux_ctx* c);
+int kx_ctx_device(krux_ctx* c);
+double kx_threshold_of(double p_c, int df);
+int kx_slot_f64_r();
+int kx_slot_f64_i();
+int kx_slot_f64_s();
+int kx_slot_minp();
+int kx_slot_stage();
+int kx_slot_nhits();
+int kx_slot_keys();
+int kx_slot_idx();
+int kx_slot_sort_tmp();
+
+// fp64 comparator (fp64.hip)
+krux_status kx_fp64_test(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum, int64_t T,
+                         int32_t K, const int8_t* geno, int64_t M, int64_t ld_geno,
+                         int64_t snp_base, double p_c, int32_t mode, krux_hit* hits,
+                         int64_t hit_capacity, int64_t* n_hits, double* min_p, double* H,
+                         double* p, int32_t* sums, hipStream_t st);
+void kx_fp64_release(krux_ctx* c);

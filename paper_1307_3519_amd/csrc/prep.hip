@@ -1,0 +1,281 @@
+// prep.hip -- operand preparation for the rank-sum GEMM.
+//
+// pack_snps: genotype rows -> (a) a packed copy with a fixed, 32-byte aligned
+//   row stride in which every code outside {0,1,2} (missing) and the padding
+//   become kMissingCode, (b) per-SNP constants (group sizes N_i, df, the
+//   integer coefficients of the MFMA columns and the weights of the
+//   statistic numerator), (c) a per-32-SNP-tile flag "has a missing
+//   genotype".  Counting N_i is the paper's N_i = sum_k I_i(m,k) (eq. (1)).
+//
+// prep_ranks: doubled midranks -> the MFMA A operand in fragment order,
+//   centred c = a - (K+1) (an integer in [-(K-1), K-1], exact in fp16 for
+//   K <= 2049 and in int8 for K <= 128), optionally through a row list
+//   (fix-up passes) and a column permutation (permuted data for the FDR).
+//   Also the per-row screen threshold theta = K^3 - K - sumT (the tie
+//   factor's numerator, eq. (2) with the tied-data correction) and the map
+//   operand row -> virtual row (perm * T + trait), -1 for padding.
+#include "kx_args.h"
+
+namespace kx {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef int int4v __attribute__((ext_vector_type(4)));
+
+// One wave per SNP row (grid-stride).  gstride: packed row bytes (>= K, %32).
+__global__ __launch_bounds__(256) void pack_snps(const int8_t* __restrict__ geno, int64_t M,
+                                                 int64_t ld, int K, int64_t m_pad, int gstride,
+                                                 int diag_ok, int8_t* __restrict__ gp,
+                                                 SnpInfo* __restrict__ info,
+                                                 int32_t* __restrict__ tile_flags) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t m = wave; m < m_pad; m += n_waves) {
+        int c0 = 0, c1 = 0, c2 = 0, cm = 0;
+        const int8_t* row = geno + m * ld;
+        int8_t* out = gp + m * (int64_t)gstride;
+        for (int k0 = 0; k0 < gstride; k0 += 64) {
+            int k = k0 + lane;
+            int8_t code = kMissingCode;
+            if (m < M && k < K) {
+                int8_t g = row[k];
+                code = (g >= 0 && g <= 2) ? g : kMissingCode;
+            }
+            if (k < gstride) out[k] = code;
+            bool valid = (m < M) && (k < K);
+            c0 += __popcll(__ballot(valid && code == 0));
+            c1 += __popcll(__ballot(valid && code == 1));
+            c2 += __popcll(__ballot(valid && code == 2));
+            cm += __popcll(__ballot(valid && code == kMissingCode));
+        }
+        if (lane == 0) {
+            SnpInfo s;
+            s.n0 = (int16_t)c0; s.n1 = (int16_t)c1; s.n2 = (int16_t)c2;
+            s.nmiss = (int16_t)cm;
+            double a0 = c0 ? 1.0 / c0 : 0.0, a1 = c1 ? 1.0 / c1 : 0.0, a2 = c2 ? 1.0 / c2 : 0.0;
+            s.a0 = (float)a0; s.a1 = (float)a1; s.a2 = (float)a2;
+            // f = a0 D0^2 + a1 D1^2 + a2 D2^2 with D0 = -D1 - D2, completed to a
+            // square in D1:  f = wy * Y^2 + wz * D2^2,  Y = cy1 D1 + cy2 D2.
+            double wy = 0.0, wz = a2;
+            int cy1 = 0, cy2 = 0;
+            if (c0 > 0 && c1 > 0) {
+                cy1 = c0 + c1; cy2 = c1;
+                wy = 1.0 / ((double)c0 * c1 * (c0 + c1));
+                wz = 1.0 / (double)(c0 + c1) + a2;
+            } else if (c1 > 0) {        // group 0 empty: f = a1 D1^2 + a2 D2^2
+                cy1 = 1; cy2 = 0; wy = a1;
+            } else if (c0 > 0) {        // group 1 empty: D0 = -D2, f = (a0 + a2) D2^2
+                cy1 = 1; cy2 = 1; wy = a0;
+            }
+            if (!diag_ok) { cy1 = 1; cy2 = 0; }
+            s.cy1 = (int16_t)cy1; s.cy2 = (int16_t)cy2;
+            s.wy = (float)wy; s.wz = (float)wz;
+            info[m] = s;
+            if (cm > 0 && m < M) atomicOr(&tile_flags[m >> 5], 1);
+        }
+    }
+}
+
+// Fill an int32 array (used instead of a memset so captured graphs stay safe).
+__global__ void fill_i32(int32_t* p, int64_t n, int32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void fill_u64(unsigned long long* p, int64_t n, unsigned long long v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+
+__device__ inline int rank_at(const PrepArgs& a, int64_t v, int k) {
+    int64_t trait = v % a.T, perm = v / a.T;
+    int kk = a.perms ? a.perms[perm * a.K + k] : k;
+    return a.ranks2[trait * a.K + kk];
+}
+
+__device__ inline int64_t count_rows(const PrepArgs& a) {
+    if (a.d_nrows) {
+        int64_t n = *a.d_nrows;
+        return n < a.n_rows ? n : a.n_rows;
+    }
+    return a.n_rows;
+}
+
+// fp16 operand: one thread per (tile, k-step, lane) writes 8 halves.
+__global__ __launch_bounds__(256) void prep_ranks_f16(PrepArgs a) {
+    const int64_t n_tiles = (a.n_rows + kTile - 1) / kTile;
+    const int64_t total = n_tiles * a.ks * kWave;
+    const int64_t nr = count_rows(a);
+    half8* A = (half8*)a.A;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int lane = (int)(i % kWave);
+        int64_t ts = i / kWave;
+        int s = (int)(ts % a.ks);
+        int64_t tile = ts / a.ks;
+        int64_t r = tile * kTile + (lane & 31);
+        half8 h;
+        for (int e = 0; e < 8; ++e) h[e] = (_Float16)0.0f;
+        if (r < nr) {
+            int64_t v = a.rows ? a.rows[r] : r;
+            int k0 = s * 16 + 8 * (lane >> 5);
+            for (int e = 0; e < 8; ++e) {
+                int k = k0 + e;
+                if (k < a.K) h[e] = (_Float16)(float)(rank_at(a, v, k) - (a.K + 1));
+            }
+        }
+        A[i] = h;
+        if (s == 0 && lane < 32) {
+            float th = __builtin_inff();
+            int32_t rv = -1;
+            if (r < nr) {
+                int64_t v = a.rows ? a.rows[r] : r;
+                int64_t E = cube_minus(a.K) - a.tiesum[v % a.T];
+                if (E > 0) th = (float)E;
+                rv = (int32_t)v;
+            }
+            a.theta[r] = th;
+            a.row_v[r] = rv;
+        }
+    }
+}
+
+// int8 operand: 16 samples per lane per k-step of 32.  With A_hi set, the
+// centred rank is split c = 128 h + l, l in [0, 127].
+__global__ __launch_bounds__(256) void prep_ranks_i8(PrepArgs a) {
+    const int64_t n_tiles = (a.n_rows + kTile - 1) / kTile;
+    const int64_t total = n_tiles * a.ks * kWave;
+    const int64_t nr = count_rows(a);
+    int4v* A = (int4v*)a.A;
+    int4v* Ah = (int4v*)a.A_hi;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int lane = (int)(i % kWave);
+        int64_t ts = i / kWave;
+        int s = (int)(ts % a.ks);
+        int64_t tile = ts / a.ks;
+        int64_t r = tile * kTile + (lane & 31);
+        int8_t lo[16], hi[16];
+        for (int e = 0; e < 16; ++e) { lo[e] = 0; hi[e] = 0; }
+        if (r < nr) {
+            int64_t v = a.rows ? a.rows[r] : r;
+            int k0 = s * 32 + 16 * (lane >> 5);
+            for (int e = 0; e < 16; ++e) {
+                int k = k0 + e;
+                if (k < a.K) {
+                    int c = rank_at(a, v, k) - (a.K + 1);
+                    if (Ah) {
+                        int h = c >> 7;               // floor(c / 128)
+                        lo[e] = (int8_t)(c - h * 128);
+                        hi[e] = (int8_t)h;
+                    } else {
+                        lo[e] = (int8_t)c;
+                    }
+                }
+            }
+        }
+        int4v wl, wh;
+        for (int w = 0; w < 4; ++w) {
+            uint32_t ul = 0, uh = 0;
+            for (int b = 0; b < 4; ++b) {
+                ul |= (uint32_t)(uint8_t)lo[4 * w + b] << (8 * b);
+                uh |= (uint32_t)(uint8_t)hi[4 * w + b] << (8 * b);
+            }
+            wl[w] = (int)ul; wh[w] = (int)uh;
+        }
+        A[i] = wl;
+        if (Ah) Ah[i] = wh;
+        if (s == 0 && lane < 32) {
+            float th = __builtin_inff();
+            int32_t rv = -1;
+            if (r < nr) {
+                int64_t v = a.rows ? a.rows[r] : r;
+                int64_t E = cube_minus(a.K) - a.tiesum[v % a.T];
+                if (E > 0) th = (float)E;
+                rv = (int32_t)v;
+            }
+            a.theta[r] = th;
+            a.row_v[r] = rv;
+        }
+    }
+}
+
+// A pass whose screen level is p_L evaluates exactly every pair with p < p_L,
+// so a row whose minimum over the evaluated pairs is below p_L (less a margin
+// for host/device rounding of p) is final.  The other rows (limit_bits =
+// bits of that bound) are listed for the next, looser pass.
+__global__ void list_unresolved(const unsigned long long* __restrict__ minp_bits,
+                                unsigned long long limit_bits,
+                                const int32_t* __restrict__ rows_in,
+                                const int32_t* __restrict__ d_n_in, int64_t n_in_max,
+                                int32_t* __restrict__ rows_out, int32_t* __restrict__ d_n_out) {
+    int64_t n_in = d_n_in ? (*d_n_in < n_in_max ? *d_n_in : n_in_max) : n_in_max;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_in;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t v = rows_in ? rows_in[i] : (int32_t)i;
+        if (minp_bits[v] >= limit_bits) {
+            int pos = atomicAdd(d_n_out, 1);
+            rows_out[pos] = v;
+        }
+    }
+}
+
+__global__ void bits_to_double(const unsigned long long* __restrict__ bits, int64_t n,
+                               double* __restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = __longlong_as_double((long long)bits[i]);
+}
+
+}  // namespace kx
+
+extern "C" {
+
+hipError_t kx_launch_pack(const int8_t* geno, int64_t M, int64_t ld, int K, int64_t m_pad,
+                          int gstride, int diag_ok, int8_t* gp, kx::SnpInfo* info,
+                          int32_t* tile_flags, int grid, hipStream_t st) {
+    int64_t n_tiles = m_pad / 32;
+    hipLaunchKernelGGL(kx::fill_i32, dim3(64), dim3(256), 0, st, tile_flags, n_tiles, 0);
+    hipLaunchKernelGGL(kx::pack_snps, dim3(grid), dim3(256), 0, st, geno, M, ld, K, m_pad,
+                       gstride, diag_ok, gp, info, tile_flags);
+    return hipGetLastError();
+}
+
+hipError_t kx_launch_prep(const kx::PrepArgs* a, int is_i8, int grid, hipStream_t st) {
+    if (is_i8)
+        hipLaunchKernelGGL(kx::prep_ranks_i8, dim3(grid), dim3(256), 0, st, *a);
+    else
+        hipLaunchKernelGGL(kx::prep_ranks_f16, dim3(grid), dim3(256), 0, st, *a);
+    return hipGetLastError();
+}
+
+hipError_t kx_launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
+    hipLaunchKernelGGL(kx::fill_i32, dim3(256), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t kx_launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(kx::fill_u64, dim3(512), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t kx_launch_list_unresolved(const unsigned long long* minp_bits,
+                                     unsigned long long limit_bits, const int32_t* rows_in,
+                                     const int32_t* d_n_in, int64_t n_in_max, int32_t* rows_out,
+                                     int32_t* d_n_out, hipStream_t st) {
+    hipLaunchKernelGGL(kx::fill_i32, dim3(1), dim3(64), 0, st, d_n_out, 1, 0);
+    hipLaunchKernelGGL(kx::list_unresolved, dim3(256), dim3(256), 0, st, minp_bits, limit_bits,
+                       rows_in, d_n_in, n_in_max, rows_out, d_n_out);
+    return hipGetLastError();
+}
+
+hipError_t kx_launch_bits_to_double(const unsigned long long* bits, int64_t n, double* out,
+                                    hipStream_t st) {
+    hipLaunchKernelGGL(kx::bits_to_double, dim3(256), dim3(256), 0, st, bits, n, out);
+    return hipGetLastError();
+}
+
+}  // extern "C"

@@ -1,0 +1,63 @@
+"""The C-ABI library loads and exports every entry point include/krux.h
+declares; host-only entry points behave as documented (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "krux.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(krux_[a-z_]+)\s*\(", src)))
+
+
+def _lib():
+    from paper_1307_3519_amd import krux
+    if not os.path.exists(krux.LIB_PATH):
+        pytest.skip("libkrux.so not built")
+    return krux.library()
+
+
+def test_every_declared_symbol_is_exported():
+    from paper_1307_3519_amd import krux
+    lib = _lib()
+    names = _declared()
+    assert set(names) == set(krux.EXPORTS), names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_threshold_matches_oracle_definition():
+    from paper_1307_3519_amd import krux
+    _lib()
+    for df in (1, 2):
+        for pc in (1.0, 0.3, 1e-3, 1e-4, 1e-5, 1e-6, 1e-9, 1e-20):
+            assert krux.threshold(pc, df) == oracle.threshold(pc, df)
+    with pytest.raises(krux.KruxError):
+        krux.threshold(0.0, 2)
+    with pytest.raises(krux.KruxError):
+        krux.threshold(0.01, 3)
+
+
+def test_null_context_is_rejected():
+    lib = _lib()
+    st = lib.krux_rank(None, None, 0, 1, 1, None, None, None, None)
+    assert st == 1  # KRUX_ERR_ARG
+    assert b"ctx" in lib.krux_last_error(None)
+    st = lib.krux_test(None, None, None, 0, 1, None, 0, 1, 0, 0.1, 0, 0,
+                       None, 0, None, None, None, None, None, None)
+    assert st == 1
+    assert lib.krux_create(None, 0) == 1
+
+
+def test_struct_layouts():
+    from paper_1307_3519_amd import krux
+    assert ctypes.sizeof(krux.Hit) == 24
+    assert ctypes.sizeof(krux.Cohort) == 80

@@ -1,0 +1,221 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bars: ranks, tie terms, group counts and rank sums bit-exact; H equal to the
+oracle's correctly rounded value (checked within 1e-12 relative, and exactly
+0 where the oracle has 0); p within 1e-10 relative (absolute floor 1e-300);
+hit lists identical as (trait, snp) sets in (trait, snp) order.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1307_3519_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+H_REL = 1e-12
+P_REL = 1e-10
+P_ABS = 1e-300
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def kx():
+    from paper_1307_3519_amd import krux
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ctx = krux.Context(0)
+    yield ctx
+    ctx.close()
+
+
+def _inputs(seed, T, K, M, tie_frac=0.05, p_missing=0.0, nan_frac=0.0):
+    rs = datagen.streams(seed)
+    x = datagen.inject_ties(rs["ties"], datagen.to_expression(
+        datagen.log_normal_z(rs["expr"], T, K)), tie_frac)
+    g, _ = datagen.genotypes(rs["geno"], M, K)
+    g = datagen.set_missing(rs["missing"], g, p_missing)
+    if nan_frac:
+        mask = rs["missing"].random(x.shape) < nan_frac
+        x[mask] = np.nan
+    return x, g
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def assert_H(Hg, Ho, where=""):
+    Hg = np.asarray(Hg); Ho = np.asarray(Ho)
+    assert np.array_equal(Hg == 0, Ho == 0), where
+    rel = np.abs(Hg - Ho) / np.maximum(np.abs(Ho), 1e-300)
+    assert rel.max(initial=0) <= H_REL, (where, rel.max())
+
+
+def assert_p(pg, po, where=""):
+    pg = np.asarray(pg); po = np.asarray(po)
+    bad = np.abs(pg - po) > np.maximum(P_REL * np.abs(po), P_ABS)
+    assert not bad.any(), (where, pg[bad][:5], po[bad][:5])
+
+
+# ---------------------------------------------------------------- rank
+@pytest.mark.parametrize("K", [1, 2, 7, 48, 102, 128, 129, 500, 1000])
+def test_rank_bit_exact(kx, K):
+    say("rank", K)
+    x, _ = _inputs(100 + K, 67, K, 1, tie_frac=0.2, nan_frac=0.02)
+    x[0, : min(K, 3)] = 0.0
+    if K > 3:
+        x[0, 3] = -0.0
+    x[1, :] = 1.5                      # all tied
+    r, ts, nv = kx.rank(_dev(x))
+    torch.cuda.synchronize()
+    ro, tso, nvo = oracle.rank(x)
+    assert np.array_equal(r.cpu().numpy().astype(np.int32), ro)
+    assert np.array_equal(ts.cpu().numpy(), tso)
+    assert np.array_equal(nv.cpu().numpy(), nvo)
+
+
+def _ranks(kx, x):
+    r, ts, nv = kx.rank(_dev(x))
+    return r, ts
+
+
+# ---------------------------------------------------------------- full / sums
+CASES = [  # (K, T, M, p_missing)
+    (5, 40, 37, 0.0), (33, 70, 100, 0.0), (102, 70, 161, 0.0), (102, 33, 65, 0.05),
+    (128, 65, 64, 0.0), (48, 64, 96, 0.1), (77, 31, 40, 0.03)]
+
+
+@pytest.mark.parametrize("prec", ["fp16", "int8", "fp64"])
+@pytest.mark.parametrize("K,T,M,pm", CASES)
+def test_full_and_sums(kx, prec, K, T, M, pm):
+    if prec == "int8" and K > 127:
+        pytest.skip("int8 path covers K <= 127")
+    say("full/sums", prec, K, T, M, pm)
+    x, g = _inputs(7 * K + T, T, K, M, p_missing=pm)
+    r, ts = _ranks(kx, x)
+    gd = _dev(g)
+    o = oracle.scan(x, g, full=True, sums=True)
+    res = kx.test(r, ts, gd, mode="full", precision=prec)
+    torch.cuda.synchronize()
+    assert_H(res["H"].cpu().numpy(), o["H"], "H")
+    assert_p(res["p"].cpu().numpy(), o["p"], "p")
+    res = kx.test(r, ts, gd, mode="sums", precision=prec)
+    torch.cuda.synchronize()
+    assert np.array_equal(res["sums"].cpu().numpy().astype(np.int64), o["sums"])
+
+
+# ---------------------------------------------------------------- hits
+def _check_hits(kx, x, g, p_c, prec, cap=1 << 15):
+    r, ts = _ranks(kx, x)
+    res = kx.test(r, ts, _dev(g), p_c=p_c, mode="hits", precision=prec, hit_capacity=cap,
+                  min_p=True)
+    torch.cuda.synchronize()
+    from paper_1307_3519_amd.krux import unpack_hits
+    n, h = unpack_hits(res)
+    o = oracle.scan(x, g, p_cs=(p_c,), hits=True, min_p=True)
+    assert n == o["n_hits"]
+    k = min(n, cap)
+    if n <= cap:
+        assert np.array_equal(h["trait"], o["hits"]["trait"])
+        assert np.array_equal(h["snp"], o["hits"]["snp"])
+        assert_H(h["H"], o["hits"]["H"], "hit H")
+        assert_p(h["p"], o["hits"]["p"], "hit p")
+    else:
+        keys = set(zip(o["hits"]["trait"].tolist(), o["hits"]["snp"].tolist()))
+        got = list(zip(h["trait"][:k].tolist(), h["snp"][:k].tolist()))
+        assert got == sorted(got) and set(got) <= keys
+    assert_p(res["min_p"].cpu().numpy(), o["min_p"], "min p")
+    return n
+
+
+@pytest.mark.parametrize("prec", ["fp16", "int8", "fp64"])
+@pytest.mark.parametrize("K,T,M,pm", CASES)
+def test_hits_and_min_p(kx, prec, K, T, M, pm):
+    if prec == "int8" and K > 127:
+        pytest.skip("int8 path covers K <= 127")
+    say("hits", prec, K, T, M, pm)
+    x, g = _inputs(11 * K + M, T, K, M, p_missing=pm)
+    n = _check_hits(kx, x, g, 0.02, prec)
+    # H <= K - 1, so at K = 5 no pair reaches p < 0.02; larger K must produce hits
+    assert n > 0 or K < 10
+
+
+def test_hits_planted_and_capacity(kx):
+    say("hits planted / capacity")
+    w = datagen.make_workload(2, T=200, M=3000, n_plant=40)
+    x, g = w["expr"], w["geno"]
+    n = _check_hits(kx, x, g, 1e-5, "fp16")
+    planted = set(map(tuple, w["planted"][:, :2].tolist()))
+    assert n >= 1
+    # capacity smaller than the count: true count reported, kept subset valid
+    n2 = _check_hits(kx, x, g, 1e-2, "fp16", cap=7)
+    assert n2 > 7
+    del planted
+
+
+def test_degenerate_inputs(kx):
+    say("degenerate")
+    K = 40
+    x, g = _inputs(5, 37, K, 50)
+    x[3, :] = 2.0                      # all-tied trait: H = 0, p = 1
+    g[4, :] = 1                        # monomorphic SNP: df = 0
+    g[5, :20] = 0; g[5, 20:] = 2       # two groups only
+    g[6, :] = -1; g[6, 7] = 1          # everything missing but one sample
+    for prec in ("fp16", "int8", "fp64"):
+        r, ts = _ranks(kx, x)
+        res = kx.test(r, ts, _dev(g), mode="full", precision=prec)
+        torch.cuda.synchronize()
+        o = oracle.scan(x, g, full=True)
+        assert_H(res["H"].cpu().numpy(), o["H"], prec)
+        assert_p(res["p"].cpu().numpy(), o["p"], prec)
+        _check_hits(kx, x, g, 0.05, prec)
+
+
+def test_empty_shapes(kx):
+    say("empty")
+    x, g = _inputs(6, 5, 20, 0)
+    r, ts = _ranks(kx, x)
+    res = kx.test(r, ts, _dev(g).reshape(0, 20), p_c=0.1)
+    torch.cuda.synchronize()
+    assert int(res["n_hits_t"].item()) == 0
+    assert np.all(res["min_p"].cpu().numpy() == 1.0)
+
+
+# ---------------------------------------------------------------- permutations
+@pytest.mark.parametrize("K,T,M", [(102, 70, 130), (30, 40, 64)])
+def test_permute_counts_and_min_p(kx, K, T, M):
+    say("permute", K, T, M)
+    x, g = _inputs(13 + K, T, K, M)
+    rs = datagen.streams(99)
+    perms = datagen.permutations(rs["perms"], 5, K)
+    r, ts = _ranks(kx, x)
+    p_cs = (0.05, 0.01, 0.001)
+    res = kx.permute(r, ts, _dev(g), _dev(perms), p_cs=p_cs)
+    torch.cuda.synchronize()
+    counts = res["counts"].cpu().numpy()
+    mp = res["min_p"].cpu().numpy()
+    for i in range(perms.shape[0]):
+        o = oracle.scan(x, g, p_cs=p_cs, perm=perms[i], min_p=True)
+        assert np.array_equal(counts[i], o["counts"]), i
+        assert_p(mp[i], o["min_p"], "perm min p")
+
+
+# ---------------------------------------------------------------- small workload, full size
+def test_small_workload_full_matrices(kx):
+    say("workload small_full 1000 x 2000 x 102")
+    w = datagen.make_workload(1)
+    x, g = w["expr"], w["geno"]
+    r, ts = _ranks(kx, x)
+    res = kx.test(r, ts, _dev(g), mode="full", precision="fp16")
+    torch.cuda.synchronize()
+    o = oracle.scan(x, g, full=True)
+    assert_H(res["H"].cpu().numpy(), o["H"], "H")
+    assert_p(res["p"].cpu().numpy(), o["p"], "p")
+    assert np.array_equal(res["H"].cpu().numpy(), o["H"])   # correctly rounded on both sides
