@@ -20,7 +20,7 @@ namespace {
 enum Slot {
     S_PACKED, S_INFO, S_FLAGS, S_A, S_THETA, S_ROWV, S_A2, S_THETA2, S_ROWV2,
     S_LIST_A, S_LIST_B, S_COUNT_A, S_COUNT_B, S_MINP, S_STAGE, S_NHITS, S_KEYS, S_IDX,
-    S_SORT_TMP, S_F64_R, S_F64_I, S_F64_S, S_COUNT_PREV,
+    S_SORT_TMP, S_F64_R, S_F64_I, S_F64_S, S_COUNT_PREV, S_CAND, S_NCAND,
     S_N_SLOTS
 };
 
@@ -87,6 +87,10 @@ void* ws(krux_ctx* c, int slot, size_t bytes, krux_status* st) {
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Capacity of the screened-pair buffer (16 B per entry).  When a scan finds
+// more candidates than this, the extra ones are evaluated inside the scan.
+constexpr int64_t kCandCap = (int64_t)1 << 22;
+
 double host_pvalue(double H, int df) {
     if (df == 1) return std::erfc(std::sqrt(H / 2.0));
     if (df == 2) return std::exp(-H / 2.0);
@@ -129,7 +133,7 @@ krux_status pack_snps(krux_ctx* c, const int8_t* geno, int64_t M, int64_t ld, in
     int64_t m_pad = std::max<int64_t>(out->n_snp_tiles, 1) * kx::kTile;
     out->G = (int8_t*)ws(c, S_PACKED, (size_t)m_pad * out->gstride, &s);
     out->info = (kx::SnpInfo*)ws(c, S_INFO, (size_t)m_pad * sizeof(kx::SnpInfo), &s);
-    out->flags = (int32_t*)ws(c, S_FLAGS, (size_t)(m_pad / kx::kTile) * 4, &s);
+    out->flags = (int32_t*)ws(c, S_FLAGS, (size_t)(m_pad / kx::kTile + 1) * 4, &s);
     if (s != KRUX_OK) return s;
     int grid = (int)std::min<int64_t>(ceil_div(m_pad, 4), (int64_t)c->n_cu * 8);
     HIP_TRY(c, kx_launch_pack(geno, M, ld, K, m_pad, out->gstride, diag_ok ? 1 : 0, out->G,
@@ -213,7 +217,14 @@ krux_status run_screen(krux_ctx* c, kx::ScanArgs a, const Variant& v, hipStream_
     int64_t items = ceil_div(n_tiles, a.tiles_per_range) *
                     ceil_div(a.n_snp_tiles, kx::kWavesPerBlock);
     if (items <= 0) return KRUX_OK;
-    int grid = (int)std::min<int64_t>(items, (int64_t)c->n_cu * 2);
+    int grid = (int)std::min<int64_t>(items, (int64_t)INT32_MAX);
+    // screened pairs go to the candidate buffer and are evaluated exactly after the scan
+    krux_status s = KRUX_OK;
+    a.cand_cap = kCandCap;
+    a.cand = (uint4*)ws(c, S_CAND, (size_t)a.cand_cap * sizeof(uint4), &s);
+    a.n_cand = (unsigned long long*)ws(c, S_NCAND, 256, &s);
+    if (s != KRUX_OK) return s;
+    HIP_TRY(c, kx_launch_fill_u64(a.n_cand, 1, 0ull, st));
     a.want_flag = 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed && c->timing) {
@@ -231,7 +242,13 @@ krux_status run_screen(krux_ctx* c, kx::ScanArgs a, const Variant& v, hipStream_
     if (e1) HIP_TRY(c, hipEventRecord(e1, st));
     a.want_flag = 1;
     HIP_TRY(c, kx_launch_scan(&a, v.elem, v.ks, 2 /*MISS3*/, 0, grid, st));
+    HIP_TRY(c, kx_launch_candidates(&a, (int)std::min<int64_t>(ceil_div(a.cand_cap, 256),
+                                                                 (int64_t)c->n_cu * 8), st));
     return KRUX_OK;
+}
+
+double screen_level_for_min_p(double p_c, int64_t M) {
+    return std::max(p_c, std::min(1.0, 64.0 / (double)std::max<int64_t>(M, 1)));
 }
 
 // Per-row minimum p: rows still at p = 1 after the main pass are re-run with
@@ -242,7 +259,7 @@ krux_status resolve_min_p(krux_ctx* c, kx::ScanArgs base, const Variant& v,
                           const int32_t* perms, int64_t V, double p_main, int64_t M,
                           hipStream_t st) {
     std::vector<double> levels;
-    double p_mid = std::min(1.0, std::max(p_main * 10.0, 64.0 / std::max<int64_t>(M, 1)));
+    double p_mid = std::min(1.0, std::max(p_main * 16.0, 1024.0 / std::max<int64_t>(M, 1)));
     if (p_mid > p_main && p_mid < 1.0) levels.push_back(p_mid);
     levels.push_back(1.0);
     krux_status s = KRUX_OK;
@@ -351,7 +368,7 @@ krux_status test_impl(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum,
         int64_t items = ceil_div(ceil_div(T, kx::kTile), a.tiles_per_range) *
                         ceil_div(a.n_snp_tiles, kx::kWavesPerBlock);
         if (items <= 0) return KRUX_OK;
-        int grid = (int)std::min<int64_t>(items, (int64_t)c->n_cu * 2);
+        int grid = (int)std::min<int64_t>(items, (int64_t)INT32_MAX);
         a.want_flag = -1;
         HIP_TRY(c, kx_launch_scan(&a, v.elem, v.ks, 2 /*MISS3*/,
                                   mode == KRUX_MODE_FULL ? 1 : 2, grid, st));
@@ -369,10 +386,15 @@ krux_status test_impl(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum,
     a.minp_bits = min_p ? minp : nullptr;
     a.counts = nullptr;
     set_levels(&a, &p_c, 1);
-    set_screen(&a, p_c);
+    // With min_p requested, the screen admits every pair with p below
+    // p_screen >= p_c (hits are still only the pairs beyond H_c(p_c)); p_screen
+    // is set so that a row of M SNPs almost surely has an exact candidate, and
+    // the few rows without one get the looser passes of resolve_min_p.
+    const double p_screen = min_p ? screen_level_for_min_p(p_c, M) : p_c;
+    set_screen(&a, p_screen);
     if ((s = run_screen(c, a, v, st, T, true)) != KRUX_OK) return s;
     if (min_p && T > 0) {
-        if ((s = resolve_min_p(c, a, v, ranks2, tiesum, T, K, nullptr, T, p_c, M, st)) != KRUX_OK)
+        if ((s = resolve_min_p(c, a, v, ranks2, tiesum, T, K, nullptr, T, p_screen, M, st)) != KRUX_OK)
             return s;
         HIP_TRY(c, kx_launch_bits_to_double(minp, T, min_p, st));
     }
@@ -548,6 +570,7 @@ krux_status krux_permute(krux_ctx* c, const int16_t* ranks2, const int64_t* ties
     a.minp_bits = min_p ? minp : nullptr;
     set_levels(&a, p_cs, n_thr);
     double loosest = *std::max_element(p_cs, p_cs + n_thr);
+    if (min_p) loosest = screen_level_for_min_p(loosest, M);
     set_screen(&a, loosest);
     if ((s = run_screen(c, a, v, st, V, true)) != KRUX_OK) return s;
     if (min_p && V > 0) {

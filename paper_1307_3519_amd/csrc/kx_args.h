@@ -58,6 +58,14 @@ struct ScanArgs {
     double* H_out;            // FULL: [T][M]
     double* p_out;
     int32_t* sums_out;        // SUMS: [3][T][M]
+    // pairs that passed the fp32 screen, evaluated exactly by scan_candidates:
+    // {operand row, SNP | form << 31, column-1 value, column-2 value}
+    uint4* cand;
+    int64_t cand_cap;
+    unsigned long long* n_cand;
 };
+
+// candidate entry form flag: column values are (Y, Z) of DIAG or (D1, D2)
+constexpr uint32_t kCandPlain = 0x80000000u;
 
 }  // namespace kx

@@ -31,6 +31,7 @@ hipError_t kx_launch_bits_to_double(const unsigned long long* bits, int64_t n, d
                                     hipStream_t st);
 hipError_t kx_launch_scan(const kx::ScanArgs* a, int elem, int ks, int form, int mode, int grid,
                           hipStream_t st);
+hipError_t kx_launch_candidates(const kx::ScanArgs* a, int grid, hipStream_t st);
 size_t kx_sort_tmp_bytes(int64_t cap);
 hipError_t kx_sort_hits(const kx::HitRec* stage, const unsigned long long* n_hits, int64_t cap,
                         unsigned long long* keys, uint32_t* idx, void* tmp, size_t tmp_bytes,

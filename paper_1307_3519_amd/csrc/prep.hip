@@ -71,7 +71,10 @@ __global__ __launch_bounds__(256) void pack_snps(const int8_t* __restrict__ geno
             s.cy1 = (int16_t)cy1; s.cy2 = (int16_t)cy2;
             s.wy = (float)wy; s.wz = (float)wz;
             info[m] = s;
-            if (cm > 0 && m < M) atomicOr(&tile_flags[m >> 5], 1);
+            if (cm > 0 && m < M) {
+                atomicOr(&tile_flags[m >> 5], 1);
+                atomicOr(&tile_flags[m_pad >> 5], 1);   // "some SNP has a missing genotype"
+            }
         }
     }
 }
@@ -237,7 +240,7 @@ hipError_t kx_launch_pack(const int8_t* geno, int64_t M, int64_t ld, int K, int6
                           int gstride, int diag_ok, int8_t* gp, kx::SnpInfo* info,
                           int32_t* tile_flags, int grid, hipStream_t st) {
     int64_t n_tiles = m_pad / 32;
-    hipLaunchKernelGGL(kx::fill_i32, dim3(64), dim3(256), 0, st, tile_flags, n_tiles, 0);
+    hipLaunchKernelGGL(kx::fill_i32, dim3(64), dim3(256), 0, st, tile_flags, n_tiles + 1, 0);
     hipLaunchKernelGGL(kx::pack_snps, dim3(grid), dim3(256), 0, st, geno, M, ld, K, m_pad,
                        gstride, diag_ok, gp, info, tile_flags);
     return hipGetLastError();

@@ -1,488 +1,29 @@
-// scan.hip -- rank-sum GEMM on MFMA with the Kruskal-Wallis statistic, tie
-// correction, chi-square p-value and hit compaction fused into its epilogue.
-//
-// What is computed (eq. (1), eq. (2), tied-data and P-value sections): for a
-// trait n with centred doubled ranks c_nk = a_nk - (K+1) and a SNP m with
-// genotype groups g_i, the twice-centred group sums
-//     D_i(n,m) = sum_{k in g_i} c_nk          (a product R * I_i^T, eq. (1))
-// give  f = sum_{N_i>0} D_i^2 / N_i  and  H = 3 (K-1) f / (K^3 - K - sumT_n),
-// which is eq. (2) divided by the tie factor, written without the
-// cancelling "- 3(K+1)" term.  sum_i D_i = 0 when no genotype is missing, so
-// two MFMA columns per SNP suffice (the paper uses l + 1 products).
-//
-// Kernel organisation (SNP-stationary): a block has 4 waves; each wave owns
-// one tile of 32 SNPs whose genotype columns it expands once into MFMA
-// B fragments held in registers, then streams 32-trait A tiles (centred
-// ranks, fragment order, L2 resident) through v_mfma 32x32 instructions.
-// The 32x32 accumulator tile never leaves registers: a 4-operation fp32
-// screen per pair compares f against the per-trait threshold; the rare
-// survivors are re-evaluated exactly (integer D_i -> exact rational H ->
-// fp64 p) and appended to the hit list with one atomic each.
-//
-// Forms of the two/three MFMA columns per SNP:
-//   DIAG   Y = cy1 D1 + cy2 D2 and Z = D2 (integer coefficients chosen so that
-//          f = wy Y^2 + wz Z^2); exact while |Y| stays below 2^24
-//   PLAIN  Y = D1, Z = D2 and f = a0 (D1+D2)^2 + a1 D1^2 + a2 D2^2
-//   MISS3  D0, D1, D2 with indicators that are 0 at missing genotypes; pairs
-//          whose SNP has missing genotypes use a rigorous upper bound of H
-//          and survivors are recomputed by the wave cooperatively with the
-//          ranks re-derived over the remaining samples.
+// scan.hip -- dispatch of the fused scan kernel over (element type, form,
+// mode); the template instances live in scan_{f16,i8}_*.hip so that they
+// compile in parallel.  The kernel itself is in scan_kernel.h.
 #include "kx_args.h"
 
-namespace kx {
+extern "C" {
+hipError_t kx_scan_f16_diag(const kx::ScanArgs*, int, int, hipStream_t);
+hipError_t kx_scan_f16_miss(const kx::ScanArgs*, int, int, hipStream_t);
+hipError_t kx_scan_f16_full(const kx::ScanArgs*, int, int, hipStream_t);
+hipError_t kx_scan_f16_sums(const kx::ScanArgs*, int, int, hipStream_t);
+hipError_t kx_scan_i8_diag(const kx::ScanArgs*, int, int, hipStream_t);
+hipError_t kx_scan_i8_miss(const kx::ScanArgs*, int, int, hipStream_t);
+hipError_t kx_scan_i8_full(const kx::ScanArgs*, int, int, hipStream_t);
+hipError_t kx_scan_i8_sums(const kx::ScanArgs*, int, int, hipStream_t);
 
-typedef _Float16 half8 __attribute__((ext_vector_type(8)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef int i32x16 __attribute__((ext_vector_type(16)));
-typedef int int4v __attribute__((ext_vector_type(4)));
-
-
-template <int E> struct ET;
-template <> struct ET<F16> {
-    using frag = half8;
-    using acc = f32x16;
-    static constexpr int kps = 16;     // samples per k-step
-    static constexpr int per_lane = 8; // samples per lane per k-step
-    __device__ static acc mma(frag a, frag b, acc c) {
-        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
-    }
-    __device__ static float val(const acc& c, int r) { return c[r]; }
-    __device__ static frag make(const int8_t* codes, float v0, float v1, float v2) {
-        frag f;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            int c = codes[e];
-            float v = c == 0 ? v0 : c == 1 ? v1 : c == 2 ? v2 : 0.0f;
-            f[e] = (_Float16)v;
-        }
-        return f;
-    }
-};
-template <> struct ET<I8> {
-    using frag = int4v;
-    using acc = i32x16;
-    static constexpr int kps = 32;
-    static constexpr int per_lane = 16;
-    __device__ static acc mma(frag a, frag b, acc c) {
-        return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
-    }
-    __device__ static float val(const acc& c, int r) { return (float)c[r]; }
-    __device__ static frag make(const int8_t* codes, float v0, float v1, float v2) {
-        frag f;
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            uint32_t u = 0;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                int c = codes[4 * w + b];
-                int v = c == 0 ? (int)v0 : c == 1 ? (int)v1 : c == 2 ? (int)v2 : 0;
-                u |= (uint32_t)(uint8_t)(int8_t)v << (8 * b);
-            }
-            f[w] = (int)u;
-        }
-        return f;
-    }
-};
-
-__device__ inline int wave_sum(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ inline long long wave_sum64(long long v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// Record one exactly evaluated pair (screen mode).
-__device__ inline void record(const ScanArgs& a, int64_t v, int64_t m, double H, int df) {
-    if (df <= 0) return;
-    int64_t trait = v % a.T, perm = v / a.T;
-    if (a.counts) {
-        for (int l = 0; l < a.n_lev; ++l)
-            if (H > a.hc[l][df - 1]) atomicAdd(&a.counts[perm * a.n_lev + l], 1ull);
-    }
-    const bool hit = H > a.hc[0][df - 1];
-    if (!(a.minp_bits || (a.hits && hit))) return;
-    double p = pvalue(H, df);
-    if (a.minp_bits) atomicMin(&a.minp_bits[v], dbl_bits(p));
-    if (a.hits && hit) {
-        unsigned long long idx = atomicAdd(a.n_hits, 1ull);
-        if ((int64_t)idx < a.hit_cap) {
-            HitRec h;
-            h.trait = (int32_t)trait;
-            h.snp = (int32_t)(a.snp_base + m);
-            h.H = H;
-            h.p = p;
-            a.hits[idx] = h;
-        }
-    }
-}
-
-// Write the FULL / SUMS outputs of one pair.
-template <int MODE>
-__device__ inline void emit_full(const ScanArgs& a, int64_t v, int64_t m, double H, int df,
-                                 int64_t s0, int64_t s1, int64_t s2) {
-    if (m >= a.M || v < 0) return;
-    if (MODE == FULL) {
-        a.H_out[v * a.M + m] = H;
-        a.p_out[v * a.M + m] = pvalue(H, df);
-    } else if (MODE == SUMS) {
-        int64_t TM = a.T * a.M;
-        a.sums_out[v * a.M + m] = (int32_t)s0;
-        a.sums_out[TM + v * a.M + m] = (int32_t)s1;
-        a.sums_out[2 * TM + v * a.M + m] = (int32_t)s2;
-    }
-}
-
-// Exact evaluation of pair (v, m) whose SNP has missing genotypes: the
-// missing samples are removed and the ranks re-derived over the rest,
-//   a'_k = a_k - sum_{j missing} (2 [a_j < a_k] + [a_j == a_k]),
-// the tie term loses 3 t (t - 1) for each removal from a tie group of
-// current size t.  All 64 lanes of the wave take part; the result is uniform.
-__device__ inline double coop_exact(const ScanArgs& a, int64_t v, int64_t m, int16_t* qbuf,
-                                    int lane, int* df_out, int64_t* s_out) {
-    const int K = a.K;
-    const int64_t trait = v % a.T, perm = v / a.T;
-    const int16_t* rk = a.ranks2 + trait * K;
-    const int32_t* pm = a.perms ? a.perms + perm * K : nullptr;
-    const int8_t* gr = a.G + m * (int64_t)a.gstride;
-    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int nq = 0;
-    for (int k0 = 0; k0 < K; k0 += kWave) {
-        int k = k0 + lane;
-        bool miss = false;
-        int ak = 0;
-        if (k < K) {
-            miss = gr[k] == kMissingCode;
-            ak = rk[pm ? pm[k] : k];
-        }
-        unsigned long long msk = __ballot(miss);
-        if (miss) qbuf[nq + __popcll(msk & lt)] = (int16_t)ak;
-        nq += __popcll(msk);
-    }
-    __builtin_amdgcn_wave_barrier();
-    long long ts = a.tiesum[trait];
-    for (int qi = 0; qi < nq; ++qi) {
-        int aj = qbuf[qi];
-        int cnt = 0;
-        for (int k0 = 0; k0 < K; k0 += kWave) {
-            int k = k0 + lane;
-            if (k < K) cnt += (rk[pm ? pm[k] : k] == aj);
-        }
-        for (int q0 = 0; q0 < qi; q0 += kWave) {
-            int qq = q0 + lane;
-            if (qq < qi) cnt -= (qbuf[qq] == aj);
-        }
-        int t = wave_sum(cnt);
-        ts -= 3ll * t * (t - 1);
-    }
-    long long s0 = 0, s1 = 0, s2 = 0;
-    for (int k0 = 0; k0 < K; k0 += kWave) {
-        int k = k0 + lane;
-        if (k < K) {
-            int code = gr[k];
-            if (code != kMissingCode) {
-                int ak = rk[pm ? pm[k] : k];
-                int w = 0;
-                for (int qi = 0; qi < nq; ++qi) {
-                    int aj = qbuf[qi];
-                    w += (aj < ak) ? 2 : (aj == ak ? 1 : 0);
-                }
-                int ap = ak - w;
-                if (code == 0) s0 += ap; else if (code == 1) s1 += ap; else s2 += ap;
-            }
-        }
-    }
-    s0 = wave_sum64(s0); s1 = wave_sum64(s1); s2 = wave_sum64(s2);
-    const SnpInfo inf = a.info[m];
-    const int64_t kp = K - nq;
-    const int64_t D0 = s0 - (int64_t)inf.n0 * (kp + 1);
-    const int64_t D1 = s1 - (int64_t)inf.n1 * (kp + 1);
-    const int64_t D2 = s2 - (int64_t)inf.n2 * (kp + 1);
-    *df_out = snp_df(inf);
-    s_out[0] = s0; s_out[1] = s1; s_out[2] = s2;
-    __builtin_amdgcn_wave_barrier();
-    return exact_H(D0, D1, D2, inf.n0, inf.n1, inf.n2, kp, ts, snp_df(inf));
-}
-
-template <int MODE>
-__device__ inline void drain(const ScanArgs& a, int2* queue, int& qn, int16_t* qbuf, int lane) {
-    for (int e = 0; e < qn; ++e) {
-        int2 q = queue[e];
-        int64_t v = a.row_v[q.x];
-        int64_t m = q.y;
-        int df;
-        int64_t s[3];
-        double H = coop_exact(a, v, m, qbuf, lane, &df, s);
-        if (lane == 0) {
-            if (MODE == SCREEN) record(a, v, m, H, df);
-            else emit_full<MODE>(a, v, m, H, df, s[0], s[1], s[2]);
-        }
-    }
-    qn = 0;
-    __builtin_amdgcn_wave_barrier();
-}
-
-template <int E, int KS, int FORM, int MODE>
-__global__ __launch_bounds__(256, 2) void scan_kernel(ScanArgs a) {
-    using T_ = ET<E>;
-    using frag = typename T_::frag;
-    using acc_t = typename T_::acc;
-    constexpr int NC = FORM == MISS3 ? 3 : 2;
-    constexpr bool QUEUE = FORM == MISS3;
-
-    __shared__ int2 s_queue[QUEUE ? kWavesPerBlock : 1][QUEUE ? kQueueCap : 1];
-    extern __shared__ int16_t s_qbuf[];   // MISS3: per wave K entries
-
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    int2* queue = s_queue[QUEUE ? wave : 0];
-    int16_t* qbuf = s_qbuf + (QUEUE ? wave * a.K : 0);
-    int qn = 0;
-
-    int64_t n_rows = a.n_rows;
-    if (a.d_nrows) {
-        int64_t d = *a.d_nrows;
-        n_rows = d < n_rows ? d : n_rows;
-    }
-    const int64_t n_tiles = (n_rows + kTile - 1) / kTile;
-    const int64_t n_ranges = (n_tiles + a.tiles_per_range - 1) / a.tiles_per_range;
-    const int64_t n_blocks = (a.n_snp_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
-    const int64_t items = n_ranges * n_blocks;
-    const frag* A = (const frag*)a.A;
-    const float kslack = 1.0f + kScreenSlack;
-
-    for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
-        const int64_t rg = item / n_blocks;
-        const int64_t st = (item % n_blocks) * kWavesPerBlock + wave;
-        if (st >= a.n_snp_tiles) continue;
-        if (a.want_flag >= 0 && a.tile_flags[st] != a.want_flag) continue;
-        const int64_t m = st * kTile + (lane & 31);
-        const SnpInfo inf = a.info[m];
-
-        // B fragments of this lane's SNP column, built once per item
-        float cv[NC][3];
-        if constexpr (FORM == DIAG) {
-            cv[0][0] = 0.f; cv[0][1] = inf.cy1; cv[0][2] = inf.cy2;
-            cv[1][0] = 0.f; cv[1][1] = 0.f; cv[1][2] = 1.f;
-        } else if (FORM == PLAIN) {
-            cv[0][0] = 0.f; cv[0][1] = 1.f; cv[0][2] = 0.f;
-            cv[1][0] = 0.f; cv[1][1] = 0.f; cv[1][2] = 1.f;
-        } else {
-#pragma unroll
-            for (int c = 0; c < NC; ++c)
-#pragma unroll
-                for (int i = 0; i < 3; ++i) cv[c][i] = (c == i) ? 1.f : 0.f;
-        }
-        frag B[KS][NC];
-        const int8_t* grow = a.G + m * (int64_t)a.gstride + T_::per_lane * (lane >> 5);
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
-            int8_t codes[T_::per_lane];
-            if constexpr (T_::per_lane == 8) {
-                uint2 w = *(const uint2*)(grow + s * T_::kps);
-                __builtin_memcpy(codes, &w, 8);
-            } else {
-                uint4 w = *(const uint4*)(grow + s * T_::kps);
-                __builtin_memcpy(codes, &w, 16);
-            }
-#pragma unroll
-            for (int c = 0; c < NC; ++c) B[s][c] = T_::make(codes, cv[c][0], cv[c][1], cv[c][2]);
-        }
-
-        // per-lane screen constants
-        const int kp = a.K - inf.nmiss;
-        const float fac = 3.0f * (float)(kp - 1) * kslack * a.inv_hc[snp_df(inf)];
-        const float wy = inf.wy * fac, wz = inf.wz * fac;
-        const float w0 = inf.a0 * fac, w1 = inf.a1 * fac, w2 = inf.a2 * fac;
-        const bool lane_miss = inf.nmiss > 0;
-        const float qn0 = (float)inf.nmiss * inf.n0, qn1 = (float)inf.nmiss * inf.n1,
-                    qn2 = (float)inf.nmiss * inf.n2;
-        const float delta = (float)(cube_minus(a.K) - cube_minus(kp));
-
-        const int64_t t0 = rg * a.tiles_per_range;
-        const int64_t t1 = (t0 + a.tiles_per_range < n_tiles) ? t0 + a.tiles_per_range : n_tiles;
-        for (int64_t t = t0; t < t1; ++t) {
-            frag Af[KS];
-#pragma unroll
-            for (int s = 0; s < KS; ++s) Af[s] = A[(t * KS + s) * kWave + lane];
-            acc_t acc[NC];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                acc[c] = acc_t{};
-#pragma unroll
-                for (int s = 0; s < KS; ++s) acc[c] = T_::mma(Af[s], B[s][c], acc[c]);
-            }
-            const int64_t rb = t * kTile + 4 * (lane >> 5);
-            if constexpr (MODE == SCREEN) {
-                float th[16];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    float4 t4 = *(const float4*)(a.theta + rb + 8 * q);
-                    th[4 * q + 0] = t4.x; th[4 * q + 1] = t4.y;
-                    th[4 * q + 2] = t4.z; th[4 * q + 3] = t4.w;
-                }
-                float g[16];
-                float gmax = -__builtin_inff();
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    float x;
-                    if constexpr (FORM == DIAG) {
-                        float y = T_::val(acc[0], r), z = T_::val(acc[1], r);
-                        x = fmaf(wy * y, y, fmaf(wz * z, z, -th[r]));
-                    } else if constexpr (FORM == PLAIN) {
-                        float d1 = T_::val(acc[0], r), d2 = T_::val(acc[1], r);
-                        float d0 = -(d1 + d2);
-                        x = fmaf(w0 * d0, d0, fmaf(w1 * d1, d1, fmaf(w2 * d2, d2, -th[r])));
-                    } else {
-                        float d0 = T_::val(acc[0], r), d1 = T_::val(acc[1], r),
-                              d2 = T_::val(acc[2], r);
-                        if (lane_miss) {
-                            // |D'_i - D_i| <= nmiss * N_i and E' >= K'^3 - K' - sumT
-                            d0 = fabsf(d0) + qn0; d1 = fabsf(d1) + qn1; d2 = fabsf(d2) + qn2;
-                            float tl = delta - th[r] * 0.99999905f;
-                            x = fmaf(w0 * d0, d0, fmaf(w1 * d1, d1, fmaf(w2 * d2, d2, tl)));
-                        } else {
-                            x = fmaf(w0 * d0, d0, fmaf(w1 * d1, d1, fmaf(w2 * d2, d2, -th[r])));
-                        }
-                    }
-                    g[r] = x;
-                    gmax = fmaxf(gmax, x);
-                }
-                if (__any(gmax > 0.0f)) {
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        const int64_t row = rb + 8 * (r >> 2) + (r & 3);
-                        bool cand = g[r] > 0.0f;
-                        if constexpr (QUEUE) {
-                            bool qpush = cand && lane_miss;
-                            unsigned long long msk = __ballot(qpush);
-                            if (msk) {
-                                if (qn + 64 > kQueueCap) drain<MODE>(a, queue, qn, qbuf, lane);
-                                const unsigned long long lt =
-                                    (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-                                if (qpush) queue[qn + __popcll(msk & lt)] = make_int2((int)row, (int)m);
-                                qn += __popcll(msk);
-                            }
-                            cand = cand && !lane_miss;
-                        }
-                        if (cand) {
-                            const int64_t v = a.row_v[row];
-                            int64_t D0, D1, D2;
-                            if constexpr (FORM == DIAG) {
-                                int64_t Y = (int64_t)T_::val(acc[0], r);
-                                D2 = (int64_t)T_::val(acc[1], r);
-                                D1 = inf.cy1 ? (Y - (int64_t)inf.cy2 * D2) / inf.cy1 : 0;
-                                D0 = -D1 - D2;
-                            } else if constexpr (FORM == PLAIN) {
-                                D1 = (int64_t)T_::val(acc[0], r);
-                                D2 = (int64_t)T_::val(acc[1], r);
-                                D0 = -D1 - D2;
-                            } else {
-                                D0 = (int64_t)T_::val(acc[0], r);
-                                D1 = (int64_t)T_::val(acc[1], r);
-                                D2 = (int64_t)T_::val(acc[2], r);
-                            }
-                            const double H = exact_H(D0, D1, D2, inf.n0, inf.n1, inf.n2, a.K,
-                                                     a.tiesum[v % a.T], snp_df(inf));
-                            record(a, v, m, H, snp_df(inf));
-                        }
-                    }
-                    if (QUEUE && qn) drain<MODE>(a, queue, qn, qbuf, lane);
-                }
-            } else if constexpr (FORM == MISS3) {
-                // FULL / SUMS: every pair exactly (MISS3 columns)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int64_t row = rb + 8 * (r >> 2) + (r & 3);
-                    const int64_t v = a.row_v[row];
-                    bool want = v >= 0 && m < a.M;
-                    if constexpr (QUEUE) {
-                        bool qpush = want && lane_miss;
-                        unsigned long long msk = __ballot(qpush);
-                        if (msk) {
-                            if (qn + 64 > kQueueCap) drain<MODE>(a, queue, qn, qbuf, lane);
-                            const unsigned long long lt =
-                                (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-                            if (qpush) queue[qn + __popcll(msk & lt)] = make_int2((int)row, (int)m);
-                            qn += __popcll(msk);
-                        }
-                        want = want && !lane_miss;
-                    }
-                    if (want) {
-                        int64_t D0 = (int64_t)T_::val(acc[0], r);
-                        int64_t D1 = (int64_t)T_::val(acc[1], r);
-                        int64_t D2 = (int64_t)T_::val(acc[2], r);
-                        const double H = exact_H(D0, D1, D2, inf.n0, inf.n1, inf.n2, a.K,
-                                                 a.tiesum[v % a.T], snp_df(inf));
-                        const int64_t k1 = a.K + 1;
-                        emit_full<MODE>(a, v, m, H, snp_df(inf), D0 + inf.n0 * k1, D1 + inf.n1 * k1,
-                                        D2 + inf.n2 * k1);
-                    }
-                }
-                if (QUEUE && qn) drain<MODE>(a, queue, qn, qbuf, lane);
-            }
-        }
-    }
-}
-
-}  // namespace kx
-
-// ---------------------------------------------------------------------------
-// Host-side dispatch over (element type, k-steps, form, mode).
-// ---------------------------------------------------------------------------
-namespace {
-
-template <int E, int KS, int FORM, int MODE>
-hipError_t launch_one(const kx::ScanArgs& a, int grid, hipStream_t st) {
-    size_t lds = FORM == kx::MISS3 ? (size_t)kx::kWavesPerBlock * a.K * sizeof(int16_t) : 0;
-    hipLaunchKernelGGL((kx::scan_kernel<E, KS, FORM, MODE>), dim3(grid), dim3(256), lds, st, a);
-    return hipGetLastError();
-}
-
-template <int E, int FORM, int MODE>
-hipError_t launch_ks(const kx::ScanArgs& a, int ks, int grid, hipStream_t st) {
-    switch (ks) {
-        case 1: return launch_one<E, 1, FORM, MODE>(a, grid, st);
-        case 2: return launch_one<E, 2, FORM, MODE>(a, grid, st);
-        case 3: return launch_one<E, 3, FORM, MODE>(a, grid, st);
-        case 4: return launch_one<E, 4, FORM, MODE>(a, grid, st);
-        case 5: if (E == kx::F16) return launch_one<E, 5, FORM, MODE>(a, grid, st); break;
-        case 6: if (E == kx::F16) return launch_one<E, 6, FORM, MODE>(a, grid, st); break;
-        case 7: if (E == kx::F16) return launch_one<E, 7, FORM, MODE>(a, grid, st); break;
-        case 8: if (E == kx::F16) return launch_one<E, 8, FORM, MODE>(a, grid, st); break;
-        default: break;
-    }
+hipError_t kx_launch_scan(const kx::ScanArgs* a, int elem, int ks, int form, int mode, int grid,
+                          hipStream_t st) {
+    using namespace kx;
+    const bool f16 = elem == F16;
+    if (elem != F16 && elem != I8) return hipErrorInvalidValue;
+    if (mode == SCREEN && form == DIAG)
+        return f16 ? kx_scan_f16_diag(a, ks, grid, st) : kx_scan_i8_diag(a, ks, grid, st);
+    if (form != MISS3) return hipErrorInvalidValue;
+    if (mode == SCREEN) return f16 ? kx_scan_f16_miss(a, ks, grid, st) : kx_scan_i8_miss(a, ks, grid, st);
+    if (mode == FULL) return f16 ? kx_scan_f16_full(a, ks, grid, st) : kx_scan_i8_full(a, ks, grid, st);
+    if (mode == SUMS) return f16 ? kx_scan_f16_sums(a, ks, grid, st) : kx_scan_i8_sums(a, ks, grid, st);
     return hipErrorInvalidValue;
 }
-
-template <int E>
-hipError_t launch_elem(const kx::ScanArgs& a, int ks, int form, int mode, int grid,
-                       hipStream_t st) {
-    if (mode == kx::SCREEN) {
-        if (form == kx::DIAG) return launch_ks<E, kx::DIAG, kx::SCREEN>(a, ks, grid, st);
-        if (form == kx::MISS3) return launch_ks<E, kx::MISS3, kx::SCREEN>(a, ks, grid, st);
-        return hipErrorInvalidValue;
-    }
-    if (form != kx::MISS3) return hipErrorInvalidValue;
-    if (mode == kx::FULL) return launch_ks<E, kx::MISS3, kx::FULL>(a, ks, grid, st);
-    if (mode == kx::SUMS) return launch_ks<E, kx::MISS3, kx::SUMS>(a, ks, grid, st);
-    return hipErrorInvalidValue;
-}
-
-}  // namespace
-
-extern "C" hipError_t kx_launch_scan(const kx::ScanArgs* a, int elem, int ks, int form, int mode,
-                                     int grid, hipStream_t st) {
-    if (elem == kx::F16) return launch_elem<kx::F16>(*a, ks, form, mode, grid, st);
-    if (elem == kx::I8) return launch_elem<kx::I8>(*a, ks, form, mode, grid, st);
-    return hipErrorInvalidValue;
-}
-
-// Occupancy-derived persistent grid size for a (elem, ks, form, mode) variant.
-extern "C" int kx_scan_blocks_per_cu(int elem, int ks, int form, int mode, int K) {
-    (void)elem; (void)ks; (void)form; (void)mode; (void)K;
-    return 2;
 }

@@ -1,0 +1,13 @@
+// scan_i8_sums.hip -- int8 MFMA, group rank sums
+#include "scan_kernel.h"
+
+extern "C" hipError_t kx_scan_i8_sums(const kx::ScanArgs* a, int ks, int grid, hipStream_t st) {
+    using namespace kx;
+    switch (ks) {
+        case 1: return launch_one<I8, 1, MISS3, SUMS>(*a, grid, st);
+        case 2: return launch_one<I8, 2, MISS3, SUMS>(*a, grid, st);
+        case 3: return launch_one<I8, 3, MISS3, SUMS>(*a, grid, st);
+        case 4: return launch_one<I8, 4, MISS3, SUMS>(*a, grid, st);
+        default: return hipErrorInvalidValue;
+    }
+}

@@ -1,0 +1,565 @@
+// scan_kernel.h -- rank-sum GEMM on MFMA with the Kruskal-Wallis statistic, tie
+// correction, chi-square p-value and hit compaction fused into its epilogue.
+//
+// What is computed (eq. (1), eq. (2), tied-data and P-value sections): for a
+// trait n with centred doubled ranks c_nk = a_nk - (K+1) and a SNP m with
+// genotype groups g_i, the twice-centred group sums
+//     D_i(n,m) = sum_{k in g_i} c_nk          (a product R * I_i^T, eq. (1))
+// give  f = sum_{N_i>0} D_i^2 / N_i  and  H = 3 (K-1) f / (K^3 - K - sumT_n),
+// which is eq. (2) divided by the tie factor, written without the
+// cancelling "- 3(K+1)" term.  sum_i D_i = 0 when no genotype is missing, so
+// two MFMA columns per SNP suffice (the paper uses l + 1 products).
+//
+// Kernel organisation (SNP-stationary): a block has 4 waves; each wave owns
+// one tile of 32 SNPs whose genotype columns it expands once into MFMA
+// B fragments held in registers, then streams 32-trait A tiles (centred
+// ranks, fragment order, L2 resident) through v_mfma 32x32 instructions.
+// The 32x32 accumulator tile never leaves registers: a 4-operation fp32
+// screen per pair compares f against the per-trait threshold; the rare
+// survivors are re-evaluated exactly (integer D_i -> exact rational H ->
+// fp64 p) and appended to the hit list with one atomic each.
+//
+// Forms of the two/three MFMA columns per SNP:
+//   DIAG   Y = cy1 D1 + cy2 D2 and Z = D2 (integer coefficients chosen so that
+//          f = wy Y^2 + wz Z^2); exact while |Y| stays below 2^24
+//   PLAIN  Y = D1, Z = D2 and f = a0 (D1+D2)^2 + a1 D1^2 + a2 D2^2
+//   MISS3  D0, D1, D2 with indicators that are 0 at missing genotypes; pairs
+//          whose SNP has missing genotypes use a rigorous upper bound of H
+//          and survivors are recomputed by the wave cooperatively with the
+//          ranks re-derived over the remaining samples.
+#pragma once
+#include "kx_args.h"
+
+namespace kx {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef int i32x16 __attribute__((ext_vector_type(16)));
+typedef int int4v __attribute__((ext_vector_type(4)));
+
+
+template <int E> struct ET;
+template <> struct ET<F16> {
+    using frag = half8;
+    using acc = f32x16;
+    static constexpr int kps = 16;     // samples per k-step
+    static constexpr int per_lane = 8; // samples per lane per k-step
+    __device__ static acc mma(frag a, frag b, acc c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+    }
+    __device__ static float val(const acc& c, int r) { return c[r]; }
+    __device__ static frag make(const int8_t* codes, float v0, float v1, float v2) {
+        frag f;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            int c = codes[e];
+            float v = c == 0 ? v0 : c == 1 ? v1 : c == 2 ? v2 : 0.0f;
+            f[e] = (_Float16)v;
+        }
+        return f;
+    }
+};
+template <> struct ET<I8> {
+    using frag = int4v;
+    using acc = i32x16;
+    static constexpr int kps = 32;
+    static constexpr int per_lane = 16;
+    __device__ static acc mma(frag a, frag b, acc c) {
+        return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
+    }
+    __device__ static float val(const acc& c, int r) { return (float)c[r]; }
+    __device__ static frag make(const int8_t* codes, float v0, float v1, float v2) {
+        frag f;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            uint32_t u = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                int c = codes[4 * w + b];
+                int v = c == 0 ? (int)v0 : c == 1 ? (int)v1 : c == 2 ? (int)v2 : 0;
+                u |= (uint32_t)(uint8_t)(int8_t)v << (8 * b);
+            }
+            f[w] = (int)u;
+        }
+        return f;
+    }
+};
+
+// Load through a global-address-space pointer: keeps the hot loads out of
+// the flat path (flat loads also count against the LDS counter, so a wait for
+// them would also wait for every outstanding prefetch).
+template <class V>
+__device__ inline V gload(const V* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    V v;
+    __builtin_memcpy(&v, (const __attribute__((address_space(1))) V*)p, sizeof(V));
+    return v;
+#else
+    return *p;
+#endif
+}
+
+__device__ inline int wave_sum(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ inline long long wave_sum64(long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Record one exactly evaluated pair (screen mode).
+__device__ inline void record(const ScanArgs& a, int64_t v, int64_t m, double H, int df) {
+    if (df <= 0) return;
+    int64_t trait = v % a.T, perm = v / a.T;
+    if (a.counts) {
+        for (int l = 0; l < a.n_lev; ++l)
+            if (H > a.hc[l][df - 1]) atomicAdd(&a.counts[perm * a.n_lev + l], 1ull);
+    }
+    const bool hit = H > a.hc[0][df - 1];
+    if (!(a.minp_bits || (a.hits && hit))) return;
+    double p = pvalue(H, df);
+    if (a.minp_bits) atomicMin(&a.minp_bits[v], dbl_bits(p));
+    if (a.hits && hit) {
+        unsigned long long idx = atomicAdd(a.n_hits, 1ull);
+        if ((int64_t)idx < a.hit_cap) {
+            HitRec h;
+            h.trait = (int32_t)trait;
+            h.snp = (int32_t)(a.snp_base + m);
+            h.H = H;
+            h.p = p;
+            a.hits[idx] = h;
+        }
+    }
+}
+
+// Write the FULL / SUMS outputs of one pair.
+template <int MODE>
+__device__ inline void emit_full(const ScanArgs& a, int64_t v, int64_t m, double H, int df,
+                                 int64_t s0, int64_t s1, int64_t s2) {
+    if (m >= a.M || v < 0) return;
+    if (MODE == FULL) {
+        a.H_out[v * a.M + m] = H;
+        a.p_out[v * a.M + m] = pvalue(H, df);
+    } else if (MODE == SUMS) {
+        int64_t TM = a.T * a.M;
+        a.sums_out[v * a.M + m] = (int32_t)s0;
+        a.sums_out[TM + v * a.M + m] = (int32_t)s1;
+        a.sums_out[2 * TM + v * a.M + m] = (int32_t)s2;
+    }
+}
+
+// Exact evaluation of one screened pair of a SNP without missing genotypes
+// from its two exact MFMA column values: (Y, Z) of the DIAG form or
+// (D1, D2) of the PLAIN form; D0 = -D1 - D2.
+__device__ inline void eval_candidate(const ScanArgs& a, int64_t row, int64_t m, float y,
+                                      float z, bool plain) {
+    const SnpInfo inf = a.info[m];
+    const int64_t v = a.row_v[row];
+    int64_t D1, D2;
+    if (plain) {
+        D1 = (int64_t)y;
+        D2 = (int64_t)z;
+    } else {
+        const int64_t Y = (int64_t)y;
+        D2 = (int64_t)z;
+        D1 = inf.cy1 ? (Y - (int64_t)inf.cy2 * D2) / inf.cy1 : 0;
+    }
+    const int64_t D0 = -D1 - D2;
+    const int df = snp_df(inf);
+    const double H = exact_H(D0, D1, D2, inf.n0, inf.n1, inf.n2, a.K, a.tiesum[v % a.T], df);
+    record(a, v, m, H, df);
+}
+
+// Used only when the candidate buffer is full: keeps its registers out of
+// the scan loop.
+__device__ __attribute__((noinline)) void eval_candidate_fallback(const ScanArgs& a, int64_t row,
+                                                                   int64_t m, float y, float z,
+                                                                   bool plain) {
+    eval_candidate(a, row, m, y, z, plain);
+}
+
+// Screened pairs are staged per wave in LDS and copied to the global
+// candidate buffer in bursts (one atomic per burst); a pair that does not fit
+// in the global buffer is evaluated on the spot.
+constexpr int kStageCap = 64;
+
+__device__ inline void flush_stage(const ScanArgs& a, uint4* stage, int& sn, int lane) {
+    if (sn == 0) return;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(a.n_cand, (unsigned long long)sn);
+    base = __shfl(base, 0, 64);
+    for (int i = lane; i < sn; i += kWave) {
+        const uint4 e = stage[i];
+        const unsigned long long idx = base + (unsigned long long)i;
+        if ((int64_t)idx < a.cand_cap) {
+            a.cand[idx] = e;
+        } else {
+            eval_candidate_fallback(a, (int64_t)e.x, (int64_t)(e.y & ~kCandPlain),
+                                    __uint_as_float(e.z), __uint_as_float(e.w),
+                                    (e.y & kCandPlain) != 0);
+        }
+    }
+    sn = 0;
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Called by all lanes of a wave (uniform control flow); `cand` per lane.
+__device__ inline void stage_candidates(const ScanArgs& a, uint4* stage, int& sn, int lane,
+                                        bool cand, int64_t row, int64_t m, float y, float z,
+                                        bool plain) {
+    const unsigned long long msk = __ballot(cand);
+    if (!msk) return;
+    const int n = __popcll(msk);
+    if (sn + n > kStageCap) flush_stage(a, stage, sn, lane);
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    if (cand)
+        stage[sn + __popcll(msk & lt)] =
+            make_uint4((uint32_t)row, (uint32_t)m | (plain ? kCandPlain : 0u),
+                       __float_as_uint(y), __float_as_uint(z));
+    sn += n;
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Exact evaluation of pair (v, m) whose SNP has missing genotypes: the
+// missing samples are removed and the ranks re-derived over the rest,
+//   a'_k = a_k - sum_{j missing} (2 [a_j < a_k] + [a_j == a_k]),
+// the tie term loses 3 t (t - 1) for each removal from a tie group of
+// current size t.  All 64 lanes of the wave take part; the result is uniform.
+__device__ inline double coop_exact(const ScanArgs& a, int64_t v, int64_t m, int16_t* qbuf,
+                                    int lane, int* df_out, int64_t* s_out) {
+    const int K = a.K;
+    const int64_t trait = v % a.T, perm = v / a.T;
+    const int16_t* rk = a.ranks2 + trait * K;
+    const int32_t* pm = a.perms ? a.perms + perm * K : nullptr;
+    const int8_t* gr = a.G + m * (int64_t)a.gstride;
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int nq = 0;
+    for (int k0 = 0; k0 < K; k0 += kWave) {
+        int k = k0 + lane;
+        bool miss = false;
+        int ak = 0;
+        if (k < K) {
+            miss = gr[k] == kMissingCode;
+            ak = rk[pm ? pm[k] : k];
+        }
+        unsigned long long msk = __ballot(miss);
+        if (miss) qbuf[nq + __popcll(msk & lt)] = (int16_t)ak;
+        nq += __popcll(msk);
+    }
+    __builtin_amdgcn_wave_barrier();
+    long long ts = a.tiesum[trait];
+    for (int qi = 0; qi < nq; ++qi) {
+        int aj = qbuf[qi];
+        int cnt = 0;
+        for (int k0 = 0; k0 < K; k0 += kWave) {
+            int k = k0 + lane;
+            if (k < K) cnt += (rk[pm ? pm[k] : k] == aj);
+        }
+        for (int q0 = 0; q0 < qi; q0 += kWave) {
+            int qq = q0 + lane;
+            if (qq < qi) cnt -= (qbuf[qq] == aj);
+        }
+        int t = wave_sum(cnt);
+        ts -= 3ll * t * (t - 1);
+    }
+    long long s0 = 0, s1 = 0, s2 = 0;
+    for (int k0 = 0; k0 < K; k0 += kWave) {
+        int k = k0 + lane;
+        if (k < K) {
+            int code = gr[k];
+            if (code != kMissingCode) {
+                int ak = rk[pm ? pm[k] : k];
+                int w = 0;
+                for (int qi = 0; qi < nq; ++qi) {
+                    int aj = qbuf[qi];
+                    w += (aj < ak) ? 2 : (aj == ak ? 1 : 0);
+                }
+                int ap = ak - w;
+                if (code == 0) s0 += ap; else if (code == 1) s1 += ap; else s2 += ap;
+            }
+        }
+    }
+    s0 = wave_sum64(s0); s1 = wave_sum64(s1); s2 = wave_sum64(s2);
+    const SnpInfo inf = a.info[m];
+    const int64_t kp = K - nq;
+    const int64_t D0 = s0 - (int64_t)inf.n0 * (kp + 1);
+    const int64_t D1 = s1 - (int64_t)inf.n1 * (kp + 1);
+    const int64_t D2 = s2 - (int64_t)inf.n2 * (kp + 1);
+    *df_out = snp_df(inf);
+    s_out[0] = s0; s_out[1] = s1; s_out[2] = s2;
+    __builtin_amdgcn_wave_barrier();
+    return exact_H(D0, D1, D2, inf.n0, inf.n1, inf.n2, kp, ts, snp_df(inf));
+}
+
+template <int MODE>
+__device__ inline void drain(const ScanArgs& a, int2* queue, int& qn, int16_t* qbuf, int lane) {
+    for (int e = 0; e < qn; ++e) {
+        int2 q = queue[e];
+        int64_t v = a.row_v[q.x];
+        int64_t m = q.y;
+        int df;
+        int64_t s[3];
+        double H = coop_exact(a, v, m, qbuf, lane, &df, s);
+        if (lane == 0) {
+            if (MODE == SCREEN) record(a, v, m, H, df);
+            else emit_full<MODE>(a, v, m, H, df, s[0], s[1], s[2]);
+        }
+    }
+    qn = 0;
+    __builtin_amdgcn_wave_barrier();
+}
+
+// PF: 1 = the A fragments of the next trait tile are loaded while the current
+// one is processed; WPE: waves per SIMD the register budget is sized for.
+template <int E, int KS, int FORM, int MODE, int PF = 1, int WPE = 2>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+void scan_kernel(ScanArgs a) {
+    using T_ = ET<E>;
+    using frag = typename T_::frag;
+    using acc_t = typename T_::acc;
+    constexpr int NC = FORM == MISS3 ? 3 : 2;
+    constexpr bool QUEUE = FORM == MISS3;
+
+    __shared__ int2 s_queue[QUEUE ? kWavesPerBlock : 1][QUEUE ? kQueueCap : 1];
+    __shared__ uint4 s_stage[MODE == SCREEN ? kWavesPerBlock : 1][kStageCap];
+    extern __shared__ int16_t s_qbuf[];   // MISS3: per wave K entries
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    int2* queue = s_queue[QUEUE ? wave : 0];
+    uint4* stage = s_stage[MODE == SCREEN ? wave : 0];
+    int sn = 0;
+    int16_t* qbuf = s_qbuf + (QUEUE ? wave * a.K : 0);
+    int qn = 0;
+
+    // tile_flags[n_snp_tiles] is set when any SNP has a missing genotype
+    if (a.want_flag == 1 && a.tile_flags[a.n_snp_tiles] == 0) return;
+    int64_t n_rows = a.n_rows;
+    if (a.d_nrows) {
+        int64_t d = *a.d_nrows;
+        n_rows = d < n_rows ? d : n_rows;
+    }
+    const int64_t n_tiles = (n_rows + kTile - 1) / kTile;
+    const int64_t n_ranges = (n_tiles + a.tiles_per_range - 1) / a.tiles_per_range;
+    const int64_t n_blocks = (a.n_snp_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int64_t items = n_ranges * n_blocks;
+    const frag* A = (const frag*)a.A;
+    const float kslack = 1.0f + kScreenSlack;
+
+    for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
+        const int64_t rg = item / n_blocks;
+        const int64_t st = (item % n_blocks) * kWavesPerBlock + wave;
+        if (st >= a.n_snp_tiles) continue;
+        if (a.want_flag >= 0 && a.tile_flags[st] != a.want_flag) continue;
+        const int64_t m = st * kTile + (lane & 31);
+        const SnpInfo inf = gload(a.info + m);
+
+        // B fragments of this lane's SNP column, built once per item
+        float cv[NC][3];
+        if constexpr (FORM == DIAG) {
+            cv[0][0] = 0.f; cv[0][1] = inf.cy1; cv[0][2] = inf.cy2;
+            cv[1][0] = 0.f; cv[1][1] = 0.f; cv[1][2] = 1.f;
+        } else if (FORM == PLAIN) {
+            cv[0][0] = 0.f; cv[0][1] = 1.f; cv[0][2] = 0.f;
+            cv[1][0] = 0.f; cv[1][1] = 0.f; cv[1][2] = 1.f;
+        } else {
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) cv[c][i] = (c == i) ? 1.f : 0.f;
+        }
+        frag B[KS][NC];
+        const int8_t* grow = a.G + m * (int64_t)a.gstride + T_::per_lane * (lane >> 5);
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            int8_t codes[T_::per_lane];
+            if constexpr (T_::per_lane == 8) {
+                uint2 w = gload((const uint2*)(grow + s * T_::kps));
+                __builtin_memcpy(codes, &w, 8);
+            } else {
+                uint4 w = gload((const uint4*)(grow + s * T_::kps));
+                __builtin_memcpy(codes, &w, 16);
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) B[s][c] = T_::make(codes, cv[c][0], cv[c][1], cv[c][2]);
+        }
+
+        // per-lane screen constants
+        const int kp = a.K - inf.nmiss;
+        const float fac = 3.0f * (float)(kp - 1) * kslack * a.inv_hc[snp_df(inf)];
+        const float wy = inf.wy * fac, wz = inf.wz * fac;
+        const float w0 = inf.a0 * fac, w1 = inf.a1 * fac, w2 = inf.a2 * fac;
+        const bool lane_miss = inf.nmiss > 0;
+        const float qn0 = (float)inf.nmiss * inf.n0, qn1 = (float)inf.nmiss * inf.n1,
+                    qn2 = (float)inf.nmiss * inf.n2;
+        const float delta = (float)(cube_minus(a.K) - cube_minus(kp));
+
+        const int64_t t0 = rg * a.tiles_per_range;
+        const int64_t t1 = (t0 + a.tiles_per_range < n_tiles) ? t0 + a.tiles_per_range : n_tiles;
+
+        // one 32-trait tile: MFMA chain into registers, then the epilogue
+        auto tile_body = [&](const int64_t t, const frag (&Af)[KS], const float4 (&th4)[4]) {
+            acc_t acc[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                acc[c] = acc_t{};
+#pragma unroll
+                for (int s = 0; s < KS; ++s) acc[c] = T_::mma(Af[s], B[s][c], acc[c]);
+            }
+            const int64_t rb = t * kTile + 4 * (lane >> 5);
+            if constexpr (MODE == SCREEN) {
+                // g = (screen value of f) - theta, > 0 for every pair beyond the
+                // screen level (the weights carry 3(K-1)(1+slack)/H_c(df))
+                auto screen = [&](int r) -> float {
+                    const float th = (&th4[r >> 2].x)[r & 3];
+                    if constexpr (FORM == DIAG) {
+                        float y = T_::val(acc[0], r), z = T_::val(acc[1], r);
+                        return fmaf(wy * y, y, fmaf(wz * z, z, -th));
+                    } else if constexpr (FORM == PLAIN) {
+                        float d1 = T_::val(acc[0], r), d2 = T_::val(acc[1], r);
+                        float d0 = -(d1 + d2);
+                        return fmaf(w0 * d0, d0, fmaf(w1 * d1, d1, fmaf(w2 * d2, d2, -th)));
+                    } else {
+                        float d0 = T_::val(acc[0], r), d1 = T_::val(acc[1], r),
+                              d2 = T_::val(acc[2], r);
+                        if (lane_miss) {
+                            // |D'_i - D_i| <= nmiss * N_i and E' >= K'^3 - K' - sumT
+                            d0 = fabsf(d0) + qn0; d1 = fabsf(d1) + qn1; d2 = fabsf(d2) + qn2;
+                            float tl = delta - th * 0.99999905f;
+                            return fmaf(w0 * d0, d0, fmaf(w1 * d1, d1, fmaf(w2 * d2, d2, tl)));
+                        }
+                        return fmaf(w0 * d0, d0, fmaf(w1 * d1, d1, fmaf(w2 * d2, d2, -th)));
+                    }
+                };
+                float gmax = -__builtin_inff();
+#pragma unroll
+                for (int r = 0; r < 16; r += 2) gmax = fmaxf(gmax, fmaxf(screen(r), screen(r + 1)));
+                if (__any(gmax > 0.0f)) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int64_t row = rb + 8 * (r >> 2) + (r & 3);
+                        bool cand = screen(r) > 0.0f;
+                        if constexpr (QUEUE) {
+                            bool qpush = cand && lane_miss;
+                            unsigned long long msk = __ballot(qpush);
+                            if (msk) {
+                                if (qn + 64 > kQueueCap) drain<MODE>(a, queue, qn, qbuf, lane);
+                                const unsigned long long lt =
+                                    (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+                                if (qpush) queue[qn + __popcll(msk & lt)] = make_int2((int)row, (int)m);
+                                qn += __popcll(msk);
+                            }
+                            cand = cand && !lane_miss;
+                        }
+                        if constexpr (FORM == DIAG)
+                            stage_candidates(a, stage, sn, lane, cand, row, m, T_::val(acc[0], r),
+                                             T_::val(acc[1], r), false);
+                        else if constexpr (FORM == PLAIN)
+                            stage_candidates(a, stage, sn, lane, cand, row, m, T_::val(acc[0], r),
+                                             T_::val(acc[1], r), true);
+                        else   // complete SNP in a MISS3 tile: D0 = -D1 - D2
+                            stage_candidates(a, stage, sn, lane, cand, row, m, T_::val(acc[1], r),
+                                             T_::val(acc[2], r), true);
+                    }
+                    if (QUEUE && qn) drain<MODE>(a, queue, qn, qbuf, lane);
+                }
+            } else if constexpr (FORM == MISS3) {
+                // FULL / SUMS: every pair exactly (MISS3 columns)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int64_t row = rb + 8 * (r >> 2) + (r & 3);
+                    const int64_t v = a.row_v[row];
+                    bool want = v >= 0 && m < a.M;
+                    if constexpr (QUEUE) {
+                        bool qpush = want && lane_miss;
+                        unsigned long long msk = __ballot(qpush);
+                        if (msk) {
+                            if (qn + 64 > kQueueCap) drain<MODE>(a, queue, qn, qbuf, lane);
+                            const unsigned long long lt =
+                                (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+                            if (qpush) queue[qn + __popcll(msk & lt)] = make_int2((int)row, (int)m);
+                            qn += __popcll(msk);
+                        }
+                        want = want && !lane_miss;
+                    }
+                    if (want) {
+                        int64_t D0 = (int64_t)T_::val(acc[0], r);
+                        int64_t D1 = (int64_t)T_::val(acc[1], r);
+                        int64_t D2 = (int64_t)T_::val(acc[2], r);
+                        const double H = exact_H(D0, D1, D2, inf.n0, inf.n1, inf.n2, a.K,
+                                                 a.tiesum[v % a.T], snp_df(inf));
+                        const int64_t k1 = a.K + 1;
+                        emit_full<MODE>(a, v, m, H, snp_df(inf), D0 + inf.n0 * k1, D1 + inf.n1 * k1,
+                                        D2 + inf.n2 * k1);
+                    }
+                }
+                if (QUEUE && qn) drain<MODE>(a, queue, qn, qbuf, lane);
+            }
+        };
+        // A fragments and thresholds of tile t
+        auto load_tile = [&](const int64_t t, frag (&Af)[KS], float4 (&th4)[4]) {
+#pragma unroll
+            for (int s = 0; s < KS; ++s) Af[s] = gload(A + (t * KS + s) * kWave + lane);
+            const float* tp = a.theta + t * kTile + 4 * (lane >> 5);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) th4[q] = gload((const float4*)(tp + 8 * q));
+        };
+        if constexpr (PF == 0) {
+            for (int64_t t = t0; t < t1; ++t) {
+                frag Ac[KS];
+                float4 hc[4];
+                load_tile(t, Ac, hc);
+                tile_body(t, Ac, hc);
+            }
+        } else {
+            frag Ac[KS];
+            float4 hc[4];
+            if (t0 < t1) load_tile(t0, Ac, hc);
+            for (int64_t t = t0; t < t1; ++t) {
+                frag An[KS];
+                const int64_t tn = (t + 1 < t1) ? t + 1 : t;
+#pragma unroll
+                for (int s = 0; s < KS; ++s) An[s] = gload(A + (tn * KS + s) * kWave + lane);
+                const float* tp = a.theta + tn * kTile + 4 * (lane >> 5);
+                float4 hn[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) hn[q] = gload((const float4*)(tp + 8 * q));
+                tile_body(t, Ac, hc);
+#pragma unroll
+                for (int s = 0; s < KS; ++s) Ac[s] = An[s];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) hc[q] = hn[q];
+            }
+        }
+    }
+    if constexpr (MODE == SCREEN) flush_stage(a, stage, sn, lane);
+}
+
+}  // namespace kx
+
+// ---------------------------------------------------------------------------
+// Launch of one (element type, k-steps, form, mode) instance.
+// ---------------------------------------------------------------------------
+
+// `grid` is the number of work items (an upper bound); the persistent launch
+// uses min(items, resident blocks) = min(grid, n_cu * occupancy).
+namespace kx {
+template <int E, int KS, int FORM, int MODE, int PF = 1, int WPE = 2>
+inline hipError_t launch_one(const kx::ScanArgs& a, int grid, hipStream_t st) {
+    size_t lds = FORM == kx::MISS3 ? (size_t)kx::kWavesPerBlock * a.K * sizeof(int16_t) : 0;
+    auto kern = kx::scan_kernel<E, KS, FORM, MODE, PF, WPE>;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 256, lds) != hipSuccess || occ < 1)
+        occ = 1;
+    int dev = 0, n_cu = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    int64_t resident = (int64_t)n_cu * occ;
+    int g = (int)(grid < resident ? grid : resident);
+    hipLaunchKernelGGL(kern, dim3(g), dim3(256), lds, st, a);
+    return hipGetLastError();
+}
+}  // namespace kx
