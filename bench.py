@@ -40,6 +40,9 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the fp64 / int8 paths")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-minp", action="store_true", help="hit list only (no per-trait min p)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one plain 256 MiB device-to-device copy first (reference for "
+                         "scaling the HBM byte counters of a profiler run)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -65,6 +68,12 @@ def main():
     x = torch.from_numpy(w["expr"]).cuda()
     g = torch.from_numpy(w["geno"]).cuda()
     ctx = krux.Context(0)
+    if args.copy_probe:
+        src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cap = 1 << 20
     bufs = {}
 

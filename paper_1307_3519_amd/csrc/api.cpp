@@ -161,7 +161,7 @@ krux_status prep_ranks(krux_ctx* c, const Variant& v, const int16_t* ranks2, con
     krux_status s = KRUX_OK;
     int64_t n_tiles = std::max<int64_t>(ceil_div(n_rows, kx::kTile), 1);
     out->A = ws(c, slotA, (size_t)n_tiles * v.ks * kx::kWave * 16, &s);
-    out->theta = (float*)ws(c, slotTh, (size_t)n_tiles * kx::kTile * 4, &s);
+    out->theta = (float*)ws(c, slotTh, (size_t)n_tiles * 4, &s);
     out->row_v = (int32_t*)ws(c, slotRv, (size_t)n_tiles * kx::kTile * 4, &s);
     if (s != KRUX_OK) return s;
     kx::PrepArgs a{};
@@ -170,6 +170,7 @@ krux_status prep_ranks(krux_ctx* c, const Variant& v, const int16_t* ranks2, con
     a.A = out->A; a.A_hi = nullptr; a.theta = out->theta; a.row_v = out->row_v;
     int64_t total = n_tiles * v.ks * kx::kWave;
     int grid = (int)std::min<int64_t>(ceil_div(total, 256), (int64_t)c->n_cu * 16);
+    HIP_TRY(c, kx_launch_fill_i32((int32_t*)out->theta, n_tiles, 0x7F800000, st));  // +inf
     HIP_TRY(c, kx_launch_prep(&a, v.elem == kx::I8 ? 1 : 0, std::max(grid, 1), st));
     return KRUX_OK;
 }

@@ -17,7 +17,7 @@ struct PrepArgs {
     int ks;                  // k-steps of the operand
     void* A;                 // fp16: half8 [tiles][ks][64]; int8: 16 B [tiles][ks][64]
     void* A_hi;              // int8 byte split: high plane, else null
-    float* theta;            // [tiles * 32]
+    float* theta;            // [tiles] min over the tile's rows of K^3 - K - sumT
     int32_t* row_v;          // [tiles * 32]
 };
 
@@ -29,7 +29,7 @@ constexpr int kQueueCap = 128;     // per-wave queue of pairs needing a re-rank
 
 struct ScanArgs {
     const void* A;            // operand tiles in fragment order
-    const float* theta;       // [tiles*32] K^3 - K - sumT (float), +inf for padding
+    const float* theta;       // [tiles] min over the tile's rows of K^3 - K - sumT (float)
     const int32_t* row_v;     // [tiles*32] virtual row (perm*T + trait), -1 padding
     const int32_t* d_nrows;   // device row count (fix-up passes) or null
     int64_t n_rows;           // host bound on operand rows

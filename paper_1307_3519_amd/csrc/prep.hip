@@ -11,9 +11,10 @@
 //   centred c = a - (K+1) (an integer in [-(K-1), K-1], exact in fp16 for
 //   K <= 2049 and in int8 for K <= 128), optionally through a row list
 //   (fix-up passes) and a column permutation (permuted data for the FDR).
-//   Also the per-row screen threshold theta = K^3 - K - sumT (the tie
-//   factor's numerator, eq. (2) with the tied-data correction) and the map
-//   operand row -> virtual row (perm * T + trait), -1 for padding.
+//   Also the screen threshold of each 32-row tile, the smallest of
+//   K^3 - K - sumT (the tie factor's numerator, eq. (2) with the tied-data
+//   correction) over its rows (+inf for rows without a finite threshold), and
+//   the map operand row -> virtual row (perm * T + trait), -1 for padding.
 #include "kx_args.h"
 
 namespace kx {
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(256) void prep_ranks_f16(PrepArgs a) {
                 if (E > 0) th = (float)E;
                 rv = (int32_t)v;
             }
-            a.theta[r] = th;
+            atomicMin((unsigned int*)&a.theta[tile], __float_as_uint(th));  // th > 0
             a.row_v[r] = rv;
         }
     }
@@ -199,7 +200,7 @@ __global__ __launch_bounds__(256) void prep_ranks_i8(PrepArgs a) {
                 if (E > 0) th = (float)E;
                 rv = (int32_t)v;
             }
-            a.theta[r] = th;
+            atomicMin((unsigned int*)&a.theta[tile], __float_as_uint(th));  // th > 0
             a.row_v[r] = rv;
         }
     }

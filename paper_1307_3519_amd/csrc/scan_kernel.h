@@ -99,6 +99,15 @@ __device__ inline V gload(const V* p) {
 #endif
 }
 
+// Wave-uniform load through the constant address space (scalar load).
+__device__ inline float cload(const float* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return *(const __attribute__((address_space(4))) float*)p;
+#else
+    return *p;
+#endif
+}
+
 __device__ inline int wave_sum(int v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -186,7 +195,8 @@ __device__ __attribute__((noinline)) void eval_candidate_fallback(const ScanArgs
 // in the global buffer is evaluated on the spot.
 constexpr int kStageCap = 64;
 
-__device__ inline void flush_stage(const ScanArgs& a, uint4* stage, int& sn, int lane) {
+__device__ inline void flush_stage(const ScanArgs& a, const ScanArgs* a_lds, uint4* stage, int& sn,
+                                   int lane) {
     if (sn == 0) return;
     unsigned long long base = 0;
     if (lane == 0) base = atomicAdd(a.n_cand, (unsigned long long)sn);
@@ -197,7 +207,7 @@ __device__ inline void flush_stage(const ScanArgs& a, uint4* stage, int& sn, int
         if ((int64_t)idx < a.cand_cap) {
             a.cand[idx] = e;
         } else {
-            eval_candidate_fallback(a, (int64_t)e.x, (int64_t)(e.y & ~kCandPlain),
+            eval_candidate_fallback(*a_lds, (int64_t)e.x, (int64_t)(e.y & ~kCandPlain),
                                     __uint_as_float(e.z), __uint_as_float(e.w),
                                     (e.y & kCandPlain) != 0);
         }
@@ -207,13 +217,13 @@ __device__ inline void flush_stage(const ScanArgs& a, uint4* stage, int& sn, int
 }
 
 // Called by all lanes of a wave (uniform control flow); `cand` per lane.
-__device__ inline void stage_candidates(const ScanArgs& a, uint4* stage, int& sn, int lane,
-                                        bool cand, int64_t row, int64_t m, float y, float z,
-                                        bool plain) {
+__device__ inline void stage_candidates(const ScanArgs& a, const ScanArgs* a_lds, uint4* stage,
+                                        int& sn, int lane, bool cand, int64_t row, int64_t m,
+                                        float y, float z, bool plain) {
     const unsigned long long msk = __ballot(cand);
     if (!msk) return;
     const int n = __popcll(msk);
-    if (sn + n > kStageCap) flush_stage(a, stage, sn, lane);
+    if (sn + n > kStageCap) flush_stage(a, a_lds, stage, sn, lane);
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     if (cand)
         stage[sn + __popcll(msk & lt)] =
@@ -312,9 +322,12 @@ __device__ inline void drain(const ScanArgs& a, int2* queue, int& qn, int16_t* q
     __builtin_amdgcn_wave_barrier();
 }
 
-// PF: 1 = the A fragments of the next trait tile are loaded while the current
-// one is processed; WPE: waves per SIMD the register budget is sized for.
-template <int E, int KS, int FORM, int MODE, int PF = 1, int WPE = 2>
+// WPE: waves per SIMD the register budget is sized for.
+// PF: 0 = load-then-compute per tile; 1 = next tile prefetched into a second
+// register buffer; 2 = software pipeline (MFMAs of the next tile interleaved
+// with the screen of the current one; screen mode, complete SNPs only).
+template <int E, int KS, int FORM, int MODE,
+          int PF = (MODE == SCREEN && FORM != MISS3) ? 2 : 0, int WPE = 2>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void scan_kernel(ScanArgs a) {
     using T_ = ET<E>;
@@ -322,9 +335,17 @@ void scan_kernel(ScanArgs a) {
     using acc_t = typename T_::acc;
     constexpr int NC = FORM == MISS3 ? 3 : 2;
     constexpr bool QUEUE = FORM == MISS3;
+    constexpr bool RING = PF == 3 && MODE == SCREEN && FORM != MISS3;
 
     __shared__ int2 s_queue[QUEUE ? kWavesPerBlock : 1][QUEUE ? kQueueCap : 1];
     __shared__ uint4 s_stage[MODE == SCREEN ? kWavesPerBlock : 1][kStageCap];
+    // copy of the arguments for the out-of-line fallback (taking the address
+    // of the kernel argument itself would move it to the stack)
+    __shared__ ScanArgs s_args;
+    // LDS ring of A tiles shared by the block's waves (PF == 3): 4 slots
+    __shared__ frag s_ring[RING ? 4 * KS * kWave : 1];
+    if (threadIdx.x == 0) s_args = a;
+    __syncthreads();
     extern __shared__ int16_t s_qbuf[];   // MISS3: per wave K entries
 
     const int lane = threadIdx.x & 63;
@@ -352,10 +373,18 @@ void scan_kernel(ScanArgs a) {
     for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
         const int64_t rg = item / n_blocks;
         const int64_t st = (item % n_blocks) * kWavesPerBlock + wave;
-        if (st >= a.n_snp_tiles) continue;
-        if (a.want_flag >= 0 && a.tile_flags[st] != a.want_flag) continue;
-        const int64_t m = st * kTile + (lane & 31);
-        const SnpInfo inf = gload(a.info + m);
+        const bool active = st < a.n_snp_tiles &&
+                            (a.want_flag < 0 || a.tile_flags[st] == a.want_flag);
+        if constexpr (RING) {
+            // the waves of a block meet at barriers: skip items as a block only;
+            // an inactive wave runs with all-zero columns (never a candidate)
+            if (!__syncthreads_or(active)) continue;
+        } else {
+            if (!active) continue;
+        }
+        const int64_t m = active ? st * kTile + (lane & 31) : 0;
+        SnpInfo inf{};
+        if (active) inf = gload(a.info + m);
 
         // B fragments of this lane's SNP column, built once per item
         float cv[NC][3];
@@ -377,10 +406,11 @@ void scan_kernel(ScanArgs a) {
         for (int s = 0; s < KS; ++s) {
             int8_t codes[T_::per_lane];
             if constexpr (T_::per_lane == 8) {
-                uint2 w = gload((const uint2*)(grow + s * T_::kps));
+                uint2 w = active ? gload((const uint2*)(grow + s * T_::kps)) : make_uint2(~0u, ~0u);
                 __builtin_memcpy(codes, &w, 8);
             } else {
-                uint4 w = gload((const uint4*)(grow + s * T_::kps));
+                uint4 w = active ? gload((const uint4*)(grow + s * T_::kps))
+                                 : make_uint4(~0u, ~0u, ~0u, ~0u);
                 __builtin_memcpy(codes, &w, 16);
             }
 #pragma unroll
@@ -400,72 +430,84 @@ void scan_kernel(ScanArgs a) {
         const int64_t t0 = rg * a.tiles_per_range;
         const int64_t t1 = (t0 + a.tiles_per_range < n_tiles) ? t0 + a.tiles_per_range : n_tiles;
 
-        // one 32-trait tile: MFMA chain into registers, then the epilogue
-        auto tile_body = [&](const int64_t t, const frag (&Af)[KS], const float4 (&th4)[4]) {
-            acc_t acc[NC];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                acc[c] = acc_t{};
-#pragma unroll
-                for (int s = 0; s < KS; ++s) acc[c] = T_::mma(Af[s], B[s][c], acc[c]);
+        // g = (screen value of f) - theta, > 0 for every pair beyond the
+        // screen level (the weights carry 3(K-1)(1+slack)/H_c(df));
+        // theta is the smallest threshold of the tile's 32 traits, which
+        // can only admit more candidates than the per-trait one
+        auto screen = [&](const acc_t (&acc)[NC], const float th, int r) -> float {
+            if constexpr (FORM == DIAG) {
+                float y = T_::val(acc[0], r), z = T_::val(acc[1], r);
+                return fmaf(wy * y, y, fmaf(wz * z, z, -th));
+            } else if constexpr (FORM == PLAIN) {
+                float d1 = T_::val(acc[0], r), d2 = T_::val(acc[1], r);
+                float d0 = -(d1 + d2);
+                return fmaf(w0 * d0, d0, fmaf(w1 * d1, d1, fmaf(w2 * d2, d2, -th)));
+            } else {
+                float d0 = T_::val(acc[0], r), d1 = T_::val(acc[1], r),
+                      d2 = T_::val(acc[2], r);
+                if (lane_miss) {
+                    // |D'_i - D_i| <= nmiss * N_i and E' >= K'^3 - K' - sumT
+                    d0 = fabsf(d0) + qn0; d1 = fabsf(d1) + qn1; d2 = fabsf(d2) + qn2;
+                    float tl = delta - th * 0.99999905f;
+                    return fmaf(w0 * d0, d0, fmaf(w1 * d1, d1, fmaf(w2 * d2, d2, tl)));
+                }
+                return fmaf(w0 * d0, d0, fmaf(w1 * d1, d1, fmaf(w2 * d2, d2, -th)));
             }
+        };
+        // the rare path: stage the pairs that pass the screen
+        auto screen_cands = [&](const int64_t t, const acc_t (&acc)[NC], const float th) {
+            const int64_t rb = t * kTile + 4 * (lane >> 5);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t row = rb + 8 * (r >> 2) + (r & 3);
+                bool cand = screen(acc, th, r) > 0.0f;
+                if constexpr (QUEUE) {
+                    bool qpush = cand && lane_miss;
+                    unsigned long long msk = __ballot(qpush);
+                    if (msk) {
+                        if (qn + 64 > kQueueCap) drain<MODE>(a, queue, qn, qbuf, lane);
+                        const unsigned long long lt =
+                            (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+                        if (qpush) queue[qn + __popcll(msk & lt)] = make_int2((int)row, (int)m);
+                        qn += __popcll(msk);
+                    }
+                    cand = cand && !lane_miss;
+                }
+                if constexpr (FORM == DIAG)
+                    stage_candidates(a, &s_args, stage, sn, lane, cand, row, m, T_::val(acc[0], r),
+                                     T_::val(acc[1], r), false);
+                else if constexpr (FORM == PLAIN)
+                    stage_candidates(a, &s_args, stage, sn, lane, cand, row, m, T_::val(acc[0], r),
+                                     T_::val(acc[1], r), true);
+                else   // complete SNP in a MISS3 tile: D0 = -D1 - D2
+                    stage_candidates(a, &s_args, stage, sn, lane, cand, row, m, T_::val(acc[1], r),
+                                     T_::val(acc[2], r), true);
+            }
+            if (QUEUE && qn) drain<MODE>(a, queue, qn, qbuf, lane);
+        };
+        // largest screen value of a tile (VALU only, no branches)
+        auto screen_max = [&](const acc_t (&acc)[NC], const float th) -> float {
+            float gmax = -__builtin_inff();
+#pragma unroll
+            for (int r = 0; r < 16; r += 2)
+                gmax = fmaxf(gmax, fmaxf(screen(acc, th, r), screen(acc, th, r + 1)));
+            return gmax;
+        };
+        // MFMA chain of one 32-trait tile into registers
+        auto mma_tile = [&](const frag (&Af)[KS], acc_t (&acc)[NC]) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[c] = acc_t{};
+#pragma unroll
+            for (int s = 0; s < KS; ++s)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) acc[c] = T_::mma(Af[s], B[s][c], acc[c]);
+        };
+        // epilogue of one tile (all modes)
+        auto tile_epilogue = [&](const int64_t t, const acc_t (&acc)[NC], const float th) {
             const int64_t rb = t * kTile + 4 * (lane >> 5);
             if constexpr (MODE == SCREEN) {
-                // g = (screen value of f) - theta, > 0 for every pair beyond the
-                // screen level (the weights carry 3(K-1)(1+slack)/H_c(df))
-                auto screen = [&](int r) -> float {
-                    const float th = (&th4[r >> 2].x)[r & 3];
-                    if constexpr (FORM == DIAG) {
-                        float y = T_::val(acc[0], r), z = T_::val(acc[1], r);
-                        return fmaf(wy * y, y, fmaf(wz * z, z, -th));
-                    } else if constexpr (FORM == PLAIN) {
-                        float d1 = T_::val(acc[0], r), d2 = T_::val(acc[1], r);
-                        float d0 = -(d1 + d2);
-                        return fmaf(w0 * d0, d0, fmaf(w1 * d1, d1, fmaf(w2 * d2, d2, -th)));
-                    } else {
-                        float d0 = T_::val(acc[0], r), d1 = T_::val(acc[1], r),
-                              d2 = T_::val(acc[2], r);
-                        if (lane_miss) {
-                            // |D'_i - D_i| <= nmiss * N_i and E' >= K'^3 - K' - sumT
-                            d0 = fabsf(d0) + qn0; d1 = fabsf(d1) + qn1; d2 = fabsf(d2) + qn2;
-                            float tl = delta - th * 0.99999905f;
-                            return fmaf(w0 * d0, d0, fmaf(w1 * d1, d1, fmaf(w2 * d2, d2, tl)));
-                        }
-                        return fmaf(w0 * d0, d0, fmaf(w1 * d1, d1, fmaf(w2 * d2, d2, -th)));
-                    }
-                };
-                float gmax = -__builtin_inff();
-#pragma unroll
-                for (int r = 0; r < 16; r += 2) gmax = fmaxf(gmax, fmaxf(screen(r), screen(r + 1)));
-                if (__any(gmax > 0.0f)) {
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        const int64_t row = rb + 8 * (r >> 2) + (r & 3);
-                        bool cand = screen(r) > 0.0f;
-                        if constexpr (QUEUE) {
-                            bool qpush = cand && lane_miss;
-                            unsigned long long msk = __ballot(qpush);
-                            if (msk) {
-                                if (qn + 64 > kQueueCap) drain<MODE>(a, queue, qn, qbuf, lane);
-                                const unsigned long long lt =
-                                    (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-                                if (qpush) queue[qn + __popcll(msk & lt)] = make_int2((int)row, (int)m);
-                                qn += __popcll(msk);
-                            }
-                            cand = cand && !lane_miss;
-                        }
-                        if constexpr (FORM == DIAG)
-                            stage_candidates(a, stage, sn, lane, cand, row, m, T_::val(acc[0], r),
-                                             T_::val(acc[1], r), false);
-                        else if constexpr (FORM == PLAIN)
-                            stage_candidates(a, stage, sn, lane, cand, row, m, T_::val(acc[0], r),
-                                             T_::val(acc[1], r), true);
-                        else   // complete SNP in a MISS3 tile: D0 = -D1 - D2
-                            stage_candidates(a, stage, sn, lane, cand, row, m, T_::val(acc[1], r),
-                                             T_::val(acc[2], r), true);
-                    }
-                    if (QUEUE && qn) drain<MODE>(a, queue, qn, qbuf, lane);
-                }
+                (void)rb;
+                if (__any(screen_max(acc, th) > 0.0f)) screen_cands(t, acc, th);
             } else if constexpr (FORM == MISS3) {
                 // FULL / SUMS: every pair exactly (MISS3 columns)
 #pragma unroll
@@ -499,43 +541,150 @@ void scan_kernel(ScanArgs a) {
                 if (QUEUE && qn) drain<MODE>(a, queue, qn, qbuf, lane);
             }
         };
-        // A fragments and thresholds of tile t
-        auto load_tile = [&](const int64_t t, frag (&Af)[KS], float4 (&th4)[4]) {
+        auto tile_body = [&](const int64_t t, const frag (&Af)[KS], const float th) {
+            acc_t acc[NC];
+            mma_tile(Af, acc);
+            tile_epilogue(t, acc, th);
+        };
+        // A fragments and the (wave-uniform) threshold of tile t
+        auto load_tile = [&](const int64_t t, frag (&Af)[KS], float& th) {
 #pragma unroll
             for (int s = 0; s < KS; ++s) Af[s] = gload(A + (t * KS + s) * kWave + lane);
-            const float* tp = a.theta + t * kTile + 4 * (lane >> 5);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) th4[q] = gload((const float4*)(tp + 8 * q));
+            th = cload(a.theta + t);
         };
-        if constexpr (PF == 0) {
+        if constexpr (RING) {
+            // As PF == 2, but each A tile is read from global memory once per
+            // block instead of once per wave: wave w loads k-steps w, w + 4 of
+            // tile t + 2 into registers, writes them to a ring of LDS slots one
+            // iteration later, and after one block barrier per tile every wave
+            // reads the whole tile from LDS.  This cuts the vector-L1 traffic
+            // of the A operand by the number of waves per block.
+            constexpr int KW = (KS + kWavesPerBlock - 1) / kWavesPerBlock;  // k-steps per wave
+            frag stg[KW];
+            auto gstage = [&](const int64_t tt) {
+                const int64_t tc = tt < t1 ? tt : t1 - 1;
+#pragma unroll
+                for (int j = 0; j < KW; ++j) {
+                    const int ks = wave + j * kWavesPerBlock;
+                    if (ks < KS) stg[j] = gload(A + (tc * KS + ks) * kWave + lane);
+                }
+            };
+            auto lstore = [&](const int64_t tt) {
+#pragma unroll
+                for (int j = 0; j < KW; ++j) {
+                    const int ks = wave + j * kWavesPerBlock;
+                    if (ks < KS) s_ring[(tt & 3) * KS * kWave + ks * kWave + lane] = stg[j];
+                }
+            };
+            auto lread = [&](const int64_t tt, frag (&Af)[KS]) {
+#pragma unroll
+                for (int s = 0; s < KS; ++s) Af[s] = s_ring[(tt & 3) * KS * kWave + s * kWave + lane];
+            };
+            auto thr = [&](const int64_t tt) { return cload(a.theta + (tt < t1 ? tt : t1 - 1)); };
+            frag Af[KS];
+            acc_t c0[NC], c1[NC];
+            // prologue: tiles t0, t0+1 into slots; tile t0+2 staged in registers
+            __syncthreads();   // the ring of the previous item is no longer read
+            gstage(t0); lstore(t0);
+            gstage(t0 + 1); lstore(t0 + 1);
+            gstage(t0 + 2);
+            __syncthreads();
+            lread(t0, Af);
+            mma_tile(Af, c0);
+            float th0 = thr(t0), th1 = 0.0f;
+            for (int64_t t = t0; t < t1; t += 2) {
+                // half 1: slot t+2 <- staged, stage t+3, barrier; MFMAs of t+1 || screen of t
+                lstore(t + 2);
+                gstage(t + 3);
+                __syncthreads();
+                th1 = thr(t + 1);
+                lread(t + 1, Af);
+                mma_tile(Af, c1);
+                const float g0 = screen_max(c0, th0);
+#pragma unroll
+                for (int i = 0; i < NC * KS; ++i) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);
+                }
+                if (__any(g0 > 0.0f)) screen_cands(t, c0, th0);
+                // half 2: slot t+3 <- staged, stage t+4, barrier; MFMAs of t+2 || screen of t+1
+                lstore(t + 3);
+                gstage(t + 4);
+                __syncthreads();
+                th0 = thr(t + 2);
+                lread(t + 2, Af);
+                mma_tile(Af, c0);
+                const float g1 = screen_max(c1, th1);
+#pragma unroll
+                for (int i = 0; i < NC * KS; ++i) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 1);
+                    __builtin_amdgcn_sched_group_barrier(0x002, 5, 1);
+                }
+                if (t + 1 < t1 && __any(g1 > 0.0f)) screen_cands(t + 1, c1, th1);
+            }
+        } else if constexpr (PF == 2 && MODE == SCREEN && FORM != MISS3) {
+            // Software pipeline over pairs of tiles: the MFMA chain of the next
+            // tile is issued in the same basic block as the fp32 screen of the
+            // current one (two accumulator sets), and the scheduler is asked to
+            // interleave one MFMA with a group of VALU operations, so that the
+            // matrix core and the vector ALU work at the same time within the
+            // wave.  The tile count of a range is even (the operand is padded
+            // with a zero tile whose threshold is +inf); loads of the tile after
+            // next are clamped into the range instead of branching.
+            frag A0[KS], A1[KS];
+            acc_t c0[NC], c1[NC];
+            float h0, h1;
+            const int64_t tl = t1 - 1;
+            load_tile(t0, A0, h0);
+            load_tile(t0 + 1 < t1 ? t0 + 1 : tl, A1, h1);
+            mma_tile(A0, c0);
+            for (int64_t t = t0; t < t1; t += 2) {
+                // half 1: MFMAs of tile t+1 || screen of tile t
+                const float th0 = h0;
+                load_tile(t + 2 < t1 ? t + 2 : tl, A0, h0);
+                mma_tile(A1, c1);
+                const float g0 = screen_max(c0, th0);
+#pragma unroll
+                for (int i = 0; i < NC * KS; ++i) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);
+                }
+                if (__any(g0 > 0.0f)) screen_cands(t, c0, th0);
+                // half 2: MFMAs of tile t+2 || screen of tile t+1
+                const float th1 = h1;
+                load_tile(t + 3 < t1 ? t + 3 : tl, A1, h1);
+                mma_tile(A0, c0);
+                const float g1 = screen_max(c1, th1);
+#pragma unroll
+                for (int i = 0; i < NC * KS; ++i) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 1);
+                    __builtin_amdgcn_sched_group_barrier(0x002, 5, 1);
+                }
+                if (t + 1 < t1 && __any(g1 > 0.0f)) screen_cands(t + 1, c1, th1);
+            }
+        } else if constexpr (PF == 0) {
             for (int64_t t = t0; t < t1; ++t) {
                 frag Ac[KS];
-                float4 hc[4];
+                float hc;
                 load_tile(t, Ac, hc);
                 tile_body(t, Ac, hc);
             }
         } else {
-            frag Ac[KS];
-            float4 hc[4];
-            if (t0 < t1) load_tile(t0, Ac, hc);
-            for (int64_t t = t0; t < t1; ++t) {
-                frag An[KS];
-                const int64_t tn = (t + 1 < t1) ? t + 1 : t;
-#pragma unroll
-                for (int s = 0; s < KS; ++s) An[s] = gload(A + (tn * KS + s) * kWave + lane);
-                const float* tp = a.theta + tn * kTile + 4 * (lane >> 5);
-                float4 hn[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) hn[q] = gload((const float4*)(tp + 8 * q));
-                tile_body(t, Ac, hc);
-#pragma unroll
-                for (int s = 0; s < KS; ++s) Ac[s] = An[s];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) hc[q] = hn[q];
+            // two register buffers, alternating: tile t+1 loads while t computes
+            frag A0[KS], A1[KS];
+            float h0 = 0.f, h1 = 0.f;
+            if (t0 < t1) load_tile(t0, A0, h0);
+            for (int64_t t = t0; t < t1; t += 2) {
+                if (t + 1 < t1) load_tile(t + 1, A1, h1);
+                tile_body(t, A0, h0);
+                if (t + 1 < t1) {
+                    if (t + 2 < t1) load_tile(t + 2, A0, h0);
+                    tile_body(t + 1, A1, h1);
+                }
             }
         }
     }
-    if constexpr (MODE == SCREEN) flush_stage(a, stage, sn, lane);
+    if constexpr (MODE == SCREEN) flush_stage(a, &s_args, stage, sn, lane);
 }
 
 }  // namespace kx
@@ -547,7 +696,8 @@ void scan_kernel(ScanArgs a) {
 // `grid` is the number of work items (an upper bound); the persistent launch
 // uses min(items, resident blocks) = min(grid, n_cu * occupancy).
 namespace kx {
-template <int E, int KS, int FORM, int MODE, int PF = 1, int WPE = 2>
+template <int E, int KS, int FORM, int MODE,
+          int PF = (MODE == kx::SCREEN && FORM != kx::MISS3) ? 2 : 0, int WPE = 2>
 inline hipError_t launch_one(const kx::ScanArgs& a, int grid, hipStream_t st) {
     size_t lds = FORM == kx::MISS3 ? (size_t)kx::kWavesPerBlock * a.K * sizeof(int16_t) : 0;
     auto kern = kx::scan_kernel<E, KS, FORM, MODE, PF, WPE>;

@@ -11,7 +11,8 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libkrux.so")
+# KRUX_LIBRARY may name another build of the same library (e.g. a tuning build)
+LIB_PATH = os.environ.get("KRUX_LIBRARY") or os.path.join(_HERE, "libkrux.so")
 
 KRUX_OK = 0
 MODE_HITS, MODE_FULL, MODE_SUMS = 0, 1, 2
