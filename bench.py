@@ -74,7 +74,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    cap = 1 << 20
+    cap = 1 << 17          # hit-list capacity (about 2.4e4 hits are expected)
     bufs = {}
 
     def step(prec):

@@ -21,6 +21,7 @@ enum Slot {
     S_PACKED, S_INFO, S_FLAGS, S_A, S_THETA, S_ROWV, S_A2, S_THETA2, S_ROWV2,
     S_LIST_A, S_LIST_B, S_COUNT_A, S_COUNT_B, S_MINP, S_STAGE, S_NHITS, S_KEYS, S_IDX,
     S_SORT_TMP, S_F64_R, S_F64_I, S_F64_S, S_COUNT_PREV, S_CAND, S_NCAND,
+    S_AH, S_AH2, S_BF, S_BF3,
     S_N_SLOTS
 };
 
@@ -126,16 +127,20 @@ struct SnpSide {
 };
 
 krux_status pack_snps(krux_ctx* c, const int8_t* geno, int64_t M, int64_t ld, int K, bool diag_ok,
-                      hipStream_t st, SnpSide* out) {
+                      int64_t row_bytes, hipStream_t st, SnpSide* out) {
     krux_status s = KRUX_OK;
-    out->gstride = (int)ceil_div(K, 32) * 32;
+    // packed rows cover every sample the kernels read (k-steps x samples per step)
+    out->gstride = (int)ceil_div(std::max<int64_t>(K, row_bytes), 32) * 32;
     out->n_snp_tiles = ceil_div(M, kx::kTile);
-    int64_t m_pad = std::max<int64_t>(out->n_snp_tiles, 1) * kx::kTile;
+    // rounded to whole blocks of 4 SNP tiles: the tiled kernel reads them
+    int64_t m_pad = std::max<int64_t>(ceil_div(out->n_snp_tiles, 4) * 4, 4) * kx::kTile;
     out->G = (int8_t*)ws(c, S_PACKED, (size_t)m_pad * out->gstride, &s);
     out->info = (kx::SnpInfo*)ws(c, S_INFO, (size_t)m_pad * sizeof(kx::SnpInfo), &s);
     out->flags = (int32_t*)ws(c, S_FLAGS, (size_t)(m_pad / kx::kTile + 1) * 4, &s);
     if (s != KRUX_OK) return s;
-    int grid = (int)std::min<int64_t>(ceil_div(m_pad, 4), (int64_t)c->n_cu * 8);
+    // one wave per SNP row, enough blocks to cover every row at once (the
+    // kernel is latency-bound when waves loop over many rows)
+    int grid = (int)std::min<int64_t>(ceil_div(m_pad, 4), (int64_t)INT32_MAX / 4);
     HIP_TRY(c, kx_launch_pack(geno, M, ld, K, m_pad, out->gstride, diag_ok ? 1 : 0, out->G,
                               out->info, out->flags, std::max(grid, 1), st));
     return KRUX_OK;
@@ -144,30 +149,46 @@ krux_status pack_snps(krux_ctx* c, const int8_t* geno, int64_t M, int64_t ld, in
 // Operand of the rank side: fragment-ordered centred ranks.
 struct RankSide {
     void* A = nullptr;
+    void* A_hi = nullptr;
     float* theta = nullptr;
     int32_t* row_v = nullptr;
 };
 
 struct Variant {
-    int elem;   // kx F16 / I8
-    int ks;     // k-steps
-    int form;   // kx DIAG / PLAIN / MISS3
+    int elem;    // kx F16 / I8
+    int ks;      // k-steps
+    int form;    // kx DIAG / PLAIN / MISS3 of the complete-SNP kernel
+    bool tiled;  // two-operand tiled GEMM (K > 128) instead of the SNP-stationary one
+    bool split;  // int8 with the centred rank split into two bytes
+};
+
+// Samples one operand row spans: k-steps x samples per k-step.
+int64_t row_bytes(const Variant& v) { return (int64_t)v.ks * (v.elem == kx::F16 ? 16 : 32); }
+
+// Genotype columns in MFMA fragment order for the tiled kernel.
+struct Columns {
+    void* Bf = nullptr;     // complete-SNP form
+    void* Bf3 = nullptr;    // three indicator columns (SNPs with missing genotypes)
 };
 
 krux_status prep_ranks(krux_ctx* c, const Variant& v, const int16_t* ranks2, const int64_t* tiesum,
                        int64_t T, int K, const int32_t* perms, const int32_t* rows,
                        const int32_t* d_nrows, int64_t n_rows, int slotA, int slotTh, int slotRv,
-                       hipStream_t st, RankSide* out) {
+                       hipStream_t st, RankSide* out, int slotAh = -1) {
     krux_status s = KRUX_OK;
-    int64_t n_tiles = std::max<int64_t>(ceil_div(n_rows, kx::kTile), 1);
+    // the tiled kernel reads whole blocks of 4 trait tiles
+    const int64_t n_alloc = v.tiled ? ceil_div(std::max<int64_t>(n_rows, 1), 128) * 128
+                                    : std::max<int64_t>(n_rows, 1);
+    int64_t n_tiles = ceil_div(n_alloc, kx::kTile);
     out->A = ws(c, slotA, (size_t)n_tiles * v.ks * kx::kWave * 16, &s);
+    out->A_hi = v.split ? ws(c, slotAh, (size_t)n_tiles * v.ks * kx::kWave * 16, &s) : nullptr;
     out->theta = (float*)ws(c, slotTh, (size_t)n_tiles * 4, &s);
     out->row_v = (int32_t*)ws(c, slotRv, (size_t)n_tiles * kx::kTile * 4, &s);
     if (s != KRUX_OK) return s;
     kx::PrepArgs a{};
     a.ranks2 = ranks2; a.tiesum = tiesum; a.perms = perms; a.rows = rows; a.d_nrows = d_nrows;
-    a.n_rows = n_rows; a.T = T; a.K = K; a.ks = v.ks;
-    a.A = out->A; a.A_hi = nullptr; a.theta = out->theta; a.row_v = out->row_v;
+    a.n_rows = n_rows; a.n_alloc_rows = n_alloc; a.T = T; a.K = K; a.ks = v.ks;
+    a.A = out->A; a.A_hi = out->A_hi; a.theta = out->theta; a.row_v = out->row_v;
     int64_t total = n_tiles * v.ks * kx::kWave;
     int grid = (int)std::min<int64_t>(ceil_div(total, 256), (int64_t)c->n_cu * 16);
     HIP_TRY(c, kx_launch_fill_i32((int32_t*)out->theta, n_tiles, 0x7F800000, st));  // +inf
@@ -175,22 +196,72 @@ krux_status prep_ranks(krux_ctx* c, const Variant& v, const int16_t* ranks2, con
     return KRUX_OK;
 }
 
+// Kernel variant per (K, precision).  The SNP-stationary kernel keeps a SNP
+// tile's columns in registers (K <= 128); larger K uses the tiled kernel.
+// The DIAG form's integer column coefficients keep the fp32 accumulation
+// exact while K^3/4 < 2^24 (K <= 406); beyond that the plain indicators.
 krux_status choose_variant(krux_ctx* c, int K, int precision, Variant* v) {
     if (precision == KRUX_PREC_FP16) {
-        if (K > 128)
-            return fail(c, KRUX_ERR_UNSUPPORTED,
-                        "fp16 path: K = %d > 128 is not supported by this build", K);
-        *v = {kx::F16, (int)ceil_div(K, 16), kx::DIAG};
+        if (K <= 128) {
+            *v = {kx::F16, (int)ceil_div(K, 16), kx::DIAG, false, false};
+        } else {
+            *v = {kx::F16, (int)ceil_div(ceil_div(K, 16), 2) * 2, K <= 400 ? kx::DIAG : kx::PLAIN,
+                  true, false};
+        }
         return KRUX_OK;
     }
     if (precision == KRUX_PREC_INT8) {
-        if (K > 127)
-            return fail(c, KRUX_ERR_UNSUPPORTED,
-                        "int8 path: K = %d > 127 is not supported by this build", K);
-        *v = {kx::I8, (int)ceil_div(K, 32), kx::DIAG};
+        if (K <= 127) {
+            *v = {kx::I8, (int)ceil_div(K, 32), kx::DIAG, false, false};
+        } else {
+            *v = {kx::I8, (int)ceil_div(ceil_div(K, 32), 2) * 2, kx::PLAIN, true, true};
+        }
         return KRUX_OK;
     }
     return fail(c, KRUX_ERR_UNSUPPORTED, "precision %d not handled by the MFMA path", precision);
+}
+
+krux_status expand_columns(krux_ctx* c, const Variant& v, const SnpSide& sn, hipStream_t st,
+                           Columns* out) {
+    if (!v.tiled) return KRUX_OK;
+    krux_status s = KRUX_OK;
+    const int64_t n_pad = ceil_div(std::max<int64_t>(sn.n_snp_tiles, 1), 4) * 4;
+    const size_t per_col = (size_t)n_pad * v.ks * kx::kWave * 16;
+    out->Bf = ws(c, S_BF, per_col * 2, &s);
+    out->Bf3 = ws(c, S_BF3, per_col * 3, &s);
+    if (s != KRUX_OK) return s;
+    int grid = (int)std::min<int64_t>(ceil_div(n_pad * v.ks * 3 * kx::kWave, 256), (int64_t)c->n_cu * 16);
+    if (v.elem == kx::F16) {
+        HIP_TRY(c, kx_launch_expand_f16(sn.G, sn.gstride, sn.info, n_pad, v.ks, v.form, out->Bf, grid, st));
+        HIP_TRY(c, kx_launch_expand_f16(sn.G, sn.gstride, sn.info, n_pad, v.ks, kx::MISS3, out->Bf3, grid, st));
+    } else {
+        HIP_TRY(c, kx_launch_expand_i8(sn.G, sn.gstride, sn.info, n_pad, v.ks, v.form, out->Bf, grid, st));
+        HIP_TRY(c, kx_launch_expand_i8(sn.G, sn.gstride, sn.info, n_pad, v.ks, kx::MISS3, out->Bf3, grid, st));
+    }
+    return KRUX_OK;
+}
+
+// One scan launch: the kernel family follows the variant.
+krux_status launch_scan(krux_ctx* c, const kx::ScanArgs& a, const Variant& v, const Columns& col,
+                        const void* A_hi, int form, int mode, int grid, hipStream_t st) {
+    if (!v.tiled) {
+        HIP_TRY(c, kx_launch_scan(&a, v.elem, v.ks, form, mode, grid, st));
+        return KRUX_OK;
+    }
+    kx::TiledArgs ta{};
+    ta.Bf = form == kx::MISS3 ? col.Bf3 : col.Bf;
+    ta.A_hi = A_hi;
+    ta.ks = v.ks;
+    if (v.elem == kx::F16) HIP_TRY(c, kx_launch_tiled_f16(&a, &ta, form, mode, grid, st));
+    else HIP_TRY(c, kx_launch_tiled_i8(&a, &ta, form, mode, grid, st));
+    return KRUX_OK;
+}
+
+// Work items of one scan launch (an upper bound; the kernels stop early).
+int64_t scan_items(const Variant& v, int64_t n_rows, int64_t n_snp_tiles, int tiles_per_range) {
+    const int64_t n_tiles = ceil_div(n_rows, kx::kTile);
+    if (v.tiled) return ceil_div(n_tiles, 4) * ceil_div(n_snp_tiles, 2);
+    return ceil_div(n_tiles, tiles_per_range) * ceil_div(n_snp_tiles, kx::kWavesPerBlock);
 }
 
 void set_levels(kx::ScanArgs* a, const double* p_cs, int n) {
@@ -212,11 +283,9 @@ void set_screen(kx::ScanArgs* a, double p_screen) {
 
 // Two launches cover every SNP tile: complete tiles on the fast form, tiles
 // with a missing genotype on the MISS3 form (each kernel skips the others).
-krux_status run_screen(krux_ctx* c, kx::ScanArgs a, const Variant& v, hipStream_t st,
-                       int64_t n_rows_max, bool timed = false) {
-    int64_t n_tiles = ceil_div(n_rows_max, kx::kTile);
-    int64_t items = ceil_div(n_tiles, a.tiles_per_range) *
-                    ceil_div(a.n_snp_tiles, kx::kWavesPerBlock);
+krux_status run_screen(krux_ctx* c, kx::ScanArgs a, const Variant& v, const Columns& col,
+                       const void* A_hi, hipStream_t st, int64_t n_rows_max, bool timed = false) {
+    int64_t items = scan_items(v, n_rows_max, a.n_snp_tiles, a.tiles_per_range);
     if (items <= 0) return KRUX_OK;
     int grid = (int)std::min<int64_t>(items, (int64_t)INT32_MAX);
     // screened pairs go to the candidate buffer and are evaluated exactly after the scan
@@ -239,10 +308,10 @@ krux_status run_screen(krux_ctx* c, kx::ScanArgs a, const Variant& v, hipStream_
         c->ev_used += 2;
         HIP_TRY(c, hipEventRecord(e0, st));
     }
-    HIP_TRY(c, kx_launch_scan(&a, v.elem, v.ks, v.form, 0, grid, st));
+    if ((s = launch_scan(c, a, v, col, A_hi, v.form, kx::SCREEN, grid, st)) != KRUX_OK) return s;
     if (e1) HIP_TRY(c, hipEventRecord(e1, st));
     a.want_flag = 1;
-    HIP_TRY(c, kx_launch_scan(&a, v.elem, v.ks, 2 /*MISS3*/, 0, grid, st));
+    if ((s = launch_scan(c, a, v, col, A_hi, kx::MISS3, kx::SCREEN, grid, st)) != KRUX_OK) return s;
     HIP_TRY(c, kx_launch_candidates(&a, (int)std::min<int64_t>(ceil_div(a.cand_cap, 256),
                                                                  (int64_t)c->n_cu * 8), st));
     return KRUX_OK;
@@ -255,7 +324,7 @@ double screen_level_for_min_p(double p_c, int64_t M) {
 // Per-row minimum p: rows still at p = 1 after the main pass are re-run with
 // a looser screen (every pair whose p falls below the level is evaluated
 // exactly), first at p_mid, then at p = 1 (every pair with H > 0).
-krux_status resolve_min_p(krux_ctx* c, kx::ScanArgs base, const Variant& v,
+krux_status resolve_min_p(krux_ctx* c, kx::ScanArgs base, const Variant& v, const Columns& col,
                           const int16_t* ranks2, const int64_t* tiesum, int64_t T, int K,
                           const int32_t* perms, int64_t V, double p_main, int64_t M,
                           hipStream_t st) {
@@ -283,14 +352,14 @@ krux_status resolve_min_p(krux_ctx* c, kx::ScanArgs base, const Variant& v,
         p_prev = levels[li];
         RankSide r2;
         s = prep_ranks(c, v, ranks2, tiesum, T, K, perms, rows_out, n_out, V, S_A2, S_THETA2,
-                       S_ROWV2, st, &r2);
+                       S_ROWV2, st, &r2, S_AH2);
         if (s != KRUX_OK) return s;
         kx::ScanArgs a = base;
         a.A = r2.A; a.theta = r2.theta; a.row_v = r2.row_v;
         a.d_nrows = n_out; a.n_rows = V;
         a.hits = nullptr; a.counts = nullptr; a.n_lev = 0;
         set_screen(&a, levels[li]);
-        s = run_screen(c, a, v, st, V);
+        s = run_screen(c, a, v, col, r2.A_hi, st, V);
         if (s != KRUX_OK) return s;
         rows_in = rows_out;
         n_in = n_out;
@@ -349,10 +418,12 @@ krux_status test_impl(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum,
     HIP_TRY(c, hipSetDevice(c->device));
 
     SnpSide sn;
-    if ((s = pack_snps(c, geno, M, ld_geno, K, v.form == kx::DIAG, st, &sn)) != KRUX_OK) return s;
+    if ((s = pack_snps(c, geno, M, ld_geno, K, v.form == kx::DIAG, row_bytes(v), st, &sn)) != KRUX_OK) return s;
+    Columns col;
+    if ((s = expand_columns(c, v, sn, st, &col)) != KRUX_OK) return s;
     RankSide rk;
     if ((s = prep_ranks(c, v, ranks2, tiesum, T, K, nullptr, nullptr, nullptr, T, S_A, S_THETA,
-                        S_ROWV, st, &rk)) != KRUX_OK)
+                        S_ROWV, st, &rk, S_AH)) != KRUX_OK)
         return s;
 
     kx::ScanArgs a{};
@@ -366,14 +437,12 @@ krux_status test_impl(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum,
         a.H_out = H; a.p_out = p; a.sums_out = sums;
         set_screen(&a, 1.0);
         set_levels(&a, nullptr, 0);
-        int64_t items = ceil_div(ceil_div(T, kx::kTile), a.tiles_per_range) *
-                        ceil_div(a.n_snp_tiles, kx::kWavesPerBlock);
+        int64_t items = scan_items(v, T, a.n_snp_tiles, a.tiles_per_range);
         if (items <= 0) return KRUX_OK;
         int grid = (int)std::min<int64_t>(items, (int64_t)INT32_MAX);
         a.want_flag = -1;
-        HIP_TRY(c, kx_launch_scan(&a, v.elem, v.ks, 2 /*MISS3*/,
-                                  mode == KRUX_MODE_FULL ? 1 : 2, grid, st));
-        return KRUX_OK;
+        return launch_scan(c, a, v, col, rk.A_hi, kx::MISS3,
+                           mode == KRUX_MODE_FULL ? kx::FULL : kx::SUMS, grid, st);
     }
 
     int64_t cap = hit_capacity;
@@ -393,9 +462,9 @@ krux_status test_impl(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum,
     // the few rows without one get the looser passes of resolve_min_p.
     const double p_screen = min_p ? screen_level_for_min_p(p_c, M) : p_c;
     set_screen(&a, p_screen);
-    if ((s = run_screen(c, a, v, st, T, true)) != KRUX_OK) return s;
+    if ((s = run_screen(c, a, v, col, rk.A_hi, st, T, true)) != KRUX_OK) return s;
     if (min_p && T > 0) {
-        if ((s = resolve_min_p(c, a, v, ranks2, tiesum, T, K, nullptr, T, p_screen, M, st)) != KRUX_OK)
+        if ((s = resolve_min_p(c, a, v, col, ranks2, tiesum, T, K, nullptr, T, p_screen, M, st)) != KRUX_OK)
             return s;
         HIP_TRY(c, kx_launch_bits_to_double(minp, T, min_p, st));
     }
@@ -516,7 +585,7 @@ krux_status krux_rank(krux_ctx* c, const float* expr, int64_t T, int32_t K, int6
     if (T > 0 && (!expr || !ranks2 || !tiesum)) return fail(c, KRUX_ERR_ARG, "NULL array");
     if (T == 0) return KRUX_OK;
     HIP_TRY(c, hipSetDevice(c->device));
-    HIP_TRY(c, kx_launch_rank(expr, T, K, ld_expr, ranks2, tiesum, nvalid, c->n_cu * 32,
+    HIP_TRY(c, kx_launch_rank(expr, T, K, ld_expr, ranks2, tiesum, nvalid, 1 << 30,
                               (hipStream_t)stream));
     return KRUX_OK;
 }
@@ -552,10 +621,12 @@ krux_status krux_permute(krux_ctx* c, const int16_t* ranks2, const int64_t* ties
     hipStream_t st = (hipStream_t)stream;
     const int64_t V = (int64_t)P * T;
     SnpSide sn;
-    if ((s = pack_snps(c, geno, M, ld_geno, K, true, st, &sn)) != KRUX_OK) return s;
+    if ((s = pack_snps(c, geno, M, ld_geno, K, v.form == kx::DIAG, row_bytes(v), st, &sn)) != KRUX_OK) return s;
+    Columns col;
+    if ((s = expand_columns(c, v, sn, st, &col)) != KRUX_OK) return s;
     RankSide rk;
     if ((s = prep_ranks(c, v, ranks2, tiesum, T, K, perms, nullptr, nullptr, V, S_A, S_THETA,
-                        S_ROWV, st, &rk)) != KRUX_OK)
+                        S_ROWV, st, &rk, S_AH)) != KRUX_OK)
         return s;
     unsigned long long* minp =
         (unsigned long long*)ws(c, S_MINP, (size_t)std::max<int64_t>(V, 1) * 8, &s);
@@ -573,9 +644,9 @@ krux_status krux_permute(krux_ctx* c, const int16_t* ranks2, const int64_t* ties
     double loosest = *std::max_element(p_cs, p_cs + n_thr);
     if (min_p) loosest = screen_level_for_min_p(loosest, M);
     set_screen(&a, loosest);
-    if ((s = run_screen(c, a, v, st, V, true)) != KRUX_OK) return s;
+    if ((s = run_screen(c, a, v, col, rk.A_hi, st, V, true)) != KRUX_OK) return s;
     if (min_p && V > 0) {
-        if ((s = resolve_min_p(c, a, v, ranks2, tiesum, T, K, perms, V, loosest, M, st)) != KRUX_OK)
+        if ((s = resolve_min_p(c, a, v, col, ranks2, tiesum, T, K, perms, V, loosest, M, st)) != KRUX_OK)
             return s;
         HIP_TRY(c, kx_launch_bits_to_double(minp, V, min_p, st));
     }

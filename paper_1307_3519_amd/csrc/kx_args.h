@@ -12,6 +12,7 @@ struct PrepArgs {
     const int32_t* rows;     // list of virtual rows or null (identity)
     const int32_t* d_nrows;  // device count of rows (with list) or null
     int64_t n_rows;          // host bound on the number of operand rows
+    int64_t n_alloc_rows;    // rows written (>= n_rows; the rest are zero padding)
     int64_t T;
     int K;
     int ks;                  // k-steps of the operand
@@ -63,6 +64,13 @@ struct ScanArgs {
     uint4* cand;
     int64_t cand_cap;
     unsigned long long* n_cand;
+};
+
+// Extra operands of the tiled large-K kernels.
+struct TiledArgs {
+    const void* Bf;      // [snp tiles][ks][NC][64] fragments
+    const void* A_hi;    // int8 byte split: high plane of A, else null
+    int ks;              // k-steps of both operands (even)
 };
 
 // candidate entry form flag: column values are (Y, Z) of DIAG or (D1, D2)

@@ -11,6 +11,7 @@
 namespace kx {
 struct PrepArgs;
 struct ScanArgs;
+struct TiledArgs;
 }
 
 extern "C" {
@@ -32,6 +33,16 @@ hipError_t kx_launch_bits_to_double(const unsigned long long* bits, int64_t n, d
 hipError_t kx_launch_scan(const kx::ScanArgs* a, int elem, int ks, int form, int mode, int grid,
                           hipStream_t st);
 hipError_t kx_launch_candidates(const kx::ScanArgs* a, int grid, hipStream_t st);
+hipError_t kx_launch_tiled_f16(const kx::ScanArgs* a, const kx::TiledArgs* ta, int form, int mode,
+                               int grid, hipStream_t st);
+hipError_t kx_launch_tiled_i8(const kx::ScanArgs* a, const kx::TiledArgs* ta, int form, int mode,
+                              int grid, hipStream_t st);
+hipError_t kx_launch_expand_f16(const int8_t* G, int gstride, const kx::SnpInfo* info,
+                                int64_t n_tiles_pad, int ks, int form, void* Bf, int grid,
+                                hipStream_t st);
+hipError_t kx_launch_expand_i8(const int8_t* G, int gstride, const kx::SnpInfo* info,
+                               int64_t n_tiles_pad, int ks, int form, void* Bf, int grid,
+                               hipStream_t st);
 size_t kx_sort_tmp_bytes(int64_t cap);
 hipError_t kx_sort_hits(const kx::HitRec* stage, const unsigned long long* n_hits, int64_t cap,
                         unsigned long long* keys, uint32_t* idx, void* tmp, size_t tmp_bytes,

@@ -74,7 +74,7 @@ __global__ __launch_bounds__(256) void pack_snps(const int8_t* __restrict__ geno
             info[m] = s;
             if (cm > 0 && m < M) {
                 atomicOr(&tile_flags[m >> 5], 1);
-                atomicOr(&tile_flags[m_pad >> 5], 1);   // "some SNP has a missing genotype"
+                atomicOr(&tile_flags[(M + 31) >> 5], 1);  // "some SNP has a missing genotype"
             }
         }
     }
@@ -109,7 +109,7 @@ __device__ inline int64_t count_rows(const PrepArgs& a) {
 
 // fp16 operand: one thread per (tile, k-step, lane) writes 8 halves.
 __global__ __launch_bounds__(256) void prep_ranks_f16(PrepArgs a) {
-    const int64_t n_tiles = (a.n_rows + kTile - 1) / kTile;
+    const int64_t n_tiles = (a.n_alloc_rows + kTile - 1) / kTile;
     const int64_t total = n_tiles * a.ks * kWave;
     const int64_t nr = count_rows(a);
     half8* A = (half8*)a.A;
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(256) void prep_ranks_f16(PrepArgs a) {
 // int8 operand: 16 samples per lane per k-step of 32.  With A_hi set, the
 // centred rank is split c = 128 h + l, l in [0, 127].
 __global__ __launch_bounds__(256) void prep_ranks_i8(PrepArgs a) {
-    const int64_t n_tiles = (a.n_rows + kTile - 1) / kTile;
+    const int64_t n_tiles = (a.n_alloc_rows + kTile - 1) / kTile;
     const int64_t total = n_tiles * a.ks * kWave;
     const int64_t nr = count_rows(a);
     int4v* A = (int4v*)a.A;

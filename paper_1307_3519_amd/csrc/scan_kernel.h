@@ -167,6 +167,7 @@ __device__ inline void eval_candidate(const ScanArgs& a, int64_t row, int64_t m,
                                       float z, bool plain) {
     const SnpInfo inf = a.info[m];
     const int64_t v = a.row_v[row];
+    if (v < 0) return;                // padding row of a partial tile
     int64_t D1, D2;
     if (plain) {
         D1 = (int64_t)y;
@@ -309,6 +310,9 @@ __device__ inline void drain(const ScanArgs& a, int2* queue, int& qn, int16_t* q
     for (int e = 0; e < qn; ++e) {
         int2 q = queue[e];
         int64_t v = a.row_v[q.x];
+        // padding rows (zero operand) can pass the missing-genotype bound; the
+        // entry is the same for the whole wave, so the skip is uniform
+        if (v < 0) continue;
         int64_t m = q.y;
         int df;
         int64_t s[3];

@@ -1,0 +1,335 @@
+// scan_tiled.h -- the rank-sum GEMM with its fused epilogue for sample counts
+// too large to keep a SNP tile's genotype columns in registers (K > 128).
+//
+// Same computation as scan_kernel (eq. (1), eq. (2) with the tie factor, the
+// chi-square screen and exact evaluation of candidates), organised as a
+// classic two-operand tiled GEMM: a block computes 128 traits x (64 or 128)
+// SNPs; the K loop runs over chunks of two 16-sample (fp16) or 32-sample
+// (int8) k-steps whose A (centred ranks) and B (genotype columns, expanded
+// once into MFMA fragment order) fragments are staged through a
+// double-buffered LDS ring with one block barrier per chunk.  Each wave owns
+// 64 traits x (32 or 64) SNPs of accumulators.  With int8 and K > 127 the
+// centred rank is split into bytes, c = 128 h + l, and two accumulator sets
+// give D = 128 D_h + D_l exactly.
+#pragma once
+#include "scan_kernel.h"
+
+namespace kx {
+
+
+// Per-lane screen constants of one SNP column.
+struct LaneK {
+    float wy, wz, w0, w1, w2, qn0, qn1, qn2, delta;
+    bool miss;
+};
+
+__device__ inline LaneK lane_constants(const SnpInfo& inf, int K, const float* inv_hc) {
+    LaneK c;
+    const int kp = K - inf.nmiss;
+    const float fac = 3.0f * (float)(kp - 1) * (1.0f + kScreenSlack) * inv_hc[snp_df(inf)];
+    c.wy = inf.wy * fac; c.wz = inf.wz * fac;
+    c.w0 = inf.a0 * fac; c.w1 = inf.a1 * fac; c.w2 = inf.a2 * fac;
+    c.miss = inf.nmiss > 0;
+    c.qn0 = (float)inf.nmiss * inf.n0; c.qn1 = (float)inf.nmiss * inf.n1;
+    c.qn2 = (float)inf.nmiss * inf.n2;
+    c.delta = (float)(cube_minus(K) - cube_minus(kp));
+    return c;
+}
+
+// Screen value (> 0: candidate) of one pair from its column values.
+template <int FORM>
+__device__ inline float screen_value(const LaneK& c, float th, float v0, float v1, float v2) {
+    if constexpr (FORM == DIAG) {
+        return fmaf(c.wy * v0, v0, fmaf(c.wz * v1, v1, -th));
+    } else if constexpr (FORM == PLAIN) {
+        const float d0 = -(v0 + v1);
+        return fmaf(c.w0 * d0, d0, fmaf(c.w1 * v0, v0, fmaf(c.w2 * v1, v1, -th)));
+    } else {
+        float d0 = v0, d1 = v1, d2 = v2;
+        if (c.miss) {
+            d0 = fabsf(d0) + c.qn0; d1 = fabsf(d1) + c.qn1; d2 = fabsf(d2) + c.qn2;
+            const float tl = c.delta - th * 0.99999905f;
+            return fmaf(c.w0 * d0, d0, fmaf(c.w1 * d1, d1, fmaf(c.w2 * d2, d2, tl)));
+        }
+        return fmaf(c.w0 * d0, d0, fmaf(c.w1 * d1, d1, fmaf(c.w2 * d2, d2, -th)));
+    }
+}
+
+template <int E, int FORM, int MODE, bool SPLIT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void scan_tiled(ScanArgs a, TiledArgs ta) {
+    using T_ = ET<E>;
+    using frag = typename T_::frag;
+    using acc_t = typename T_::acc;
+    constexpr int NC = FORM == MISS3 ? 3 : 2;
+    constexpr int WS = (NC == 2 && !SPLIT) ? 2 : 1;    // SNP tiles per wave
+    constexpr int NP = SPLIT ? 2 : 1;                  // A planes
+    constexpr int KC = 2;                              // k-steps per chunk
+    constexpr int BT = 4;                              // trait tiles per block
+    constexpr int BS = 2 * WS;                         // SNP tiles per block
+    constexpr int NFA = BT * KC * NP;                  // A fragments per chunk
+    constexpr int NFB = BS * KC * NC;                  // B fragments per chunk
+    constexpr int NF = NFA + NFB;
+    constexpr int FPW = (NF + kWavesPerBlock - 1) / kWavesPerBlock;  // loads per wave
+    constexpr bool QUEUE = FORM == MISS3;
+
+    __shared__ frag s_buf[2][NF][kWave];
+    __shared__ int2 s_queue[QUEUE ? kWavesPerBlock : 1][QUEUE ? kQueueCap : 1];
+    __shared__ uint4 s_stage[MODE == SCREEN ? kWavesPerBlock : 1][kStageCap];
+    __shared__ ScanArgs s_args;
+    extern __shared__ int16_t s_qbuf[];
+    if (threadIdx.x == 0) s_args = a;
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    int2* queue = s_queue[QUEUE ? wave : 0];
+    uint4* stage = s_stage[MODE == SCREEN ? wave : 0];
+    int sn = 0, qn = 0;
+    int16_t* qbuf = s_qbuf + (QUEUE ? wave * a.K : 0);
+
+    if (a.want_flag == 1 && a.tile_flags[a.n_snp_tiles] == 0) return;
+    int64_t n_rows = a.n_rows;
+    if (a.d_nrows) {
+        int64_t d = *a.d_nrows;
+        n_rows = d < n_rows ? d : n_rows;
+    }
+    const int KS = ta.ks;
+    const int64_t n_tiles = (n_rows + kTile - 1) / kTile;
+    const int64_t n_tb = (n_tiles + BT - 1) / BT;
+    const int64_t n_sb = (a.n_snp_tiles + BS - 1) / BS;
+    const int64_t items = n_tb * n_sb;
+    const frag* A = (const frag*)a.A;
+    const frag* Ah = (const frag*)ta.A_hi;
+    const frag* Bf = (const frag*)ta.Bf;
+    const int nchunks = KS / KC;
+
+    for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
+        const int64_t sb = item / n_tb, tb = item % n_tb;
+        // SNP tiles of this wave and whether each is handled by this kernel
+        int64_t stl[WS];
+        bool act[WS];
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < WS; ++j) {
+            stl[j] = sb * BS + (wave & 1) * WS + j;
+            act[j] = stl[j] < a.n_snp_tiles &&
+                     (a.want_flag < 0 || a.tile_flags[stl[j]] == a.want_flag);
+            any = any || act[j];
+        }
+        if (!__syncthreads_or(any)) continue;   // block-uniform skip
+
+        // fragment loads of chunk ch: fragment f of the block's stage
+        frag ld[FPW];
+        auto gload_chunk = [&](int ch) {
+#pragma unroll
+            for (int i = 0; i < FPW; ++i) {
+                const int f = wave * FPW + i;
+                if (f < NF) {
+                    if (f < NFA) {
+                        const int p = f / (BT * KC), r = f % (BT * KC);
+                        const int tt = r / KC, kk = r % KC;
+                        const int64_t tile = tb * BT + tt;
+                        const frag* src = p ? Ah : A;
+                        ld[i] = gload(src + (tile * KS + ch * KC + kk) * kWave + lane);
+                    } else {
+                        const int g = f - NFA;
+                        const int s = g / (KC * NC), r = g % (KC * NC);
+                        const int kk = r / NC, c = r % NC;
+                        const int64_t st = sb * BS + s;
+                        ld[i] = gload(Bf + ((st * KS + ch * KC + kk) * NC + c) * kWave + lane);
+                    }
+                }
+            }
+        };
+        auto sstore_chunk = [&](int buf) {
+#pragma unroll
+            for (int i = 0; i < FPW; ++i) {
+                const int f = wave * FPW + i;
+                if (f < NF) s_buf[buf][f][lane] = ld[i];
+            }
+        };
+        acc_t acc[NP][2][WS][NC];
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                for (int j = 0; j < WS; ++j)
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) acc[p][ti][j][c] = acc_t{};
+
+        __syncthreads();              // previous item's readers are done with s_buf
+        gload_chunk(0);
+        sstore_chunk(0);
+        __syncthreads();
+        for (int ch = 0; ch < nchunks; ++ch) {
+            const int buf = ch & 1;
+            if (ch + 1 < nchunks) gload_chunk(ch + 1);
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk) {
+                frag fa[NP][2], fb[WS][NC];
+#pragma unroll
+                for (int p = 0; p < NP; ++p)
+#pragma unroll
+                    for (int ti = 0; ti < 2; ++ti)
+                        fa[p][ti] = s_buf[buf][p * BT * KC + ((wave >> 1) * 2 + ti) * KC + kk][lane];
+#pragma unroll
+                for (int j = 0; j < WS; ++j)
+#pragma unroll
+                    for (int c = 0; c < NC; ++c)
+                        fb[j][c] = s_buf[buf][NFA + ((wave & 1) * WS + j) * KC * NC + kk * NC + c][lane];
+#pragma unroll
+                for (int p = 0; p < NP; ++p)
+#pragma unroll
+                    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                        for (int j = 0; j < WS; ++j)
+#pragma unroll
+                            for (int c = 0; c < NC; ++c)
+                                acc[p][ti][j][c] = T_::mma(fa[p][ti], fb[j][c], acc[p][ti][j][c]);
+            }
+            if (ch + 1 < nchunks) sstore_chunk(buf ^ 1);
+            __syncthreads();
+        }
+
+        // epilogue over the wave's 2 x WS output tiles
+#pragma unroll
+        for (int j = 0; j < WS; ++j) {
+            if (!act[j]) continue;
+            const int64_t m = stl[j] * kTile + (lane & 31);
+            const SnpInfo inf = gload(a.info + m);
+            const LaneK lk = lane_constants(inf, a.K, a.inv_hc);
+#pragma unroll
+            for (int ti = 0; ti < 2; ++ti) {
+                const int64_t tt = tb * BT + (wave >> 1) * 2 + ti;
+                if (tt >= n_tiles) continue;
+                const int64_t rb = tt * kTile + 4 * (lane >> 5);
+                auto colv = [&](int c, int r) -> float {
+                    if constexpr (SPLIT)
+                        return (float)(128 * acc[1][ti][j][c][r] + acc[0][ti][j][c][r]);
+                    else
+                        return T_::val(acc[0][ti][j][c], r);
+                };
+                if constexpr (MODE == SCREEN) {
+                    const float th = cload(a.theta + tt);
+                    float gmax = -__builtin_inff();
+#pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        gmax = fmaxf(gmax, screen_value<FORM>(lk, th, colv(0, r), colv(1, r),
+                                                              NC == 3 ? colv(NC - 1, r) : 0.0f));
+                    if (!__any(gmax > 0.0f)) continue;
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int64_t row = rb + 8 * (r >> 2) + (r & 3);
+                        const float v0 = colv(0, r), v1 = colv(1, r);
+                        const float v2 = NC == 3 ? colv(NC - 1, r) : 0.0f;
+                        bool cand = screen_value<FORM>(lk, th, v0, v1, v2) > 0.0f;
+                        if constexpr (QUEUE) {
+                            const bool qpush = cand && lk.miss;
+                            const unsigned long long msk = __ballot(qpush);
+                            if (msk) {
+                                if (qn + 64 > kQueueCap) drain<MODE>(a, queue, qn, qbuf, lane);
+                                const unsigned long long lt =
+                                    (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+                                if (qpush) queue[qn + __popcll(msk & lt)] = make_int2((int)row, (int)m);
+                                qn += __popcll(msk);
+                            }
+                            cand = cand && !lk.miss;
+                        }
+                        if constexpr (FORM == DIAG)
+                            stage_candidates(a, &s_args, stage, sn, lane, cand, row, m, v0, v1, false);
+                        else if constexpr (FORM == PLAIN)
+                            stage_candidates(a, &s_args, stage, sn, lane, cand, row, m, v0, v1, true);
+                        else
+                            stage_candidates(a, &s_args, stage, sn, lane, cand, row, m, v1, v2, true);
+                    }
+                    if (QUEUE && qn) drain<MODE>(a, queue, qn, qbuf, lane);
+                } else if constexpr (FORM == MISS3) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int64_t row = rb + 8 * (r >> 2) + (r & 3);
+                        const int64_t v = a.row_v[row];
+                        bool want = v >= 0 && m < a.M;
+                        const bool qpush = want && lk.miss;
+                        const unsigned long long msk = __ballot(qpush);
+                        if (msk) {
+                            if (qn + 64 > kQueueCap) drain<MODE>(a, queue, qn, qbuf, lane);
+                            const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+                            if (qpush) queue[qn + __popcll(msk & lt)] = make_int2((int)row, (int)m);
+                            qn += __popcll(msk);
+                        }
+                        want = want && !lk.miss;
+                        if (want) {
+                            const int64_t D0 = (int64_t)colv(0, r), D1 = (int64_t)colv(1, r),
+                                          D2 = (int64_t)colv(2, r);
+                            const double H = exact_H(D0, D1, D2, inf.n0, inf.n1, inf.n2, a.K,
+                                                     a.tiesum[v % a.T], snp_df(inf));
+                            const int64_t k1 = a.K + 1;
+                            emit_full<MODE>(a, v, m, H, snp_df(inf), D0 + inf.n0 * k1,
+                                            D1 + inf.n1 * k1, D2 + inf.n2 * k1);
+                        }
+                    }
+                    if (qn) drain<MODE>(a, queue, qn, qbuf, lane);
+                }
+            }
+        }
+    }
+    if constexpr (MODE == SCREEN) flush_stage(a, &s_args, stage, sn, lane);
+}
+
+// B fragments of every SNP tile: column c of SNP m at sample k is
+// coef(c, code(m, k)) for the form's coefficients, 0 at missing samples.
+template <int E, int FORM>
+__global__ __launch_bounds__(256) void expand_columns(const int8_t* __restrict__ G, int gstride,
+                                                      const SnpInfo* __restrict__ info,
+                                                      int64_t n_tiles_pad, int KS, void* Bf) {
+    using T_ = ET<E>;
+    using frag = typename T_::frag;
+    constexpr int NC = FORM == MISS3 ? 3 : 2;
+    frag* out = (frag*)Bf;
+    const int64_t total = n_tiles_pad * KS * NC * kWave;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int lane = (int)(i % kWave);
+        int64_t q = i / kWave;
+        const int c = (int)(q % NC);
+        q /= NC;
+        const int s = (int)(q % KS);
+        const int64_t st = q / KS;
+        const int64_t m = st * kTile + (lane & 31);
+        const SnpInfo inf = info[m];
+        float cv[3];
+        if constexpr (FORM == DIAG) {
+            if (c == 0) { cv[0] = 0.f; cv[1] = inf.cy1; cv[2] = inf.cy2; }
+            else { cv[0] = 0.f; cv[1] = 0.f; cv[2] = 1.f; }
+        } else if constexpr (FORM == PLAIN) {
+            cv[0] = 0.f; cv[1] = c == 0 ? 1.f : 0.f; cv[2] = c == 1 ? 1.f : 0.f;
+        } else {
+            cv[0] = c == 0 ? 1.f : 0.f; cv[1] = c == 1 ? 1.f : 0.f; cv[2] = c == 2 ? 1.f : 0.f;
+        }
+        int8_t codes[T_::per_lane];
+        const int8_t* src = G + m * (int64_t)gstride + s * T_::kps + T_::per_lane * (lane >> 5);
+#pragma unroll
+        for (int e = 0; e < T_::per_lane; ++e) codes[e] = src[e];
+        out[i] = T_::make(codes, cv[0], cv[1], cv[2]);
+    }
+}
+
+template <int E, int FORM, int MODE, bool SPLIT>
+inline hipError_t launch_tiled(const ScanArgs& a, const TiledArgs& ta, int grid, hipStream_t st) {
+    size_t lds = FORM == MISS3 ? (size_t)kWavesPerBlock * a.K * sizeof(int16_t) : 0;
+    auto kern = scan_tiled<E, FORM, MODE, SPLIT>;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 256, lds) != hipSuccess || occ < 1)
+        occ = 1;
+    int dev = 0, n_cu = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    int64_t resident = (int64_t)n_cu * occ;
+    int g = (int)(grid < resident ? grid : resident);
+    hipLaunchKernelGGL(kern, dim3(g), dim3(256), lds, st, a, ta);
+    return hipGetLastError();
+}
+
+}  // namespace kx

@@ -89,14 +89,16 @@ def _ranks(kx, x):
 # ---------------------------------------------------------------- full / sums
 CASES = [  # (K, T, M, p_missing)
     (5, 40, 37, 0.0), (33, 70, 100, 0.0), (102, 70, 161, 0.0), (102, 33, 65, 0.05),
-    (128, 65, 64, 0.0), (48, 64, 96, 0.1), (77, 31, 40, 0.03)]
+    (128, 65, 64, 0.0), (48, 64, 96, 0.1), (77, 31, 40, 0.03),
+    # tiled large-K kernels: ragged trait blocks (T % 128) and SNP blocks (M % 128),
+    # the DIAG / PLAIN boundary at K = 400 / 401, byte-split int8 ranks
+    (129, 70, 100, 0.0), (150, 140, 161, 0.0), (233, 65, 97, 0.02), (400, 40, 70, 0.0),
+    (401, 36, 45, 0.0), (500, 37, 70, 0.01), (1000, 33, 40, 0.0)]
 
 
 @pytest.mark.parametrize("prec", ["fp16", "int8", "fp64"])
 @pytest.mark.parametrize("K,T,M,pm", CASES)
 def test_full_and_sums(kx, prec, K, T, M, pm):
-    if prec == "int8" and K > 127:
-        pytest.skip("int8 path covers K <= 127")
     say("full/sums", prec, K, T, M, pm)
     x, g = _inputs(7 * K + T, T, K, M, p_missing=pm)
     r, ts = _ranks(kx, x)
@@ -138,8 +140,6 @@ def _check_hits(kx, x, g, p_c, prec, cap=1 << 15):
 @pytest.mark.parametrize("prec", ["fp16", "int8", "fp64"])
 @pytest.mark.parametrize("K,T,M,pm", CASES)
 def test_hits_and_min_p(kx, prec, K, T, M, pm):
-    if prec == "int8" and K > 127:
-        pytest.skip("int8 path covers K <= 127")
     say("hits", prec, K, T, M, pm)
     x, g = _inputs(11 * K + M, T, K, M, p_missing=pm)
     n = _check_hits(kx, x, g, 0.02, prec)
@@ -189,7 +189,7 @@ def test_empty_shapes(kx):
 
 
 # ---------------------------------------------------------------- permutations
-@pytest.mark.parametrize("K,T,M", [(102, 70, 130), (30, 40, 64)])
+@pytest.mark.parametrize("K,T,M", [(102, 70, 130), (30, 40, 64), (233, 40, 70)])
 def test_permute_counts_and_min_p(kx, K, T, M):
     say("permute", K, T, M)
     x, g = _inputs(13 + K, T, K, M)
