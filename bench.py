@@ -29,6 +29,31 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+ROOT = os.path.dirname(os.path.abspath(__file__))
+PROFILE = os.path.join(ROOT, "profiles", "scan_f16_diag_screen_K102_T20000_M500000.txt")
+
+
+def measured_traffic():
+    """HBM bytes per main-pass launch of the dominant kernel from the committed
+    counter summary (FETCH_SIZE and WRITE_SIZE runs, scaled by a plain copy),
+    or None when the kernel's sources changed since the counters were taken."""
+    import hashlib
+    try:
+        fields = {}
+        for line in open(PROFILE):
+            if ":" in line:
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+        h = hashlib.sha256()
+        for src in fields["sources"].split():
+            h.update(open(os.path.join(ROOT, src), "rb").read())
+        if h.hexdigest() != fields["source_sha256"]:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -38,7 +63,7 @@ def main():
     ap.add_argument("--M", type=int, default=None, help="override SNP count")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip the fp64 / int8 paths")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-minp", action="store_true", help="hit list only (no per-trait min p)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 256 MiB device-to-device copy first (reference for "
@@ -129,7 +154,7 @@ def main():
                                                                 " + per-trait min p")},
         "roofline": {"bound": "mfma", "kernel": "scan_kernel<F16, KS=7, DIAG, SCREEN>",
                      "achieved": achieved, "peak": PEAK_FP16_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP16_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP16_TFLOPS, "traffic": measured_traffic(),
                      "kernel_ms": kern_ms, "kernel_launches": kn,
                      "flops_per_pair": flops_per_pair},
         "n_hits": n_hits,
@@ -163,7 +188,7 @@ def main():
     if not args.no_cpu:
         import oracle
         xs, gs = w["expr"], w["geno"]
-        probe = 20
+        probe = 200
         t0 = time.perf_counter()
         oracle.scan(xs, gs[:probe], p_cs=(p_c,), hits=True, min_p=True)
         dt = time.perf_counter() - t0

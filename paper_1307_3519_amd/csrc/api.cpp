@@ -257,6 +257,19 @@ krux_status launch_scan(krux_ctx* c, const kx::ScanArgs& a, const Variant& v, co
     return KRUX_OK;
 }
 
+// Trait tiles per work item of the SNP-stationary kernel.  Concurrent blocks
+// walk consecutive SNP blocks of one trait range, so the range's operand
+// slice is what every XCD's L2 (4 MB) holds: at most ~2.5 MB per range, and
+// at least two ranges so that the persistent grid's last round is short.
+int trait_range(const Variant& v, int64_t n_rows) {
+    const int64_t n_tiles = std::max<int64_t>(ceil_div(n_rows, kx::kTile), 1);
+    const int64_t tile_bytes = (int64_t)v.ks * kx::kWave * 16;
+    int64_t ranges = ceil_div(n_tiles * tile_bytes, (int64_t)5 << 19);
+    if (n_tiles >= 128) ranges = std::max<int64_t>(ranges, 2);
+    const int64_t tpr = ceil_div(ceil_div(n_tiles, ranges), 2) * 2;
+    return (int)std::min<int64_t>(tpr, 1 << 20);
+}
+
 // Work items of one scan launch (an upper bound; the kernels stop early).
 int64_t scan_items(const Variant& v, int64_t n_rows, int64_t n_snp_tiles, int tiles_per_range) {
     const int64_t n_tiles = ceil_div(n_rows, kx::kTile);
@@ -380,7 +393,8 @@ krux_status check_ranks(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesu
 
 krux_status check_geno(krux_ctx* c, const int8_t* geno, int64_t M, int64_t ld, int32_t K) {
     if (M < 0) return fail(c, KRUX_ERR_ARG, "M = %lld < 0", (long long)M);
-    if (M > INT32_MAX - 4096) return fail(c, KRUX_ERR_UNSUPPORTED, "M too large");
+    // SNP indices share a 32-bit word with two flag bits in the candidate buffer
+    if (M > (1LL << 30) - 4096) return fail(c, KRUX_ERR_UNSUPPORTED, "M too large");
     if (M > 0 && !geno) return fail(c, KRUX_ERR_ARG, "geno is NULL");
     if (ld < K) return fail(c, KRUX_ERR_SHAPE, "ld_geno = %lld < K = %d", (long long)ld, K);
     return KRUX_OK;
@@ -430,7 +444,7 @@ krux_status test_impl(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum,
     a.A = rk.A; a.theta = rk.theta; a.row_v = rk.row_v; a.d_nrows = nullptr; a.n_rows = T;
     a.T = std::max<int64_t>(T, 1); a.tiesum = tiesum; a.ranks2 = ranks2; a.perms = nullptr;
     a.G = sn.G; a.gstride = sn.gstride; a.info = sn.info; a.tile_flags = sn.flags;
-    a.M = M; a.n_snp_tiles = sn.n_snp_tiles; a.K = K; a.tiles_per_range = 64;
+    a.M = M; a.n_snp_tiles = sn.n_snp_tiles; a.K = K; a.tiles_per_range = trait_range(v, T);
     a.snp_base = snp_base;
 
     if (mode != KRUX_MODE_HITS) {
@@ -637,7 +651,7 @@ krux_status krux_permute(krux_ctx* c, const int16_t* ranks2, const int64_t* ties
     a.A = rk.A; a.theta = rk.theta; a.row_v = rk.row_v; a.d_nrows = nullptr; a.n_rows = V;
     a.T = std::max<int64_t>(T, 1); a.tiesum = tiesum; a.ranks2 = ranks2; a.perms = perms;
     a.G = sn.G; a.gstride = sn.gstride; a.info = sn.info; a.tile_flags = sn.flags;
-    a.M = M; a.n_snp_tiles = sn.n_snp_tiles; a.K = K; a.tiles_per_range = 64;
+    a.M = M; a.n_snp_tiles = sn.n_snp_tiles; a.K = K; a.tiles_per_range = trait_range(v, V);
     a.hits = nullptr; a.counts = (unsigned long long*)counts;
     a.minp_bits = min_p ? minp : nullptr;
     set_levels(&a, p_cs, n_thr);

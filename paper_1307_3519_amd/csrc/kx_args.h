@@ -73,7 +73,11 @@ struct TiledArgs {
     int ks;              // k-steps of both operands (even)
 };
 
-// candidate entry form flag: column values are (Y, Z) of DIAG or (D1, D2)
+// candidate entry flags (high bits of the SNP word): column values are
+// (D1, D2) of the PLAIN form, else (Y, Z) of DIAG; kCandZs: the DIAG Z column
+// carries the per-SNP scale q (Z = q D2, see diag_zscale)
 constexpr uint32_t kCandPlain = 0x80000000u;
+constexpr uint32_t kCandZs = 0x40000000u;
+constexpr uint32_t kCandSnp = 0x3FFFFFFFu;
 
 }  // namespace kx

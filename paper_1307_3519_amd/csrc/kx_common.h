@@ -36,6 +36,25 @@ __host__ __device__ inline int snp_df(const SnpInfo& s) {
     return ne > 0 ? ne - 1 : 0;
 }
 
+// Scale of the fp16 DIAG screen's second column: q = sqrt(wz / wy) rounded
+// up to an fp16 value, so that with Z = q D2 the screen reads
+// f / wy <= Y^2 + Z^2 (two VALU operations per pair).  Z stays exact: the
+// partial sums of q * D2 have at most 11 + 13 significant bits while
+// sum_k |c_k| < 2^13 (K <= 128).  0 when wy = 0 (a SNP without groups 0
+// and 1, which is monomorphic and never screened in).
+__device__ inline float diag_zscale(const SnpInfo& s) {
+    if (!(s.wy > 0.0f) || !(s.wz > 0.0f)) return 0.0f;
+    const double x = sqrt((double)s.wz / (double)s.wy);
+    _Float16 h = (_Float16)x;
+    if ((double)h < x) {
+        uint16_t b;
+        __builtin_memcpy(&b, &h, 2);
+        ++b;                                   // next fp16 up (x > 0, finite)
+        __builtin_memcpy(&h, &b, 2);
+    }
+    return (float)h;
+}
+
 // Hit record, identical layout to krux_hit of the C ABI.
 struct HitRec {
     int32_t trait;

@@ -10,8 +10,8 @@ __global__ __launch_bounds__(256) void scan_candidates(ScanArgs a) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const uint4 e = a.cand[i];
-        eval_candidate(a, (int64_t)e.x, (int64_t)(e.y & ~kCandPlain), __uint_as_float(e.z),
-                       __uint_as_float(e.w), (e.y & kCandPlain) != 0);
+        eval_candidate(a, (int64_t)e.x, (int64_t)(e.y & kCandSnp), __uint_as_float(e.z),
+                       __uint_as_float(e.w), e.y & ~kCandSnp);
     }
 }
 

@@ -164,17 +164,23 @@ __device__ inline void emit_full(const ScanArgs& a, int64_t v, int64_t m, double
 // from its two exact MFMA column values: (Y, Z) of the DIAG form or
 // (D1, D2) of the PLAIN form; D0 = -D1 - D2.
 __device__ inline void eval_candidate(const ScanArgs& a, int64_t row, int64_t m, float y,
-                                      float z, bool plain) {
+                                      float z, uint32_t flags) {
     const SnpInfo inf = a.info[m];
     const int64_t v = a.row_v[row];
     if (v < 0) return;                // padding row of a partial tile
     int64_t D1, D2;
-    if (plain) {
+    if (flags & kCandPlain) {
         D1 = (int64_t)y;
         D2 = (int64_t)z;
     } else {
         const int64_t Y = (int64_t)y;
-        D2 = (int64_t)z;
+        if (flags & kCandZs) {
+            // z = q D2 exactly; the quotient is an integer
+            const float q = diag_zscale(inf);
+            D2 = q > 0.0f ? (int64_t)rint((double)z / (double)q) : 0;
+        } else {
+            D2 = (int64_t)z;
+        }
         D1 = inf.cy1 ? (Y - (int64_t)inf.cy2 * D2) / inf.cy1 : 0;
     }
     const int64_t D0 = -D1 - D2;
@@ -187,8 +193,8 @@ __device__ inline void eval_candidate(const ScanArgs& a, int64_t row, int64_t m,
 // the scan loop.
 __device__ __attribute__((noinline)) void eval_candidate_fallback(const ScanArgs& a, int64_t row,
                                                                    int64_t m, float y, float z,
-                                                                   bool plain) {
-    eval_candidate(a, row, m, y, z, plain);
+                                                                   uint32_t flags) {
+    eval_candidate(a, row, m, y, z, flags);
 }
 
 // Screened pairs are staged per wave in LDS and copied to the global
@@ -208,9 +214,9 @@ __device__ inline void flush_stage(const ScanArgs& a, const ScanArgs* a_lds, uin
         if ((int64_t)idx < a.cand_cap) {
             a.cand[idx] = e;
         } else {
-            eval_candidate_fallback(*a_lds, (int64_t)e.x, (int64_t)(e.y & ~kCandPlain),
+            eval_candidate_fallback(*a_lds, (int64_t)e.x, (int64_t)(e.y & kCandSnp),
                                     __uint_as_float(e.z), __uint_as_float(e.w),
-                                    (e.y & kCandPlain) != 0);
+                                    e.y & ~kCandSnp);
         }
     }
     sn = 0;
@@ -220,7 +226,7 @@ __device__ inline void flush_stage(const ScanArgs& a, const ScanArgs* a_lds, uin
 // Called by all lanes of a wave (uniform control flow); `cand` per lane.
 __device__ inline void stage_candidates(const ScanArgs& a, const ScanArgs* a_lds, uint4* stage,
                                         int& sn, int lane, bool cand, int64_t row, int64_t m,
-                                        float y, float z, bool plain) {
+                                        float y, float z, uint32_t flags) {
     const unsigned long long msk = __ballot(cand);
     if (!msk) return;
     const int n = __popcll(msk);
@@ -228,7 +234,7 @@ __device__ inline void stage_candidates(const ScanArgs& a, const ScanArgs* a_lds
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     if (cand)
         stage[sn + __popcll(msk & lt)] =
-            make_uint4((uint32_t)row, (uint32_t)m | (plain ? kCandPlain : 0u),
+            make_uint4((uint32_t)row, (uint32_t)m | flags,
                        __float_as_uint(y), __float_as_uint(z));
     sn += n;
     __builtin_amdgcn_wave_barrier();
@@ -340,6 +346,9 @@ void scan_kernel(ScanArgs a) {
     constexpr int NC = FORM == MISS3 ? 3 : 2;
     constexpr bool QUEUE = FORM == MISS3;
     constexpr bool RING = PF == 3 && MODE == SCREEN && FORM != MISS3;
+    // fp16 DIAG: second column scaled by q (diag_zscale), screen Y^2 + Z^2
+    constexpr bool ZS = E == F16 && FORM == DIAG;
+    constexpr uint32_t kDiagFlags = ZS ? kCandZs : 0u;
 
     __shared__ int2 s_queue[QUEUE ? kWavesPerBlock : 1][QUEUE ? kQueueCap : 1];
     __shared__ uint4 s_stage[MODE == SCREEN ? kWavesPerBlock : 1][kStageCap];
@@ -394,7 +403,7 @@ void scan_kernel(ScanArgs a) {
         float cv[NC][3];
         if constexpr (FORM == DIAG) {
             cv[0][0] = 0.f; cv[0][1] = inf.cy1; cv[0][2] = inf.cy2;
-            cv[1][0] = 0.f; cv[1][1] = 0.f; cv[1][2] = 1.f;
+            cv[1][0] = 0.f; cv[1][1] = 0.f; cv[1][2] = ZS ? diag_zscale(inf) : 1.f;
         } else if (FORM == PLAIN) {
             cv[0][0] = 0.f; cv[0][1] = 1.f; cv[0][2] = 0.f;
             cv[1][0] = 0.f; cv[1][1] = 0.f; cv[1][2] = 1.f;
@@ -430,6 +439,8 @@ void scan_kernel(ScanArgs a) {
         const float qn0 = (float)inf.nmiss * inf.n0, qn1 = (float)inf.nmiss * inf.n1,
                     qn2 = (float)inf.nmiss * inf.n2;
         const float delta = (float)(cube_minus(a.K) - cube_minus(kp));
+        // ZS: candidate iff Y^2 + Z^2 > theta * invc (inf when wy * fac = 0)
+        const float invc = ZS ? 1.0f / (inf.wy * fac) : 0.0f;
 
         const int64_t t0 = rg * a.tiles_per_range;
         const int64_t t1 = (t0 + a.tiles_per_range < n_tiles) ? t0 + a.tiles_per_range : n_tiles;
@@ -439,7 +450,10 @@ void scan_kernel(ScanArgs a) {
         // theta is the smallest threshold of the tile's 32 traits, which
         // can only admit more candidates than the per-trait one
         auto screen = [&](const acc_t (&acc)[NC], const float th, int r) -> float {
-            if constexpr (FORM == DIAG) {
+            if constexpr (ZS) {
+                float y = T_::val(acc[0], r), z = T_::val(acc[1], r);
+                return fmaf(y, y, z * z) - th * invc;
+            } else if constexpr (FORM == DIAG) {
                 float y = T_::val(acc[0], r), z = T_::val(acc[1], r);
                 return fmaf(wy * y, y, fmaf(wz * z, z, -th));
             } else if constexpr (FORM == PLAIN) {
@@ -479,18 +493,28 @@ void scan_kernel(ScanArgs a) {
                 }
                 if constexpr (FORM == DIAG)
                     stage_candidates(a, &s_args, stage, sn, lane, cand, row, m, T_::val(acc[0], r),
-                                     T_::val(acc[1], r), false);
+                                     T_::val(acc[1], r), kDiagFlags);
                 else if constexpr (FORM == PLAIN)
                     stage_candidates(a, &s_args, stage, sn, lane, cand, row, m, T_::val(acc[0], r),
-                                     T_::val(acc[1], r), true);
+                                     T_::val(acc[1], r), kCandPlain);
                 else   // complete SNP in a MISS3 tile: D0 = -D1 - D2
                     stage_candidates(a, &s_args, stage, sn, lane, cand, row, m, T_::val(acc[1], r),
-                                     T_::val(acc[2], r), true);
+                                     T_::val(acc[2], r), kCandPlain);
             }
             if (QUEUE && qn) drain<MODE>(a, queue, qn, qbuf, lane);
         };
         // largest screen value of a tile (VALU only, no branches)
         auto screen_max = [&](const acc_t (&acc)[NC], const float th) -> float {
+            if constexpr (ZS) {
+                float smax = 0.0f;
+#pragma unroll
+                for (int r = 0; r < 16; r += 2) {
+                    const float y0 = T_::val(acc[0], r), z0 = T_::val(acc[1], r);
+                    const float y1 = T_::val(acc[0], r + 1), z1 = T_::val(acc[1], r + 1);
+                    smax = fmaxf(smax, fmaxf(fmaf(y0, y0, z0 * z0), fmaf(y1, y1, z1 * z1)));
+                }
+                return smax - th * invc;
+            }
             float gmax = -__builtin_inff();
 #pragma unroll
             for (int r = 0; r < 16; r += 2)

@@ -238,11 +238,11 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
                             cand = cand && !lk.miss;
                         }
                         if constexpr (FORM == DIAG)
-                            stage_candidates(a, &s_args, stage, sn, lane, cand, row, m, v0, v1, false);
+                            stage_candidates(a, &s_args, stage, sn, lane, cand, row, m, v0, v1, 0u);
                         else if constexpr (FORM == PLAIN)
-                            stage_candidates(a, &s_args, stage, sn, lane, cand, row, m, v0, v1, true);
+                            stage_candidates(a, &s_args, stage, sn, lane, cand, row, m, v0, v1, kCandPlain);
                         else
-                            stage_candidates(a, &s_args, stage, sn, lane, cand, row, m, v1, v2, true);
+                            stage_candidates(a, &s_args, stage, sn, lane, cand, row, m, v1, v2, kCandPlain);
                     }
                     if (QUEUE && qn) drain<MODE>(a, queue, qn, qbuf, lane);
                 } else if constexpr (FORM == MISS3) {
