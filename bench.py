@@ -1,15 +1,28 @@
 #!/usr/bin/env python3
 """Benchmark of the Kruskal-Wallis SNP x trait scan on one MI355X.
 
-A step is one pass of the whole path over the paper-scale workload with the
-inputs resident in HBM: per-trait ranking (krux_rank) and the test of every
-trait against every SNP (krux_test, HITS mode with the per-trait minimum p):
-genotype packing, the fused fp16 MFMA rank-sum GEMM with its statistic /
-threshold / p-value / compaction epilogue, hit sorting and the min-p passes.
+A step is one pass of the whole path over one workload with the inputs
+resident in HBM: per-trait ranking (krux_rank) and the test of every trait
+against every SNP (krux_test / krux_permute / krux_test_batched): genotype
+packing, the fused MFMA rank-sum GEMM with its statistic / threshold /
+p-value / compaction epilogue, exact evaluation of screened pairs, hit
+sorting and the per-trait minimum-p passes.
 
-Workload: 102 samples, 20,000 log-normal traits with 5% forced ties,
-500,000 Hardy-Weinberg SNPs (MAF U[0.05, 0.5]), 500 planted pairs, hits at
-p < 1e-5 (synthetic stand-in for the paper's human blood data set).
+Workloads (--workload; seeded synthetic data shaped like the paper's
+102-sample human blood data set):
+  paper_scale_hits (default)  K=102, 20,000 log-normal traits with 5% forced
+      ties, 500,000 Hardy-Weinberg SNPs (MAF U[0.05, 0.5]), 500 planted pairs;
+      sorted hits at p < 1e-5 plus the per-trait minimum p; fp16 path, beside
+      the int8 path and the fp64-GEMM comparator on the same inputs
+  precision_K500   K=500, 20,000 traits, 100,000 SNPs; hits at p < 1e-5 through
+      the fp16, int8 (byte-split ranks) and fp64-GEMM paths, plus group rank
+      sums of a slice compared bit for bit across the three
+  permutations     K=102, 20,000 traits, 100,000 SNPs, 200 permutations of the
+      samples; per-permutation hit counts at p < {1e-4, 1e-5, 1e-6} and the
+      per-(permutation, trait) minimum p
+  cohorts_missing  8 cohorts, K in {48, ..., 1000}, 5,000-20,000 traits each,
+      one 200,000-SNP panel with 2% missing genotypes; hits at p < 1e-5 per
+      cohort
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -23,6 +36,7 @@ METRIC = "SNP-trait pairs/sec at N=102 (exact MFMA vs FP64 GEMM), % MFMA peak"
 PEAK_FP16_TFLOPS = 2500.0      # MI355X dense fp16 MFMA
 PEAK_INT8_TOPS = 5000.0        # MI355X dense int8 MFMA
 PEAK_FP64_TFLOPS = 78.6        # MI355X fp64 MFMA
+DATA = "synthetic (seeded generators shaped like the paper's 102-sample blood data)"
 
 
 def log(*a):
@@ -54,13 +68,317 @@ def measured_traffic():
         return None
 
 
+class Runner:
+    """Warmup + timed steps with the fused-kernel timer."""
+
+    def __init__(self, ctx, torch):
+        self.ctx = ctx
+        self.torch = torch
+
+    def run(self, step, steps, warmup):
+        torch = self.torch
+        res = None
+        for _ in range(warmup):
+            res = step()
+        torch.cuda.synchronize()
+        self.ctx.timer_start()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res = step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kms, kn = self.ctx.timer_read()
+        # per step: all timed scan launches (two per main pass)
+        return (t1 - t0) * 1e3 / steps, res, kms / max(steps, 1), kn
+
+
+def same_hits(a, b):
+    import numpy as np
+    return bool(a[0] == b[0] and np.array_equal(a[1]["trait"], b[1]["trait"])
+                and np.array_equal(a[1]["snp"], b[1]["snp"]))
+
+
+def base_line(args, metric, value, unit, ms, dtype, config):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": dtype, "data": DATA, "config": config}
+
+
+def roofline(kernel, pairs, flops_per_pair, kern_ms, peak, unit, traffic=None):
+    achieved = pairs * flops_per_pair / (kern_ms / 1e3) / 1e12
+    return {"bound": "mfma", "kernel": kernel, "achieved": achieved, "peak": peak,
+            "unit": unit, "frac": achieved / peak, "traffic": traffic, "kernel_ms": kern_ms,
+            "flops_per_pair": flops_per_pair}
+
+
+def oracle_baseline(args, T, n_total, label, run_sample):
+    """Times the oracle on a bounded prefix of the SNPs: run_sample(n) scans
+    all traits against the first n SNPs."""
+    import oracle
+    probe = max(1, min(n_total, 200))
+    t0 = time.perf_counter()
+    run_sample(probe)
+    rate = T * probe / (time.perf_counter() - t0)
+    n_snp = int(min(n_total, max(probe, args.cpu_seconds * rate / max(T, 1))))
+    log("oracle baseline: %d traits x %d SNPs (probe %.3e pairs/s)" % (T, n_snp, rate))
+    t0 = time.perf_counter()
+    run_sample(n_snp)
+    dt = time.perf_counter() - t0
+    log("oracle: %.3e pairs/s on %d threads" % (T * n_snp / dt, oracle.num_threads()))
+    return {"value": T * n_snp / dt, "unit": "pairs/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "all %d traits x the first %d of %d SNPs (%s), %.1f s"
+                      % (T, n_snp, n_total, label, dt)}
+
+
+# ---------------------------------------------------------------- workloads
+def paper_scale_hits(args, ctx, torch, np, datagen, krux):
+    wl = dict(datagen.WORKLOADS[2])
+    T = args.T or wl["T"]
+    M = args.M or wl["M"]
+    K = wl["K"]
+    p_c = 1e-5
+    log("generating workload K=%d T=%d M=%d" % (K, T, M))
+    t0 = time.time()
+    w = datagen.make_workload(2, T=T, M=M)
+    log("generated in %.1fs" % (time.time() - t0))
+    x = torch.from_numpy(w["expr"]).cuda()
+    g = torch.from_numpy(w["geno"]).cuda()
+    cap = 1 << 17          # hit-list capacity (about 2.4e4 hits are expected)
+    bufs = {}
+    runner = Runner(ctx, torch)
+
+    def step_for(prec):
+        def step():
+            r, ts, _ = ctx.rank(x)
+            res = ctx.test(r, ts, g, p_c=p_c, mode="hits", precision=prec, hit_capacity=cap,
+                           min_p=not args.no_minp, out=bufs.get(prec))
+            bufs[prec] = res
+            return res
+        return step
+
+    log("fp16 path: %d warmup + %d timed steps" % (args.warmup, args.steps))
+    ms, res, kern_ms, kn = runner.run(step_for("fp16"), args.steps, args.warmup)
+    pairs = float(T) * float(M)
+    value = pairs / (ms / 1e3)
+    hits16 = krux.unpack_hits(res)
+    planted = set(map(tuple, w["planted"][:, :2].tolist()))
+    found = set(zip(hits16[1]["trait"].tolist(), hits16[1]["snp"].tolist()))
+    log("fp16: %.3f ms/step, %.3e pairs/s, hits %d, planted recovered %d/%d"
+        % (ms, value, hits16[0], len(planted & found), len(planted)))
+    flops_per_pair = 2 * K * 2          # two genotype classes of a K-long contraction
+    out = base_line(args, METRIC, value, "pairs/s", ms, "f16", {
+        "workload": "paper_scale_hits", "K": K, "T": T, "M": M,
+        "planted": int(w["planted"].shape[0]), "p_c": p_c,
+        "outputs": "sorted hit list (p < 1e-5)" + ("" if args.no_minp else " + per-trait min p")})
+    rl = roofline("scan_kernel<F16, KS=7, DIAG, SCREEN>", pairs, flops_per_pair, kern_ms,
+                  PEAK_FP16_TFLOPS, "TFLOP/s", measured_traffic())
+    rl["kernel_launches"] = kn
+    rl["kernel_ms_note"] = ("main pass per step: the complete-SNP kernel plus the "
+                            "missing-genotype kernel, which returns at once here")
+    out["roofline"] = rl
+    out["n_hits"] = hits16[0]
+    out["planted_recovered"] = [len(planted & found), len(planted)]
+
+    if not args.no_compare:
+        log("fp64 GEMM comparator: 1 warmup + 2 timed steps")
+        ms64, res64, _, _ = runner.run(step_for("fp64"), 2, 1)
+        same = same_hits(krux.unpack_hits(res64), hits16)
+        log("fp64: %.3f ms/step, %.3e pairs/s, identical hits %s" % (ms64, pairs / (ms64 / 1e3), same))
+        out["fp64_gemm"] = {"value": pairs / (ms64 / 1e3), "unit": "pairs/s", "ms_per_step": ms64,
+                            "identical_hits": same,
+                            "speedup_of_fp16": (pairs / (ms / 1e3)) / (pairs / (ms64 / 1e3)),
+                            "peak_fp64_tflops": PEAK_FP64_TFLOPS}
+        n8 = max(3, args.steps // 2)
+        log("int8 path: 1 warmup + %d timed steps" % n8)
+        ms8, res8, k8ms, _ = runner.run(step_for("int8"), n8, 1)
+        same8 = same_hits(krux.unpack_hits(res8), hits16)
+        out["int8"] = {"value": pairs / (ms8 / 1e3), "unit": "pairs/s", "ms_per_step": ms8,
+                       "kernel_ms": k8ms,
+                       "kernel_tops": pairs * flops_per_pair / (k8ms / 1e3) / 1e12,
+                       "frac_of_int8_peak": pairs * flops_per_pair / (k8ms / 1e3) / 1e12 / PEAK_INT8_TOPS,
+                       "identical_hits": same8}
+        log("int8: %.3f ms/step, identical hits %s" % (ms8, same8))
+
+    if not args.no_cpu:
+        import oracle
+        out["cpu_baseline"] = oracle_baseline(
+            args, T, M, "hits at p<1e-5 + per-trait min p",
+            lambda n: oracle.scan(w["expr"], w["geno"][:n], p_cs=(p_c,), hits=True, min_p=True))
+    out["paper_context"] = {"kruX_matlab_single_cpu_pairs_per_s": 4.2e6,
+                            "note": "derived from the paper's ~2,500 s for 19,610 x 530,222 "
+                                    "pairs on one CPU; another machine and method, context only"}
+    return out
+
+
+def precision_k500(args, ctx, torch, np, datagen, krux):
+    wl = dict(datagen.WORKLOADS[3])
+    T = args.T or wl["T"]
+    M = args.M or wl["M"]
+    K = wl["K"]
+    p_c = 1e-5
+    log("generating workload K=%d T=%d M=%d" % (K, T, M))
+    w = datagen.make_workload(3, T=T, M=M)
+    x = torch.from_numpy(w["expr"]).cuda()
+    g = torch.from_numpy(w["geno"]).cuda()
+    runner = Runner(ctx, torch)
+    bufs = {}
+
+    def step_for(prec):
+        def step():
+            r, ts, _ = ctx.rank(x)
+            res = ctx.test(r, ts, g, p_c=p_c, mode="hits", precision=prec, hit_capacity=1 << 17,
+                           min_p=True, out=bufs.get(prec))
+            bufs[prec] = res
+            return res
+        return step
+
+    pairs = float(T) * float(M)
+    flops_per_pair = 4 * K
+    res = {}
+    for prec, steps, warm in (("fp16", args.steps, args.warmup), ("int8", args.steps, args.warmup),
+                              ("fp64", 2, 1)):
+        log("%s: %d warmup + %d timed steps" % (prec, warm, steps))
+        ms, r, kms, _ = runner.run(step_for(prec), steps, warm)
+        res[prec] = (ms, krux.unpack_hits(r), kms, r["min_p"].cpu().numpy())
+        log("%s: %.3f ms/step, %.3e pairs/s, hits %d" % (prec, ms, pairs / (ms / 1e3), res[prec][1][0]))
+    ms = res["fp16"][0]
+    out = base_line(args, "SNP-trait pairs/sec at N=500, three precisions", pairs / (ms / 1e3),
+                    "pairs/s", ms, "f16", {"workload": "precision_K500", "K": K, "T": T, "M": M,
+                                           "p_c": p_c, "outputs": "hits + per-trait min p"})
+    out["roofline"] = roofline("scan_tiled<F16, PLAIN, SCREEN>", pairs, flops_per_pair,
+                               res["fp16"][2], PEAK_FP16_TFLOPS, "TFLOP/s")
+    for prec, peak in (("int8", PEAK_INT8_TOPS), ("fp64", PEAK_FP64_TFLOPS)):
+        ms_p, hits_p, kms_p, mp_p = res[prec]
+        d = {"value": pairs / (ms_p / 1e3), "unit": "pairs/s", "ms_per_step": ms_p,
+             "identical_hits": same_hits(hits_p, res["fp16"][1]),
+             "identical_min_p": bool(np.array_equal(mp_p, res["fp16"][3]))}
+        if prec == "int8":
+            d["kernel_ms"] = kms_p
+            d["frac_of_int8_peak"] = pairs * flops_per_pair / (kms_p / 1e3) / 1e12 / peak
+        out[prec] = d
+    # group rank sums of a slice, bit for bit across the three precisions
+    ms_slice = min(M, 2000)
+    r, ts, _ = ctx.rank(x)
+    sums = {p: ctx.test(r, ts, g[:ms_slice], mode="sums", precision=p)["sums"].cpu().numpy()
+            for p in ("fp16", "int8", "fp64")}
+    out["sums_slice"] = {"traits": T, "snps": ms_slice,
+                         "fp16_eq_fp64": bool(np.array_equal(sums["fp16"], sums["fp64"])),
+                         "int8_eq_fp64": bool(np.array_equal(sums["int8"], sums["fp64"]))}
+    log("sums slice identical: %s" % out["sums_slice"])
+    if not args.no_cpu:
+        import oracle
+        out["cpu_baseline"] = oracle_baseline(
+            args, T, M, "hits at p<1e-5 + per-trait min p",
+            lambda n: oracle.scan(w["expr"], w["geno"][:n], p_cs=(p_c,), hits=True, min_p=True))
+    return out
+
+
+def permutations(args, ctx, torch, np, datagen, krux):
+    wl = dict(datagen.WORKLOADS[4])
+    T = args.T or wl["T"]
+    M = args.M or wl["M"]
+    K = wl["K"]
+    P = args.P or wl["P"]
+    p_cs = (1e-4, 1e-5, 1e-6)
+    log("generating workload K=%d T=%d M=%d P=%d" % (K, T, M, P))
+    w = datagen.make_workload(4, T=T, M=M, P=P)
+    x = torch.from_numpy(w["expr"]).cuda()
+    g = torch.from_numpy(w["geno"]).cuda()
+    perms = torch.from_numpy(w["perms"]).cuda()
+    runner = Runner(ctx, torch)
+    buf = {}
+
+    def step():
+        r, ts, _ = ctx.rank(x)
+        res = ctx.permute(r, ts, g, perms, p_cs=p_cs, min_p=True, out=buf.get("o"))
+        buf["o"] = res
+        return res
+
+    steps = max(1, min(args.steps, 3))
+    log("permutations: 1 warmup + %d timed steps" % steps)
+    ms, res, kms, _ = runner.run(step, steps, 1)
+    pairs = float(P) * T * M
+    counts = res["counts"].cpu().numpy()
+    log("permute: %.1f ms/step, %.3e pairs/s, mean counts %s" % (ms, pairs / (ms / 1e3),
+                                                                 counts.mean(axis=0)))
+    out = base_line(args, "permuted SNP-trait pairs/sec at N=102", pairs / (ms / 1e3), "pairs/s",
+                    ms, "f16", {"workload": "permutations", "K": K, "T": T, "M": M, "P": P,
+                                "p_c": list(p_cs),
+                                "outputs": "per-permutation counts + per-(permutation, trait) min p"})
+    out["steps"] = steps
+    out["warmup"] = 1
+    out["roofline"] = roofline("scan_kernel<F16, KS=7, DIAG, SCREEN>", pairs, 4 * K, kms,
+                               PEAK_FP16_TFLOPS, "TFLOP/s")
+    out["mean_counts"] = counts.mean(axis=0).tolist()
+    if not args.no_cpu:
+        import oracle
+        out["cpu_baseline"] = oracle_baseline(
+            args, T, M, "one permutation, counts + min p",
+            lambda n: oracle.scan(w["expr"], w["geno"][:n], p_cs=p_cs, perm=w["perms"][0],
+                                  min_p=True))
+    return out
+
+
+def cohorts_missing(args, ctx, torch, np, datagen, krux):
+    M = args.M or datagen.WORKLOADS[5]["M"]
+    p_c = 1e-5
+    log("generating 8 cohorts, M=%d" % M)
+    t0 = time.time()
+    cs = datagen.make_cohorts(M=M, T_scale=(args.T / 12500.0) if args.T else 1.0)
+    log("generated in %.1fs: K %s, T %s" % (time.time() - t0, [c["K"] for c in cs],
+                                            [c["T"] for c in cs]))
+    dev = [dict(x=torch.from_numpy(c["expr"]).cuda(), geno=torch.from_numpy(c["geno"]).cuda())
+           for c in cs]
+    runner = Runner(ctx, torch)
+
+    def step():
+        batch = []
+        for d in dev:
+            r, ts, _ = ctx.rank(d["x"])
+            batch.append(dict(ranks2=r, tiesum=ts, geno=d["geno"]))
+        return ctx.test_batched(batch, M, p_c=p_c, precision="fp16", hit_capacity=1 << 16,
+                                min_p=True)
+
+    steps = max(1, min(args.steps, 5))
+    log("cohorts: 1 warmup + %d timed steps" % steps)
+    ms, res, kms, _ = runner.run(step, steps, 1)
+    pairs = float(sum(c["T"] for c in cs)) * M
+    flops = float(sum(c["T"] * 4 * c["K"] for c in cs)) * M
+    n_hits = [krux.unpack_hits(r)[0] for r in res]
+    log("cohorts: %.1f ms/step, %.3e pairs/s, hits %s" % (ms, pairs / (ms / 1e3), n_hits))
+    out = base_line(args, "SNP-trait pairs/sec over uneven cohorts", pairs / (ms / 1e3), "pairs/s",
+                    ms, "f16", {"workload": "cohorts_missing", "K": [c["K"] for c in cs],
+                                "T": [c["T"] for c in cs], "M": M, "p_missing": 0.02, "p_c": p_c,
+                                "outputs": "hits + per-trait min p per cohort"})
+    out["steps"] = steps
+    out["warmup"] = 1
+    out["roofline"] = roofline("scan kernels of all cohorts", pairs, flops / pairs, kms,
+                               PEAK_FP16_TFLOPS, "TFLOP/s")
+    out["n_hits"] = n_hits
+    if not args.no_cpu:
+        import oracle
+        c0 = cs[2]          # the K = 102 cohort
+        out["cpu_baseline"] = oracle_baseline(
+            args, c0["T"], M, "cohort K=%d, hits + min p" % c0["K"],
+            lambda n: oracle.scan(c0["expr"], c0["geno"][:n], p_cs=(p_c,), hits=True, min_p=True))
+    return out
+
+
+WORKLOADS = {"paper_scale_hits": paper_scale_hits, "precision_K500": precision_k500,
+             "permutations": permutations, "cohorts_missing": cohorts_missing}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="paper_scale_hits")
     ap.add_argument("--T", type=int, default=None, help="override trait count")
     ap.add_argument("--M", type=int, default=None, help="override SNP count")
+    ap.add_argument("--P", type=int, default=None, help="override permutation count")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip the fp64 / int8 paths")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -81,17 +399,6 @@ def main():
     import torch
     from paper_1307_3519_amd import datagen, krux
 
-    wl = dict(datagen.WORKLOADS[2])
-    T = args.T or wl["T"]
-    M = args.M or wl["M"]
-    K = wl["K"]
-    p_c = 1e-5
-    log("generating workload K=%d T=%d M=%d" % (K, T, M))
-    t0 = time.time()
-    w = datagen.make_workload(2, T=T, M=M)
-    log("generated in %.1fs" % (time.time() - t0))
-    x = torch.from_numpy(w["expr"]).cuda()
-    g = torch.from_numpy(w["geno"]).cuda()
     ctx = krux.Context(0)
     if args.copy_probe:
         src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
@@ -99,114 +406,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    cap = 1 << 17          # hit-list capacity (about 2.4e4 hits are expected)
-    bufs = {}
-
-    def step(prec):
-        r, ts, _ = ctx.rank(x)
-        res = ctx.test(r, ts, g, p_c=p_c, mode="hits", precision=prec, hit_capacity=cap,
-                       min_p=not args.no_minp, out=bufs)
-        bufs.update(res)
-        return res
-
-    def run(prec, steps, warmup, timed_kernel=False):
-        for _ in range(warmup):
-            step(prec)
-        torch.cuda.synchronize()
-        if timed_kernel:
-            ctx.timer_start()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            res = step(prec)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        kern = ctx.timer_read() if timed_kernel else None
-        return (t1 - t0) * 1e3 / steps, res, kern
-
-    log("fp16 path: %d warmup + %d timed steps" % (args.warmup, args.steps))
-    ms, res, (kms, kn) = run("fp16", args.steps, args.warmup, timed_kernel=True)
-    pairs = float(T) * float(M)
-    value = pairs / (ms / 1e3)
-    n_hits, hits = krux.unpack_hits(res)
-    planted = set(map(tuple, w["planted"][:, :2].tolist()))
-    found = set(zip(hits["trait"].tolist(), hits["snp"].tolist()))
-    log("fp16: %.3f ms/step, %.3e pairs/s, hits %d, planted recovered %d/%d"
-        % (ms, value, n_hits, len(planted & found), len(planted)))
-    kern_ms = kms / max(kn, 1)
-    flops_per_pair = 2 * K * 2          # two genotype classes of a K-long contraction
-    achieved = pairs * flops_per_pair / (kern_ms / 1e3) / 1e12
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "pairs/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f16",
-        "data": "synthetic (seeded generators shaped like the paper's 102-sample blood data)",
-        "config": {"workload": "paper_scale_hits", "K": K, "T": T, "M": M,
-                   "planted": int(w["planted"].shape[0]), "p_c": p_c,
-                   "outputs": "sorted hit list (p < 1e-5)" + ("" if args.no_minp else
-                                                                " + per-trait min p")},
-        "roofline": {"bound": "mfma", "kernel": "scan_kernel<F16, KS=7, DIAG, SCREEN>",
-                     "achieved": achieved, "peak": PEAK_FP16_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP16_TFLOPS, "traffic": measured_traffic(),
-                     "kernel_ms": kern_ms, "kernel_launches": kn,
-                     "flops_per_pair": flops_per_pair},
-        "n_hits": n_hits,
-        "planted_recovered": [len(planted & found), len(planted)],
-    }
-
-    if not args.no_compare:
-        log("fp64 GEMM comparator: 1 warmup + 2 timed steps")
-        ms64, res64, _ = run("fp64", 2, 1)
-        n64, h64 = krux.unpack_hits(res64)
-        same = (n64 == n_hits and np.array_equal(h64["trait"], hits["trait"])
-                and np.array_equal(h64["snp"], hits["snp"]))
-        log("fp64: %.3f ms/step, %.3e pairs/s, identical hits %s" % (ms64, pairs / (ms64 / 1e3), same))
-        out["fp64_gemm"] = {"value": pairs / (ms64 / 1e3), "unit": "pairs/s", "ms_per_step": ms64,
-                            "identical_hits": bool(same),
-                            "speedup_of_fp16": (pairs / (ms / 1e3)) / (pairs / (ms64 / 1e3)),
-                            "peak_fp64_tflops": PEAK_FP64_TFLOPS}
-        log("int8 path: 1 warmup + %d timed steps" % max(3, args.steps // 2))
-        ms8, res8, (k8, n8) = run("int8", max(3, args.steps // 2), 1, timed_kernel=True)
-        n8h, h8 = krux.unpack_hits(res8)
-        same8 = (n8h == n_hits and np.array_equal(h8["trait"], hits["trait"])
-                 and np.array_equal(h8["snp"], hits["snp"]))
-        k8ms = k8 / max(n8, 1)
-        out["int8"] = {"value": pairs / (ms8 / 1e3), "unit": "pairs/s", "ms_per_step": ms8,
-                       "kernel_ms": k8ms,
-                       "kernel_tops": pairs * flops_per_pair / (k8ms / 1e3) / 1e12,
-                       "frac_of_int8_peak": pairs * flops_per_pair / (k8ms / 1e3) / 1e12 / PEAK_INT8_TOPS,
-                       "identical_hits": bool(same8)}
-        log("int8: %.3f ms/step, identical hits %s" % (ms8, same8))
-
-    if not args.no_cpu:
-        import oracle
-        xs, gs = w["expr"], w["geno"]
-        probe = 200
-        t0 = time.perf_counter()
-        oracle.scan(xs, gs[:probe], p_cs=(p_c,), hits=True, min_p=True)
-        dt = time.perf_counter() - t0
-        rate = T * probe / dt
-        n_snp = int(min(M, max(probe, args.cpu_seconds * rate / T)))
-        log("oracle baseline: %d traits x %d SNPs (probe rate %.3e pairs/s)" % (T, n_snp, rate))
-        t0 = time.perf_counter()
-        oracle.scan(xs, gs[:n_snp], p_cs=(p_c,), hits=True, min_p=True)
-        dt = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": T * n_snp / dt, "unit": "pairs/s",
-                               "cores": oracle.num_threads(), "kind": "oracle",
-                               "sample": "all %d traits x the first %d of %d SNPs (hits at "
-                                         "p<1e-5 + per-trait min p), %.1f s" % (T, n_snp, M, dt)}
-        log("oracle: %.3e pairs/s on %d threads" % (T * n_snp / dt, oracle.num_threads()))
-
-    out["paper_context"] = {"kruX_matlab_single_cpu_pairs_per_s": 4.2e6,
-                            "note": "derived from the paper's ~2,500 s for 19,610 x 530,222 "
-                                    "pairs on one CPU; another machine and method, context only"}
+    out = WORKLOADS[args.workload](args, ctx, torch, np, datagen, krux)
     ctx.close()
     print(json.dumps(out), flush=True)
 

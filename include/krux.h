@@ -170,12 +170,14 @@ krux_status krux_test_batched(krux_ctx* ctx, const krux_cohort* cohorts,
                               int32_t n_cohorts, int64_t M, double p_c,
                               int32_t precision, void* stream);
 
-/* Instrumentation of the fused scan kernel (the rank-sum GEMM with its
- * epilogue): after krux_timer_start, every launch of that kernel made by the
- * main pass of krux_test / krux_permute is bracketed by HIP events recorded on
- * the launch stream.  krux_timer_read synchronises those events, returns the
- * summed kernel time (host, ms) and the number of launches, and stops the
- * timer.  Meant for benchmarks; it adds two event records per launch. */
+/* Instrumentation of the fused scan kernels (the rank-sum GEMM with its
+ * epilogue): after krux_timer_start, each main pass of krux_test /
+ * krux_permute (one per cohort for krux_test_batched) brackets its two scan
+ * launches with HIP events on the launch stream: the complete-SNP kernel and
+ * the missing-genotype kernel (which returns at once when no SNP has a
+ * missing genotype).  krux_timer_read synchronises those events, returns the
+ * summed kernel time (host, ms) and the number of timed launches (two per
+ * main pass), and stops the timer.  Meant for benchmarks. */
 krux_status krux_timer_start(krux_ctx* ctx);
 krux_status krux_timer_read(krux_ctx* ctx, double* total_ms, int64_t* launches);
 

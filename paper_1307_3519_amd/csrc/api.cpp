@@ -90,7 +90,14 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Capacity of the screened-pair buffer (16 B per entry).  When a scan finds
 // more candidates than this, the extra ones are evaluated inside the scan.
-constexpr int64_t kCandCap = (int64_t)1 << 22;
+// Candidate buffer entries: sized for about four times the expected number of
+// screened pairs of a main pass (the screen level times the pair count), at
+// least 2^22 and at most 2^28 (4 GiB); pairs beyond it are evaluated in the
+// scan kernel itself.
+int64_t candidate_capacity(int64_t rows, int64_t M, double p_screen) {
+    const double want = 4.0 * (double)rows * (double)M * p_screen + (double)(1 << 20);
+    return (int64_t)std::min(std::max(want, (double)(1 << 22)), (double)(1LL << 28));
+}
 
 double host_pvalue(double H, int df) {
     if (df == 1) return std::erfc(std::sqrt(H / 2.0));
@@ -258,16 +265,32 @@ krux_status launch_scan(krux_ctx* c, const kx::ScanArgs& a, const Variant& v, co
 }
 
 // Trait tiles per work item of the SNP-stationary kernel.  Concurrent blocks
-// walk consecutive SNP blocks of one trait range, so the range's operand
-// slice is what every XCD's L2 (4 MB) holds: at most ~2.5 MB per range, and
-// at least two ranges so that the persistent grid's last round is short.
-int trait_range(const Variant& v, int64_t n_rows) {
+// walk consecutive SNP blocks of one trait range, so the operand slices of
+// the ranges in flight are what every XCD's L2 (4 MB) must hold: about
+// 1 + resident blocks / SNP blocks ranges are in flight, and together they
+// get ~2.5 MB.  At least two ranges, so that the persistent grid's last
+// round is short.
+int trait_range(const Variant& v, int64_t n_rows, int64_t n_snp_tiles, int n_cu) {
     const int64_t n_tiles = std::max<int64_t>(ceil_div(n_rows, kx::kTile), 1);
     const int64_t tile_bytes = (int64_t)v.ks * kx::kWave * 16;
-    int64_t ranges = ceil_div(n_tiles * tile_bytes, (int64_t)5 << 19);
+    const int64_t snp_blocks = std::max<int64_t>(ceil_div(n_snp_tiles, kx::kWavesPerBlock), 1);
+    const double in_flight = 1.0 + 2.0 * n_cu / (double)snp_blocks;   // 2 blocks per CU
+    const int64_t budget = std::max<int64_t>((int64_t)((double)(5 << 19) / in_flight), 64 << 10);
+    int64_t ranges = ceil_div(n_tiles * tile_bytes, budget);
     if (n_tiles >= 128) ranges = std::max<int64_t>(ranges, 2);
     const int64_t tpr = ceil_div(ceil_div(n_tiles, ranges), 2) * 2;
     return (int)std::min<int64_t>(tpr, 1 << 20);
+}
+
+// Pipeline of the SNP-stationary screen kernel.  Every wave reads each A
+// tile of its range from L2; when the operand is large (many trait ranges,
+// each shared by few blocks at a time) those reads dominate, and the block's
+// LDS ring, which reads a tile once per block, is faster (200 permutations x
+// 20,000 traits: 1.5x); for a few MB of operand the register double buffer
+// without block barriers is a few percent faster.
+int use_ring(const Variant& v, int64_t n_rows) {
+    const int64_t bytes = ceil_div(n_rows, kx::kTile) * (int64_t)v.ks * kx::kWave * 16;
+    return !v.tiled && bytes > ((int64_t)16 << 20) ? 1 : 0;
 }
 
 // Work items of one scan launch (an upper bound; the kernels stop early).
@@ -303,33 +326,40 @@ krux_status run_screen(krux_ctx* c, kx::ScanArgs a, const Variant& v, const Colu
     int grid = (int)std::min<int64_t>(items, (int64_t)INT32_MAX);
     // screened pairs go to the candidate buffer and are evaluated exactly after the scan
     krux_status s = KRUX_OK;
-    a.cand_cap = kCandCap;
     a.cand = (uint4*)ws(c, S_CAND, (size_t)a.cand_cap * sizeof(uint4), &s);
     a.n_cand = (unsigned long long*)ws(c, S_NCAND, 256, &s);
     if (s != KRUX_OK) return s;
     HIP_TRY(c, kx_launch_fill_u64(a.n_cand, 1, 0ull, st));
     a.want_flag = 0;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    // timed: one event pair around each of the two scan launches
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     if (timed && c->timing) {
-        while (c->ev.size() < c->ev_used + 2) {
+        while (c->ev.size() < c->ev_used + 4) {
             hipEvent_t e;
             HIP_TRY(c, hipEventCreate(&e));
             c->ev.push_back(e);
         }
-        e0 = c->ev[c->ev_used];
-        e1 = c->ev[c->ev_used + 1];
-        c->ev_used += 2;
-        HIP_TRY(c, hipEventRecord(e0, st));
+        for (int i = 0; i < 4; ++i) ev[i] = c->ev[c->ev_used + i];
+        c->ev_used += 4;
     }
+    if (ev[0]) HIP_TRY(c, hipEventRecord(ev[0], st));
     if ((s = launch_scan(c, a, v, col, A_hi, v.form, kx::SCREEN, grid, st)) != KRUX_OK) return s;
-    if (e1) HIP_TRY(c, hipEventRecord(e1, st));
+    if (ev[1]) HIP_TRY(c, hipEventRecord(ev[1], st));
     a.want_flag = 1;
+    if (ev[2]) HIP_TRY(c, hipEventRecord(ev[2], st));
     if ((s = launch_scan(c, a, v, col, A_hi, kx::MISS3, kx::SCREEN, grid, st)) != KRUX_OK) return s;
+    if (ev[3]) HIP_TRY(c, hipEventRecord(ev[3], st));
     HIP_TRY(c, kx_launch_candidates(&a, (int)std::min<int64_t>(ceil_div(a.cand_cap, 256),
                                                                  (int64_t)c->n_cu * 8), st));
     return KRUX_OK;
 }
 
+// Main-pass screen level when per-row minima are wanted.  The chi-square
+// p-values of the test are conservative in the far tail (a trait's smallest p
+// over M null SNPs is typically several times 1/M), so the level is 64/M:
+// then nearly every row has an exactly evaluated pair below it and the
+// fix-up passes see few rows (at 8/M a quarter of the rows stayed open at
+// K = 48 and an eighth at K = 102).
 double screen_level_for_min_p(double p_c, int64_t M) {
     return std::max(p_c, std::min(1.0, 64.0 / (double)std::max<int64_t>(M, 1)));
 }
@@ -444,7 +474,8 @@ krux_status test_impl(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum,
     a.A = rk.A; a.theta = rk.theta; a.row_v = rk.row_v; a.d_nrows = nullptr; a.n_rows = T;
     a.T = std::max<int64_t>(T, 1); a.tiesum = tiesum; a.ranks2 = ranks2; a.perms = nullptr;
     a.G = sn.G; a.gstride = sn.gstride; a.info = sn.info; a.tile_flags = sn.flags;
-    a.M = M; a.n_snp_tiles = sn.n_snp_tiles; a.K = K; a.tiles_per_range = trait_range(v, T);
+    a.M = M; a.n_snp_tiles = sn.n_snp_tiles; a.K = K; a.tiles_per_range = trait_range(v, T, sn.n_snp_tiles, c->n_cu);
+    a.ring = use_ring(v, T);
     a.snp_base = snp_base;
 
     if (mode != KRUX_MODE_HITS) {
@@ -476,6 +507,7 @@ krux_status test_impl(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum,
     // the few rows without one get the looser passes of resolve_min_p.
     const double p_screen = min_p ? screen_level_for_min_p(p_c, M) : p_c;
     set_screen(&a, p_screen);
+    a.cand_cap = candidate_capacity(T, M, p_screen);
     if ((s = run_screen(c, a, v, col, rk.A_hi, st, T, true)) != KRUX_OK) return s;
     if (min_p && T > 0) {
         if ((s = resolve_min_p(c, a, v, col, ranks2, tiesum, T, K, nullptr, T, p_screen, M, st)) != KRUX_OK)
@@ -651,13 +683,15 @@ krux_status krux_permute(krux_ctx* c, const int16_t* ranks2, const int64_t* ties
     a.A = rk.A; a.theta = rk.theta; a.row_v = rk.row_v; a.d_nrows = nullptr; a.n_rows = V;
     a.T = std::max<int64_t>(T, 1); a.tiesum = tiesum; a.ranks2 = ranks2; a.perms = perms;
     a.G = sn.G; a.gstride = sn.gstride; a.info = sn.info; a.tile_flags = sn.flags;
-    a.M = M; a.n_snp_tiles = sn.n_snp_tiles; a.K = K; a.tiles_per_range = trait_range(v, V);
+    a.M = M; a.n_snp_tiles = sn.n_snp_tiles; a.K = K; a.tiles_per_range = trait_range(v, V, sn.n_snp_tiles, c->n_cu);
+    a.ring = use_ring(v, V);
     a.hits = nullptr; a.counts = (unsigned long long*)counts;
     a.minp_bits = min_p ? minp : nullptr;
     set_levels(&a, p_cs, n_thr);
     double loosest = *std::max_element(p_cs, p_cs + n_thr);
     if (min_p) loosest = screen_level_for_min_p(loosest, M);
     set_screen(&a, loosest);
+    a.cand_cap = candidate_capacity(V, M, loosest);
     if ((s = run_screen(c, a, v, col, rk.A_hi, st, V, true)) != KRUX_OK) return s;
     if (min_p && V > 0) {
         if ((s = resolve_min_p(c, a, v, col, ranks2, tiesum, T, K, perms, V, loosest, M, st)) != KRUX_OK)

@@ -22,61 +22,102 @@ namespace kx {
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef int int4v __attribute__((ext_vector_type(4)));
 
-// One wave per SNP row (grid-stride).  gstride: packed row bytes (>= K, %32).
+// Per-SNP constants from the group counts (one thread per SNP).
+__device__ inline SnpInfo snp_constants(int c0, int c1, int c2, int cm, int diag_ok) {
+    SnpInfo s;
+    s.n0 = (int16_t)c0; s.n1 = (int16_t)c1; s.n2 = (int16_t)c2;
+    s.nmiss = (int16_t)cm;
+    double a0 = c0 ? 1.0 / c0 : 0.0, a1 = c1 ? 1.0 / c1 : 0.0, a2 = c2 ? 1.0 / c2 : 0.0;
+    s.a0 = (float)a0; s.a1 = (float)a1; s.a2 = (float)a2;
+    // f = a0 D0^2 + a1 D1^2 + a2 D2^2 with D0 = -D1 - D2, completed to a
+    // square in D1:  f = wy * Y^2 + wz * D2^2,  Y = cy1 D1 + cy2 D2.
+    double wy = 0.0, wz = a2;
+    int cy1 = 0, cy2 = 0;
+    if (c0 > 0 && c1 > 0) {
+        cy1 = c0 + c1; cy2 = c1;
+        wy = 1.0 / ((double)c0 * c1 * (c0 + c1));
+        wz = 1.0 / (double)(c0 + c1) + a2;
+    } else if (c1 > 0) {        // group 0 empty: f = a1 D1^2 + a2 D2^2
+        cy1 = 1; cy2 = 0; wy = a1;
+    } else if (c0 > 0) {        // group 1 empty: D0 = -D2, f = (a0 + a2) D2^2
+        cy1 = 1; cy2 = 1; wy = a0;
+    }
+    if (!diag_ok) { cy1 = 1; cy2 = 0; }
+    s.cy1 = (int16_t)cy1; s.cy2 = (int16_t)cy2;
+    s.wy = (float)wy; s.wz = (float)wz;
+    return s;
+}
+
+// Counts of the codes 0, 1, 2, 3 among the four bytes of w (codes 0..3).
+__device__ inline void count_codes(uint32_t w, int& c0, int& c1, int& c2, int& c3) {
+    const uint32_t b0 = w & 0x01010101u, b1 = (w >> 1) & 0x01010101u;
+    c3 += __popc(b0 & b1);
+    c1 += __popc(b0 & ~b1);
+    c2 += __popc(~b0 & b1);
+    c0 += __popc(~(b0 | b1) & 0x01010101u);
+}
+
+// A block packs kPackRows SNP rows through LDS, one column chunk of
+// kPackCols bytes at a time: the block loads the chunk's input bytes
+// (consecutive threads take consecutive bytes of a row), rewrites them as
+// codes and stores them to the packed rows, then each thread counts the codes
+// of its own row in LDS.  gstride: packed row bytes (>= K, multiple of 32).
+constexpr int kPackRows = 256;
+constexpr int kPackCols = 128;
+constexpr int kPackLds = kPackCols + 4;     // padded LDS row: conflict-free dword reads
+
 __global__ __launch_bounds__(256) void pack_snps(const int8_t* __restrict__ geno, int64_t M,
                                                  int64_t ld, int K, int64_t m_pad, int gstride,
                                                  int diag_ok, int8_t* __restrict__ gp,
                                                  SnpInfo* __restrict__ info,
                                                  int32_t* __restrict__ tile_flags) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    for (int64_t m = wave; m < m_pad; m += n_waves) {
-        int c0 = 0, c1 = 0, c2 = 0, cm = 0;
-        const int8_t* row = geno + m * ld;
-        int8_t* out = gp + m * (int64_t)gstride;
-        for (int k0 = 0; k0 < gstride; k0 += 64) {
-            int k = k0 + lane;
+    __shared__ uint32_t s_rows[kPackRows * kPackLds / 4];
+    uint8_t* s_bytes = (uint8_t*)s_rows;
+    const int tid = threadIdx.x;
+    const int64_t m0 = (int64_t)blockIdx.x * kPackRows;
+    const int64_t m_me = m0 + tid;
+    int c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+    for (int col0 = 0; col0 < gstride; col0 += kPackCols) {
+        const int w = gstride - col0 < kPackCols ? gstride - col0 : kPackCols;
+        for (int idx = tid; idx < kPackRows * kPackCols; idx += 256) {
+            const int r = idx / kPackCols, cc = idx % kPackCols;
+            if (cc >= w) continue;
+            const int64_t m = m0 + r;
+            const int col = col0 + cc;
             int8_t code = kMissingCode;
-            if (m < M && k < K) {
-                int8_t g = row[k];
+            if (m < M && col < K) {
+                const int8_t g = geno[m * ld + col];
                 code = (g >= 0 && g <= 2) ? g : kMissingCode;
             }
-            if (k < gstride) out[k] = code;
-            bool valid = (m < M) && (k < K);
-            c0 += __popcll(__ballot(valid && code == 0));
-            c1 += __popcll(__ballot(valid && code == 1));
-            c2 += __popcll(__ballot(valid && code == 2));
-            cm += __popcll(__ballot(valid && code == kMissingCode));
+            s_bytes[r * kPackLds + cc] = (uint8_t)code;
+            if (m < m_pad) gp[m * (int64_t)gstride + col] = code;
         }
-        if (lane == 0) {
-            SnpInfo s;
-            s.n0 = (int16_t)c0; s.n1 = (int16_t)c1; s.n2 = (int16_t)c2;
-            s.nmiss = (int16_t)cm;
-            double a0 = c0 ? 1.0 / c0 : 0.0, a1 = c1 ? 1.0 / c1 : 0.0, a2 = c2 ? 1.0 / c2 : 0.0;
-            s.a0 = (float)a0; s.a1 = (float)a1; s.a2 = (float)a2;
-            // f = a0 D0^2 + a1 D1^2 + a2 D2^2 with D0 = -D1 - D2, completed to a
-            // square in D1:  f = wy * Y^2 + wz * D2^2,  Y = cy1 D1 + cy2 D2.
-            double wy = 0.0, wz = a2;
-            int cy1 = 0, cy2 = 0;
-            if (c0 > 0 && c1 > 0) {
-                cy1 = c0 + c1; cy2 = c1;
-                wy = 1.0 / ((double)c0 * c1 * (c0 + c1));
-                wz = 1.0 / (double)(c0 + c1) + a2;
-            } else if (c1 > 0) {        // group 0 empty: f = a1 D1^2 + a2 D2^2
-                cy1 = 1; cy2 = 0; wy = a1;
-            } else if (c0 > 0) {        // group 1 empty: D0 = -D2, f = (a0 + a2) D2^2
-                cy1 = 1; cy2 = 1; wy = a0;
-            }
-            if (!diag_ok) { cy1 = 1; cy2 = 0; }
-            s.cy1 = (int16_t)cy1; s.cy2 = (int16_t)cy2;
-            s.wy = (float)wy; s.wz = (float)wz;
-            info[m] = s;
-            if (cm > 0 && m < M) {
-                atomicOr(&tile_flags[m >> 5], 1);
-                atomicOr(&tile_flags[(M + 31) >> 5], 1);  // "some SNP has a missing genotype"
-            }
+        __syncthreads();
+        // this thread's row: only the K real columns count
+        const int valid = K - col0 < w ? (K - col0 > 0 ? K - col0 : 0) : w;
+        const uint32_t* row = s_rows + tid * (kPackLds / 4);
+        const int full = valid >> 2;
+        for (int q = 0; q < full; ++q) count_codes(row[q], c0, c1, c2, c3);
+        if (valid & 3) {
+            const uint32_t keep = (1u << (8 * (valid & 3))) - 1u;
+            // masked-off bytes read as code 0: subtract them afterwards
+            count_codes(row[full] & keep, c0, c1, c2, c3);
+            c0 -= 4 - (valid & 3);
         }
+        __syncthreads();
+    }
+    const bool real = m_me < M;
+    if (!real) { c0 = c1 = c2 = c3 = 0; }
+    if (m_me < m_pad) info[m_me] = snp_constants(c0, c1, c2, c3, diag_ok);
+    // per 32-SNP tile: has a missing genotype (tiles past the last SNP are
+    // never read as tile flags; one of them holds the any-missing flag)
+    const unsigned long long miss = __ballot(real && c3 > 0);
+    const int lane = tid & 63;
+    if ((lane & 31) == 0) {
+        const int64_t tile = m_me >> 5;
+        const uint32_t bits = (uint32_t)(miss >> (lane & 32));
+        if (tile < (M + 31) >> 5) tile_flags[tile] = bits ? 1 : 0;
+        if (bits) atomicOr(&tile_flags[(M + 31) >> 5], 1);   // "some SNP has a missing genotype"
     }
 }
 
@@ -242,8 +283,11 @@ hipError_t kx_launch_pack(const int8_t* geno, int64_t M, int64_t ld, int K, int6
                           int32_t* tile_flags, int grid, hipStream_t st) {
     int64_t n_tiles = m_pad / 32;
     hipLaunchKernelGGL(kx::fill_i32, dim3(64), dim3(256), 0, st, tile_flags, n_tiles + 1, 0);
-    hipLaunchKernelGGL(kx::pack_snps, dim3(grid), dim3(256), 0, st, geno, M, ld, K, m_pad,
-                       gstride, diag_ok, gp, info, tile_flags);
+    (void)grid;
+    const int64_t blocks = (m_pad + kx::kPackRows - 1) / kx::kPackRows;
+    if (blocks > 0)
+        hipLaunchKernelGGL(kx::pack_snps, dim3((unsigned)blocks), dim3(256), 0, st, geno, M, ld,
+                           K, m_pad, gstride, diag_ok, gp, info, tile_flags);
     return hipGetLastError();
 }
 

@@ -335,7 +335,8 @@ __device__ inline void drain(const ScanArgs& a, int2* queue, int& qn, int16_t* q
 // WPE: waves per SIMD the register budget is sized for.
 // PF: 0 = load-then-compute per tile; 1 = next tile prefetched into a second
 // register buffer; 2 = software pipeline (MFMAs of the next tile interleaved
-// with the screen of the current one; screen mode, complete SNPs only).
+// with the screen of the current one; screen mode, complete SNPs only);
+// 3 = the same pipeline fed from an LDS ring shared by the block.
 template <int E, int KS, int FORM, int MODE,
           int PF = (MODE == SCREEN && FORM != MISS3) ? 2 : 0, int WPE = 2>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
@@ -581,52 +582,66 @@ void scan_kernel(ScanArgs a) {
             th = cload(a.theta + t);
         };
         if constexpr (RING) {
-            // As PF == 2, but each A tile is read from global memory once per
-            // block instead of once per wave: wave w loads k-steps w, w + 4 of
-            // tile t + 2 into registers, writes them to a ring of LDS slots one
-            // iteration later, and after one block barrier per tile every wave
-            // reads the whole tile from LDS.  This cuts the vector-L1 traffic
-            // of the A operand by the number of waves per block.
-            constexpr int KW = (KS + kWavesPerBlock - 1) / kWavesPerBlock;  // k-steps per wave
-            frag stg[KW];
-            auto gstage = [&](const int64_t tt) {
+            // As PF == 2, but the A tiles come through a ring of 4 LDS slots
+            // shared by the block's 4 waves (they walk the same trait range):
+            // each wave copies its share of the k-steps of tile t + 2 straight
+            // from global memory into the ring (LDS-DMA loads, no registers),
+            // waits for its own copies of tile t, and after one block barrier
+            // every wave reads tile t from LDS.  This reads each A tile once
+            // per block instead of once per wave, and keeps two tiles in
+            // flight without registers.  A slot is rewritten two barriers
+            // after its last read.
+            constexpr int LPW = (KS + kWavesPerBlock - 1) / kWavesPerBlock;  // copies per wave
+            // The copies are issued from inline assembly: they have no
+            // register result, and keeping them out of the compiler's view
+            // stops it from waiting for every copy in flight before each
+            // read of the ring; arrive() does the exact wait instead.
+            auto issue = [&](const int64_t tt) {
                 const int64_t tc = tt < t1 ? tt : t1 - 1;
 #pragma unroll
-                for (int j = 0; j < KW; ++j) {
-                    const int ks = wave + j * kWavesPerBlock;
-                    if (ks < KS) stg[j] = gload(A + (tc * KS + ks) * kWave + lane);
+                for (int j = 0; j < LPW; ++j) {
+                    int ks = wave + j * kWavesPerBlock;
+                    ks = ks < KS ? ks : KS - 1;     // the spare copy repeats the last k-step
+                    const frag* src = A + (tc * KS + ks) * kWave + lane;
+                    const uint32_t dst = (uint32_t)(uintptr_t)(
+                        (__attribute__((address_space(3))) frag*)&s_ring[((tt & 3) * KS + ks) * kWave]);
+                    asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
+                                 :
+                                 : "s"(__builtin_amdgcn_readfirstlane(dst)), "v"(src)
+                                 : "memory");
                 }
             };
-            auto lstore = [&](const int64_t tt) {
-#pragma unroll
-                for (int j = 0; j < KW; ++j) {
-                    const int ks = wave + j * kWavesPerBlock;
-                    if (ks < KS) s_ring[(tt & 3) * KS * kWave + ks * kWave + lane] = stg[j];
-                }
+            // this wave's copies of the oldest tile in flight have landed
+            // (vmcnt counts in issue order; the two younger tiles may still
+            // be in flight), then the block barrier publishes them
+            auto arrive = [&]() {
+                __builtin_amdgcn_s_waitcnt((2 * LPW) | (0x7 << 4) | (0xF << 8));
+                __builtin_amdgcn_s_barrier();
             };
             auto lread = [&](const int64_t tt, frag (&Af)[KS]) {
 #pragma unroll
-                for (int s = 0; s < KS; ++s) Af[s] = s_ring[(tt & 3) * KS * kWave + s * kWave + lane];
+                for (int s = 0; s < KS; ++s) Af[s] = s_ring[((tt & 3) * KS + s) * kWave + lane];
             };
             auto thr = [&](const int64_t tt) { return cload(a.theta + (tt < t1 ? tt : t1 - 1)); };
             frag Af[KS];
             acc_t c0[NC], c1[NC];
-            // prologue: tiles t0, t0+1 into slots; tile t0+2 staged in registers
-            __syncthreads();   // the ring of the previous item is no longer read
-            gstage(t0); lstore(t0);
-            gstage(t0 + 1); lstore(t0 + 1);
-            gstage(t0 + 2);
-            __syncthreads();
+            // every wave is done with the ring of the previous item (its last
+            // reads fed MFMAs that have issued)
+            __builtin_amdgcn_s_waitcnt(0);
+            __builtin_amdgcn_s_barrier();
+            issue(t0);
+            issue(t0 + 1);
+            issue(t0 + 2);
+            arrive();
             lread(t0, Af);
-            mma_tile(Af, c0);
             float th0 = thr(t0), th1 = 0.0f;
+            mma_tile(Af, c0);
             for (int64_t t = t0; t < t1; t += 2) {
-                // half 1: slot t+2 <- staged, stage t+3, barrier; MFMAs of t+1 || screen of t
-                lstore(t + 2);
-                gstage(t + 3);
-                __syncthreads();
-                th1 = thr(t + 1);
+                // half 1: MFMAs of t+1 || screen of t
+                issue(t + 3);
+                arrive();
                 lread(t + 1, Af);
+                th1 = thr(t + 1);
                 mma_tile(Af, c1);
                 const float g0 = screen_max(c0, th0);
 #pragma unroll
@@ -635,12 +650,11 @@ void scan_kernel(ScanArgs a) {
                     __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);
                 }
                 if (__any(g0 > 0.0f)) screen_cands(t, c0, th0);
-                // half 2: slot t+3 <- staged, stage t+4, barrier; MFMAs of t+2 || screen of t+1
-                lstore(t + 3);
-                gstage(t + 4);
-                __syncthreads();
-                th0 = thr(t + 2);
+                // half 2: MFMAs of t+2 || screen of t+1
+                issue(t + 4);
+                arrive();
                 lread(t + 2, Af);
+                th0 = thr(t + 2);
                 mma_tile(Af, c0);
                 const float g1 = screen_max(c1, th1);
 #pragma unroll
@@ -650,6 +664,8 @@ void scan_kernel(ScanArgs a) {
                 }
                 if (t + 1 < t1 && __any(g1 > 0.0f)) screen_cands(t + 1, c1, th1);
             }
+            // the copies past the range end are still landing in the ring
+            __builtin_amdgcn_s_waitcnt(0);
         } else if constexpr (PF == 2 && MODE == SCREEN && FORM != MISS3) {
             // Software pipeline over pairs of tiles: the MFMA chain of the next
             // tile is issued in the same basic block as the fp32 screen of the

@@ -228,22 +228,33 @@ class Context:
         return dict(counts=counts, min_p=mp)
 
     # ------------------------------------------------------------------ cohorts
-    def test_batched(self, cohorts, M, p_c=1e-5, precision="fp16", hit_capacity=1 << 16,
-                     min_p=False):
-        """cohorts: list of dicts with ranks2, tiesum, geno (device tensors).
-        Returns a list of result dicts (hits_raw, n_hits_t, min_p)."""
-        arr = (Cohort * len(cohorts))()
+    def test_batched_buffers(self, cohorts, hit_capacity=1 << 16, min_p=False):
+        """Output buffers of test_batched (one dict per cohort), for `out`."""
         res = []
-        for i, c in enumerate(cohorts):
-            T, K = c["ranks2"].shape
+        for c in cohorts:
+            T = c["ranks2"].shape[0]
             dev = c["ranks2"].device
-            hits = torch.empty(max(hit_capacity, 1) * 24, dtype=torch.uint8, device=dev)
-            nh = torch.zeros(1, dtype=torch.int64, device=dev)
-            mp = torch.empty(T, dtype=torch.float64, device=dev) if min_p else None
+            res.append(dict(
+                hits_raw=torch.empty(max(hit_capacity, 1) * 24, dtype=torch.uint8, device=dev),
+                n_hits_t=torch.zeros(1, dtype=torch.int64, device=dev),
+                min_p=torch.empty(T, dtype=torch.float64, device=dev) if min_p else None,
+                hit_capacity=hit_capacity))
+        return res
+
+    def test_batched(self, cohorts, M, p_c=1e-5, precision="fp16", hit_capacity=1 << 16,
+                     min_p=False, out=None):
+        """cohorts: list of dicts with ranks2, tiesum, geno (device tensors).
+        Returns a list of result dicts (hits_raw, n_hits_t, min_p); `out` may
+        pass the buffers of test_batched_buffers."""
+        res = out if out is not None else self.test_batched_buffers(cohorts, hit_capacity, min_p)
+        arr = (Cohort * len(cohorts))()
+        for i, (c, b) in enumerate(zip(cohorts, res)):
+            T, K = c["ranks2"].shape
+            mp = b["min_p"]
             arr[i] = Cohort(c["ranks2"].data_ptr(), c["tiesum"].data_ptr(), T, K,
-                            c["geno"].data_ptr(), c["geno"].stride(0), hits.data_ptr(),
-                            hit_capacity, nh.data_ptr(), mp.data_ptr() if mp is not None else None)
-            res.append(dict(hits_raw=hits, n_hits_t=nh, min_p=mp, hit_capacity=hit_capacity))
+                            c["geno"].data_ptr(), c["geno"].stride(0), b["hits_raw"].data_ptr(),
+                            b["hit_capacity"], b["n_hits_t"].data_ptr(),
+                            mp.data_ptr() if mp is not None else None)
         self._check(self.lib.krux_test_batched(self.h, ctypes.cast(arr, ctypes.c_void_p),
                                                len(cohorts), int(M), float(p_c),
                                                _PREC[precision], _stream()))

@@ -207,6 +207,26 @@ def test_permute_counts_and_min_p(kx, K, T, M):
         assert_p(mp[i], o["min_p"], "perm min p")
 
 
+def test_permute_large_operand(kx):
+    # 50 permutations x 1500 traits: a 16 MB operand, screened through the
+    # block-shared LDS ring pipeline
+    K, T, M, P = 102, 1500, 97, 50
+    say("permute large operand", K, T, M, P)
+    x, g = _inputs(29, T, K, M)
+    rs = datagen.streams(31)
+    perms = datagen.permutations(rs["perms"], P, K)
+    r, ts = _ranks(kx, x)
+    p_cs = (0.05, 0.01, 0.001)
+    res = kx.permute(r, ts, _dev(g), _dev(perms), p_cs=p_cs)
+    torch.cuda.synchronize()
+    counts = res["counts"].cpu().numpy()
+    mp = res["min_p"].cpu().numpy()
+    for i in range(P):
+        o = oracle.scan(x, g, p_cs=p_cs, perm=perms[i], min_p=True)
+        assert np.array_equal(counts[i], o["counts"]), i
+        assert_p(mp[i], o["min_p"], "perm min p %d" % i)
+
+
 # ---------------------------------------------------------------- small workload, full size
 def test_small_workload_full_matrices(kx):
     say("workload small_full 1000 x 2000 x 102")
