@@ -20,7 +20,7 @@ namespace {
 enum Slot {
     S_PACKED, S_INFO, S_FLAGS, S_A, S_THETA, S_ROWV, S_A2, S_THETA2, S_ROWV2,
     S_LIST_A, S_LIST_B, S_COUNT_A, S_COUNT_B, S_MINP, S_STAGE, S_NHITS, S_KEYS, S_IDX,
-    S_SORT_TMP, S_F64_R, S_F64_I, S_F64_S, S_COUNT_PREV, S_CAND, S_NCAND,
+    S_SORT_TMP, S_F64_R, S_F64_I, S_F64_S, S_COUNT_PREV, S_CAND, S_NCAND, S_MCAND, S_NMCAND,
     S_AH, S_AH2, S_BF, S_BF3,
     S_N_SLOTS
 };
@@ -328,8 +328,13 @@ krux_status run_screen(krux_ctx* c, kx::ScanArgs a, const Variant& v, const Colu
     krux_status s = KRUX_OK;
     a.cand = (uint4*)ws(c, S_CAND, (size_t)a.cand_cap * sizeof(uint4), &s);
     a.n_cand = (unsigned long long*)ws(c, S_NCAND, 256, &s);
+    // pairs of SNPs with missing genotypes that pass the bound: up to 1/16 of
+    // the pairs, at most 2^26 entries (512 MB); the rest are evaluated in the scan
+    a.mcand_cap = std::min<int64_t>(std::max<int64_t>(n_rows_max * a.M / 16, 1 << 16), 1LL << 26);
+    a.mcand = (int2*)ws(c, S_MCAND, (size_t)a.mcand_cap * sizeof(int2), &s);
+    a.n_mcand = a.n_cand + 1;
     if (s != KRUX_OK) return s;
-    HIP_TRY(c, kx_launch_fill_u64(a.n_cand, 1, 0ull, st));
+    HIP_TRY(c, kx_launch_fill_u64(a.n_cand, 2, 0ull, st));
     a.want_flag = 0;
     // timed: one event pair around each of the two scan launches
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -351,6 +356,7 @@ krux_status run_screen(krux_ctx* c, kx::ScanArgs a, const Variant& v, const Colu
     if (ev[3]) HIP_TRY(c, hipEventRecord(ev[3], st));
     HIP_TRY(c, kx_launch_candidates(&a, (int)std::min<int64_t>(ceil_div(a.cand_cap, 256),
                                                                  (int64_t)c->n_cu * 8), st));
+    HIP_TRY(c, kx_launch_missing(&a, c->n_cu * 8, st));
     return KRUX_OK;
 }
 

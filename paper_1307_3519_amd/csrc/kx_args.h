@@ -65,6 +65,11 @@ struct ScanArgs {
     uint4* cand;
     int64_t cand_cap;
     unsigned long long* n_cand;
+    // screen mode: pairs of SNPs with missing genotypes that passed the
+    // bound, {operand row, SNP}, evaluated by scan_missing (null: in the scan)
+    int2* mcand;
+    int64_t mcand_cap;
+    unsigned long long* n_mcand;
 };
 
 // Extra operands of the tiled large-K kernels.

@@ -245,58 +245,72 @@ __device__ inline void stage_candidates(const ScanArgs& a, const ScanArgs* a_lds
 //   a'_k = a_k - sum_{j missing} (2 [a_j < a_k] + [a_j == a_k]),
 // the tie term loses 3 t (t - 1) for each removal from a tie group of
 // current size t.  All 64 lanes of the wave take part; the result is uniform.
-__device__ inline double coop_exact(const ScanArgs& a, int64_t v, int64_t m, int16_t* qbuf,
+// sbuf: 2K entries of this wave's LDS: the pair's samples (rank | code << 13,
+// ranks are below 2^13 for K <= 4095) and the ranks of its missing samples.
+constexpr int kCodeShift = 13;
+constexpr int kRankMask = (1 << kCodeShift) - 1;
+
+__device__ inline double coop_exact(const ScanArgs& a, int64_t v, int64_t m, int16_t* sbuf,
                                     int lane, int* df_out, int64_t* s_out) {
     const int K = a.K;
     const int64_t trait = v % a.T, perm = v / a.T;
     const int16_t* rk = a.ranks2 + trait * K;
     const int32_t* pm = a.perms ? a.perms + perm * K : nullptr;
     const int8_t* gr = a.G + m * (int64_t)a.gstride;
+    uint16_t* sr = (uint16_t*)sbuf;
+    int16_t* qb = sbuf + K;
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    // one pass over global memory: rank and genotype code of every sample
+    for (int k0 = 0; k0 < K; k0 += kWave) {
+        const int k = k0 + lane;
+        if (k < K) {
+            const int code = gr[k];
+            const int ak = rk[pm ? pm[k] : k];
+            sr[k] = (uint16_t)(ak | (code << kCodeShift));
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
     int nq = 0;
     for (int k0 = 0; k0 < K; k0 += kWave) {
-        int k = k0 + lane;
-        bool miss = false;
-        int ak = 0;
-        if (k < K) {
-            miss = gr[k] == kMissingCode;
-            ak = rk[pm ? pm[k] : k];
-        }
-        unsigned long long msk = __ballot(miss);
-        if (miss) qbuf[nq + __popcll(msk & lt)] = (int16_t)ak;
+        const int k = k0 + lane;
+        const int x = k < K ? sr[k] : 0;
+        const bool miss = k < K && (x >> kCodeShift) == kMissingCode;
+        const unsigned long long msk = __ballot(miss);
+        if (miss) qb[nq + __popcll(msk & lt)] = (int16_t)(x & kRankMask);
         nq += __popcll(msk);
     }
     __builtin_amdgcn_wave_barrier();
     long long ts = a.tiesum[trait];
-    for (int qi = 0; qi < nq; ++qi) {
-        int aj = qbuf[qi];
-        int cnt = 0;
-        for (int k0 = 0; k0 < K; k0 += kWave) {
-            int k = k0 + lane;
-            if (k < K) cnt += (rk[pm ? pm[k] : k] == aj);
+    if (ts != 0) {
+        for (int qi = 0; qi < nq; ++qi) {
+            const int aj = qb[qi];
+            int cnt = 0;
+            for (int k0 = 0; k0 < K; k0 += kWave) {
+                const int k = k0 + lane;
+                if (k < K) cnt += ((sr[k] & kRankMask) == aj);
+            }
+            for (int q0 = 0; q0 < qi; q0 += kWave) {
+                const int qq = q0 + lane;
+                if (qq < qi) cnt -= (qb[qq] == aj);
+            }
+            const int t = wave_sum(cnt);
+            ts -= 3ll * t * (t - 1);
         }
-        for (int q0 = 0; q0 < qi; q0 += kWave) {
-            int qq = q0 + lane;
-            if (qq < qi) cnt -= (qbuf[qq] == aj);
-        }
-        int t = wave_sum(cnt);
-        ts -= 3ll * t * (t - 1);
     }
     long long s0 = 0, s1 = 0, s2 = 0;
     for (int k0 = 0; k0 < K; k0 += kWave) {
-        int k = k0 + lane;
-        if (k < K) {
-            int code = gr[k];
-            if (code != kMissingCode) {
-                int ak = rk[pm ? pm[k] : k];
-                int w = 0;
-                for (int qi = 0; qi < nq; ++qi) {
-                    int aj = qbuf[qi];
-                    w += (aj < ak) ? 2 : (aj == ak ? 1 : 0);
-                }
-                int ap = ak - w;
-                if (code == 0) s0 += ap; else if (code == 1) s1 += ap; else s2 += ap;
+        const int k = k0 + lane;
+        const int x = k < K ? sr[k] : (kMissingCode << kCodeShift);
+        const int code = x >> kCodeShift;
+        if (code != kMissingCode) {
+            const int ak = x & kRankMask;
+            int w = 0;
+            for (int qi = 0; qi < nq; ++qi) {
+                const int aj = qb[qi];
+                w += (aj < ak) ? 2 : (aj == ak ? 1 : 0);
             }
+            const int ap = ak - w;
+            if (code == 0) s0 += ap; else if (code == 1) s1 += ap; else s2 += ap;
         }
     }
     s0 = wave_sum64(s0); s1 = wave_sum64(s1); s2 = wave_sum64(s2);
@@ -311,9 +325,26 @@ __device__ inline double coop_exact(const ScanArgs& a, int64_t v, int64_t m, int
     return exact_H(D0, D1, D2, inf.n0, inf.n1, inf.n2, kp, ts, snp_df(inf));
 }
 
+// Empties a wave's queue of screened pairs of SNPs with missing genotypes.
+// In screen mode the pairs go to the global buffer (one atomic per burst) for
+// scan_missing, which runs them at full occupancy instead of stalling the
+// scan; pairs beyond its capacity, and the FULL / SUMS outputs, are
+// evaluated here.
 template <int MODE>
 __device__ inline void drain(const ScanArgs& a, int2* queue, int& qn, int16_t* qbuf, int lane) {
-    for (int e = 0; e < qn; ++e) {
+    int e0 = 0;
+    if constexpr (MODE == SCREEN) {
+        if (a.mcand) {
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(a.n_mcand, (unsigned long long)qn);
+            base = __shfl(base, 0, 64);
+            const int64_t room = a.mcand_cap - (int64_t)base;
+            const int fit = room <= 0 ? 0 : (room < qn ? (int)room : qn);
+            for (int i = lane; i < fit; i += kWave) a.mcand[base + i] = queue[i];
+            e0 = fit;
+        }
+    }
+    for (int e = e0; e < qn; ++e) {
         int2 q = queue[e];
         int64_t v = a.row_v[q.x];
         // padding rows (zero operand) can pass the missing-genotype bound; the
@@ -360,14 +391,14 @@ void scan_kernel(ScanArgs a) {
     __shared__ frag s_ring[RING ? 4 * KS * kWave : 1];
     if (threadIdx.x == 0) s_args = a;
     __syncthreads();
-    extern __shared__ int16_t s_qbuf[];   // MISS3: per wave K entries
+    extern __shared__ int16_t s_qbuf[];   // MISS3: per wave 2K entries
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     int2* queue = s_queue[QUEUE ? wave : 0];
     uint4* stage = s_stage[MODE == SCREEN ? wave : 0];
     int sn = 0;
-    int16_t* qbuf = s_qbuf + (QUEUE ? wave * a.K : 0);
+    int16_t* qbuf = s_qbuf + (QUEUE ? wave * 2 * a.K : 0);
     int qn = 0;
 
     // tile_flags[n_snp_tiles] is set when any SNP has a missing genotype
@@ -743,7 +774,7 @@ namespace kx {
 template <int E, int KS, int FORM, int MODE,
           int PF = (MODE == kx::SCREEN && FORM != kx::MISS3) ? 2 : 0, int WPE = 2>
 inline hipError_t launch_one(const kx::ScanArgs& a, int grid, hipStream_t st) {
-    size_t lds = FORM == kx::MISS3 ? (size_t)kx::kWavesPerBlock * a.K * sizeof(int16_t) : 0;
+    size_t lds = FORM == kx::MISS3 ? (size_t)kx::kWavesPerBlock * 2 * a.K * sizeof(int16_t) : 0;
     auto kern = kx::scan_kernel<E, KS, FORM, MODE, PF, WPE>;
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 256, lds) != hipSuccess || occ < 1)
