@@ -312,6 +312,29 @@ def permutations(args, ctx, torch, np, datagen, krux):
     out["roofline"] = roofline("scan_kernel<F16, KS=7, DIAG, SCREEN>", pairs, 4 * K, kms,
                                PEAK_FP16_TFLOPS, "TFLOP/s")
     out["mean_counts"] = counts.mean(axis=0).tolist()
+    # the same step captured once into a HIP graph and replayed as one launch
+    r, ts, _ = ctx.rank(x)
+    o = buf["o"]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        ctx.permute(r, ts, g, perms, p_cs=p_cs, min_p=True, out=o)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        rr, tt, _ = ctx.rank(x, out=(r, ts))
+        ctx.permute(rr, tt, g, perms, p_cs=p_cs, min_p=True, out=o)
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    gms = (time.perf_counter() - t0) * 1e3 / steps
+    same = bool(np.array_equal(o["counts"].cpu().numpy(), counts))
+    log("graph replay: %.1f ms/step, counts identical %s" % (gms, same))
+    out["graph_replay"] = {"ms_per_step": gms, "value": pairs / (gms / 1e3), "unit": "pairs/s",
+                           "identical_counts": same}
     if not args.no_cpu:
         import oracle
         out["cpu_baseline"] = oracle_baseline(

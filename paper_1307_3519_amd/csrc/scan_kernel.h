@@ -197,6 +197,15 @@ __device__ __attribute__((noinline)) void eval_candidate_fallback(const ScanArgs
     eval_candidate(a, row, m, y, z, flags);
 }
 
+// Block barrier without a memory fence (the LDS-DMA waits are explicit);
+// the empty asm statements keep the compiler from moving memory accesses
+// across it.
+__device__ inline void block_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
 // Screened pairs are staged per wave in LDS and copied to the global
 // candidate buffer in bursts (one atomic per burst); a pair that does not fit
 // in the global buffer is evaluated on the spot.
@@ -394,7 +403,7 @@ void scan_kernel(ScanArgs a) {
     extern __shared__ int16_t s_qbuf[];   // MISS3: per wave 2K entries
 
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
     int2* queue = s_queue[QUEUE ? wave : 0];
     uint4* stage = s_stage[MODE == SCREEN ? wave : 0];
     int sn = 0;
@@ -647,7 +656,7 @@ void scan_kernel(ScanArgs a) {
             // be in flight), then the block barrier publishes them
             auto arrive = [&]() {
                 __builtin_amdgcn_s_waitcnt((2 * LPW) | (0x7 << 4) | (0xF << 8));
-                __builtin_amdgcn_s_barrier();
+                block_barrier();
             };
             auto lread = [&](const int64_t tt, frag (&Af)[KS]) {
 #pragma unroll
@@ -659,7 +668,7 @@ void scan_kernel(ScanArgs a) {
             // every wave is done with the ring of the previous item (its last
             // reads fed MFMAs that have issued)
             __builtin_amdgcn_s_waitcnt(0);
-            __builtin_amdgcn_s_barrier();
+            block_barrier();
             issue(t0);
             issue(t0 + 1);
             issue(t0 + 2);

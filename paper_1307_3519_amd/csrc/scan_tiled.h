@@ -70,10 +70,15 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
     constexpr int NFA = BT * KC * NP;                  // A fragments per chunk
     constexpr int NFB = BS * KC * NC;                  // B fragments per chunk
     constexpr int NF = NFA + NFB;
-    constexpr int FPW = (NF + kWavesPerBlock - 1) / kWavesPerBlock;  // loads per wave
+    constexpr int FPW = NF / kWavesPerBlock;           // copies per wave per chunk (NF % 4 == 0)
+    static_assert(NF % kWavesPerBlock == 0, "every wave copies the same number of fragments");
     constexpr bool QUEUE = FORM == MISS3;
+    // ring of R chunk slots filled D = R - 1 chunks ahead by LDS-DMA copies
+    constexpr int R = NF * kWave * 16 * 4 <= 100 * 1024 ? 4 : 3;
+    constexpr int D = R - 1;
+    static_assert((D - 1) * FPW <= 15, "wait count fits the vmcnt field");
 
-    __shared__ frag s_buf[2][NF][kWave];
+    __shared__ frag s_buf[R][NF][kWave];
     __shared__ int2 s_queue[QUEUE ? kWavesPerBlock : 1][QUEUE ? kQueueCap : 1];
     __shared__ uint4 s_stage[MODE == SCREEN ? kWavesPerBlock : 1][kStageCap];
     __shared__ ScanArgs s_args;
@@ -82,7 +87,7 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
     int2* queue = s_queue[QUEUE ? wave : 0];
     uint4* stage = s_stage[MODE == SCREEN ? wave : 0];
     int sn = 0, qn = 0;
@@ -104,8 +109,31 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
     const frag* Bf = (const frag*)ta.Bf;
     const int nchunks = KS / KC;
 
-    for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
-        const int64_t sb = item / n_tb, tb = item % n_tb;
+    // Item order: blocks go round-robin to the 8 XCDs, so the blocks of one
+    // XCD (b, b + 8, ...) take, round after round, one 8 x (G/64) group of
+    // (trait block, SNP block) items: the group's A and B slices stay in that
+    // XCD's L2 while its blocks share them.  Without a multiple of 8 blocks,
+    // plain row-major order.
+    const bool grouped = (gridDim.x % 8) == 0 && gridDim.x >= 64;
+    const int64_t per_xcd = gridDim.x / 8;
+    const int64_t GT = 8, GS = grouped ? per_xcd / 8 : 1;
+    const int64_t n_gt = (n_tb + GT - 1) / GT, n_gs = (n_sb + GS - 1) / GS;
+    const int64_t n_rounds = grouped ? (n_gt * n_gs + 7) / 8 : (items + gridDim.x - 1) / gridDim.x;
+    for (int64_t round = 0; round < n_rounds; ++round) {
+        int64_t tb, sb;
+        if (grouped) {
+            const int64_t grp = round * 8 + blockIdx.x % 8;
+            const int64_t j = blockIdx.x / 8;
+            if (grp >= n_gt * n_gs || j >= GT * GS) continue;
+            tb = (grp % n_gt) * GT + j % GT;
+            sb = (grp / n_gt) * GS + j / GT;
+        } else {
+            const int64_t item = round * gridDim.x + blockIdx.x;
+            if (item >= items) continue;
+            sb = item / n_tb;
+            tb = item % n_tb;
+        }
+        if (tb >= n_tb || sb >= n_sb) continue;
         // SNP tiles of this wave and whether each is handled by this kernel
         int64_t stl[WS];
         bool act[WS];
@@ -119,34 +147,36 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
         }
         if (!__syncthreads_or(any)) continue;   // block-uniform skip
 
-        // fragment loads of chunk ch: fragment f of the block's stage
-        frag ld[FPW];
-        auto gload_chunk = [&](int ch) {
+        // LDS-DMA copy of chunk ch (clamped into range) into slot ch % R:
+        // this wave's FPW fragments, each 64 lanes x 16 bytes, contiguous in
+        // global memory and in the slot.  Issued from inline assembly so
+        // that the compiler does not wait for every copy in flight before
+        // reading the ring; the waits below are exact.
+        auto issue_chunk = [&](int ch) {
+            const int chc = ch < nchunks ? ch : nchunks - 1;
+            const int slot = ch % R;
 #pragma unroll
             for (int i = 0; i < FPW; ++i) {
                 const int f = wave * FPW + i;
-                if (f < NF) {
-                    if (f < NFA) {
-                        const int p = f / (BT * KC), r = f % (BT * KC);
-                        const int tt = r / KC, kk = r % KC;
-                        const int64_t tile = tb * BT + tt;
-                        const frag* src = p ? Ah : A;
-                        ld[i] = gload(src + (tile * KS + ch * KC + kk) * kWave + lane);
-                    } else {
-                        const int g = f - NFA;
-                        const int s = g / (KC * NC), r = g % (KC * NC);
-                        const int kk = r / NC, c = r % NC;
-                        const int64_t st = sb * BS + s;
-                        ld[i] = gload(Bf + ((st * KS + ch * KC + kk) * NC + c) * kWave + lane);
-                    }
+                const frag* src;
+                if (f < NFA) {
+                    const int p = f / (BT * KC), r = f % (BT * KC);
+                    const int tt = r / KC, kk = r % KC;
+                    const int64_t tile = tb * BT + tt;
+                    src = (p ? Ah : A) + (tile * KS + chc * KC + kk) * kWave + lane;
+                } else {
+                    const int g = f - NFA;
+                    const int s2 = g / (KC * NC), r = g % (KC * NC);
+                    const int kk = r / NC, c = r % NC;
+                    const int64_t st = sb * BS + s2;
+                    src = Bf + ((st * KS + chc * KC + kk) * NC + c) * kWave + lane;
                 }
-            }
-        };
-        auto sstore_chunk = [&](int buf) {
-#pragma unroll
-            for (int i = 0; i < FPW; ++i) {
-                const int f = wave * FPW + i;
-                if (f < NF) s_buf[buf][f][lane] = ld[i];
+                const uint32_t dst = (uint32_t)(uintptr_t)(
+                    (__attribute__((address_space(3))) frag*)&s_buf[slot][f][0]);
+                asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
+                             :
+                             : "s"(__builtin_amdgcn_readfirstlane(dst)), "v"(src)
+                             : "memory");
             }
         };
         acc_t acc[NP][2][WS][NC];
@@ -159,13 +189,20 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
 #pragma unroll
                     for (int c = 0; c < NC; ++c) acc[p][ti][j][c] = acc_t{};
 
-        __syncthreads();              // previous item's readers are done with s_buf
-        gload_chunk(0);
-        sstore_chunk(0);
-        __syncthreads();
+        // every wave is done reading the ring of the previous item
+        __builtin_amdgcn_s_waitcnt(0);
+        block_barrier();
+#pragma unroll
+        for (int d = 0; d < D; ++d) issue_chunk(d);
         for (int ch = 0; ch < nchunks; ++ch) {
-            const int buf = ch & 1;
-            if (ch + 1 < nchunks) gload_chunk(ch + 1);
+            // this wave's copies of chunk ch have landed (the D - 1 younger
+            // chunks may still be in flight); the barrier publishes every
+            // wave's copies and certifies that chunk ch - 1, whose slot the
+            // next copy reuses, has been read by all waves
+            __builtin_amdgcn_s_waitcnt(((D - 1) * FPW) | (0x7 << 4) | (0xF << 8));
+            block_barrier();
+            issue_chunk(ch + D);
+            const int buf = ch % R;
 #pragma unroll
             for (int kk = 0; kk < KC; ++kk) {
                 frag fa[NP][2], fb[WS][NC];
@@ -189,9 +226,9 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
                             for (int c = 0; c < NC; ++c)
                                 acc[p][ti][j][c] = T_::mma(fa[p][ti], fb[j][c], acc[p][ti][j][c]);
             }
-            if (ch + 1 < nchunks) sstore_chunk(buf ^ 1);
-            __syncthreads();
         }
+        // the clamped copies past the last chunk are still landing
+        __builtin_amdgcn_s_waitcnt(0);
 
         // epilogue over the wave's 2 x WS output tiles
 #pragma unroll

@@ -138,15 +138,22 @@ class Context:
         return ms.value, n.value
 
     # ------------------------------------------------------------------ rank
-    def rank(self, expr):
+    def rank(self, expr, out=None):
         """expr: (T, K) float32 cuda tensor (row-contiguous, any row stride)
-        -> ranks2 (T, K) int16, tiesum (T,) int64, nvalid (T,) int32."""
+        -> ranks2 (T, K) int16, tiesum (T,) int64, nvalid (T,) int32.
+        `out` may pass (ranks2, tiesum[, nvalid]) buffers."""
         assert expr.is_cuda and expr.dtype == torch.float32 and expr.dim() == 2
         assert expr.stride(1) == 1
         T, K = expr.shape
-        r = torch.empty((T, K), dtype=torch.int16, device=expr.device)
-        ts = torch.empty(T, dtype=torch.int64, device=expr.device)
-        nv = torch.empty(T, dtype=torch.int32, device=expr.device)
+        if out is not None:
+            r, ts = out[0], out[1]
+            nv = out[2] if len(out) > 2 else None
+            assert r.shape == (T, K) and r.dtype == torch.int16 and r.is_contiguous()
+            assert ts.shape == (T,) and ts.dtype == torch.int64
+        else:
+            r = torch.empty((T, K), dtype=torch.int16, device=expr.device)
+            ts = torch.empty(T, dtype=torch.int64, device=expr.device)
+            nv = torch.empty(T, dtype=torch.int32, device=expr.device)
         self._check(self.lib.krux_rank(self.h, _ptr(expr), T, K, expr.stride(0) if T else K,
                                        _ptr(r), _ptr(ts), _ptr(nv), _stream()))
         return r, ts, nv
