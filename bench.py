@@ -355,6 +355,14 @@ def cohorts_missing(args, ctx, torch, np, datagen, krux):
     dev = [dict(x=torch.from_numpy(c["expr"]).cuda(), geno=torch.from_numpy(c["geno"]).cuda())
            for c in cs]
     runner = Runner(ctx, torch)
+    # launch configuration per sample count, tuned on a slice of the panel
+    tuned = []
+    t0 = time.time()
+    for d, c in zip(dev, cs):
+        r, ts, _ = ctx.rank(d["x"])
+        ms_t = ctx.autotune(r, ts, d["geno"][: min(M, 50000)], precision="fp16")
+        tuned.append(dict(K=c["K"], ms_slice=ms_t, **ctx.tuning_of(c["K"], "fp16")))
+    log("autotuned in %.1fs: %s" % (time.time() - t0, tuned))
 
     def step():
         batch = []
@@ -380,6 +388,7 @@ def cohorts_missing(args, ctx, torch, np, datagen, krux):
     out["roofline"] = roofline("scan kernels of all cohorts", pairs, flops / pairs, kms,
                                PEAK_FP16_TFLOPS, "TFLOP/s")
     out["n_hits"] = n_hits
+    out["autotuned"] = tuned
     if not args.no_cpu:
         import oracle
         c0 = cs[2]          # the K = 102 cohort

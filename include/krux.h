@@ -181,6 +181,37 @@ krux_status krux_test_batched(krux_ctx* ctx, const krux_cohort* cohorts,
 krux_status krux_timer_start(krux_ctx* ctx);
 krux_status krux_timer_read(krux_ctx* ctx, double* total_ms, int64_t* launches);
 
+/* Autotuner of the launch configuration (Data slicing: the work is tiled
+ * over traits and SNP blocks; how large a trait range each work item covers,
+ * whether the A tiles of the K <= 128 kernel go through the block's LDS ring,
+ * and the XCD-grouped item order of the K > 128 kernel are machine- and
+ * shape-dependent).  Times krux_test (hit mode, P_c = 1e-5, no minimum p) on
+ * the caller's inputs -- device arrays as for krux_test; a representative
+ * slice of a few 1e9 pairs is enough -- for every candidate configuration of
+ * the kernel that serves (K, precision), and keeps the fastest in the context:
+ * later krux_test / krux_permute / krux_test_batched calls with that K and
+ * precision use it.  precision: KRUX_PREC_FP16 or KRUX_PREC_INT8 (the fp64
+ * comparator has nothing to tune: KRUX_ERR_UNSUPPORTED).  cache_path (host,
+ * nullable): the choice is appended to this text file as one JSON object per
+ * line keyed by architecture, K, precision and mode.  best_ms (host,
+ * nullable): time of the chosen configuration per call.  Synchronises the
+ * stream.  Results of the scan do not depend on the configuration. */
+krux_status krux_autotune(krux_ctx* ctx, const int16_t* ranks2, const int64_t* tiesum,
+                          int64_t T, int32_t K, const int8_t* geno, int64_t M,
+                          int64_t ld_geno, int32_t precision, const char* cache_path,
+                          double* best_ms, void* stream);
+
+/* Loads the entries of a cache file written by krux_autotune that match this
+ * device's architecture (later lines win; other lines are ignored). */
+krux_status krux_load_tuning(krux_ctx* ctx, const char* cache_path);
+
+/* The configuration in use for (K, precision): ring (1 LDS ring, 0 register
+ * double buffer), range_kb (trait-range operand budget) and grouped (XCD-
+ * grouped item order); -1 / 0 mean the built-in rule.  Host outputs,
+ * each nullable. */
+krux_status krux_tuning_of(krux_ctx* ctx, int32_t K, int32_t precision, int32_t* ring,
+                           int32_t* range_kb, int32_t* grouped);
+
 #ifdef __cplusplus
 }
 #endif

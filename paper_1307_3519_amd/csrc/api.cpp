@@ -8,6 +8,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <map>
+#include <utility>
 #include <vector>
 
 #include "../../include/krux.h"
@@ -21,6 +23,7 @@ enum Slot {
     S_PACKED, S_INFO, S_FLAGS, S_A, S_THETA, S_ROWV, S_A2, S_THETA2, S_ROWV2,
     S_LIST_A, S_LIST_B, S_COUNT_A, S_COUNT_B, S_MINP, S_STAGE, S_NHITS, S_KEYS, S_IDX,
     S_SORT_TMP, S_F64_R, S_F64_I, S_F64_S, S_COUNT_PREV, S_CAND, S_NCAND, S_MCAND, S_NMCAND,
+    S_TUNE_HITS, S_TUNE_N,
     S_AH, S_AH2, S_BF, S_BF3,
     S_N_SLOTS
 };
@@ -32,9 +35,20 @@ struct Buf {
 
 }  // namespace
 
+// Launch configuration chosen by krux_autotune for one (K, precision).
+// -1 / 0: the built-in rule.
+struct Tuning {
+    int ring = -1;       // SNP-stationary kernel: 1 = LDS ring, 0 = register double buffer
+    int range_kb = 0;    // SNP-stationary kernel: trait-range operand budget
+    int grouped = -1;    // tiled kernel: XCD-grouped item order
+    double ms = 0.0;     // time of the tuning run
+};
+
 struct krux_ctx {
     int device = 0;
     int n_cu = 256;
+    char arch[32] = {0};
+    std::map<std::pair<int, int>, Tuning> tuned;   // (K, precision) -> configuration
     std::string err;
     Buf bufs[S_N_SLOTS];
     void* blas = nullptr;   // rocBLAS handle of the fp64 comparator (created on first use)
@@ -270,12 +284,14 @@ krux_status launch_scan(krux_ctx* c, const kx::ScanArgs& a, const Variant& v, co
 // 1 + resident blocks / SNP blocks ranges are in flight, and together they
 // get ~2.5 MB.  At least two ranges, so that the persistent grid's last
 // round is short.
-int trait_range(const Variant& v, int64_t n_rows, int64_t n_snp_tiles, int n_cu) {
+int trait_range(const Variant& v, int64_t n_rows, int64_t n_snp_tiles, int n_cu,
+                int budget_kb = 2560) {
     const int64_t n_tiles = std::max<int64_t>(ceil_div(n_rows, kx::kTile), 1);
     const int64_t tile_bytes = (int64_t)v.ks * kx::kWave * 16;
     const int64_t snp_blocks = std::max<int64_t>(ceil_div(n_snp_tiles, kx::kWavesPerBlock), 1);
     const double in_flight = 1.0 + 2.0 * n_cu / (double)snp_blocks;   // 2 blocks per CU
-    const int64_t budget = std::max<int64_t>((int64_t)((double)(5 << 19) / in_flight), 64 << 10);
+    const int64_t budget = std::max<int64_t>((int64_t)((double)budget_kb * 1024.0 / in_flight),
+                                             64 << 10);
     int64_t ranges = ceil_div(n_tiles * tile_bytes, budget);
     if (n_tiles >= 128) ranges = std::max<int64_t>(ranges, 2);
     const int64_t tpr = ceil_div(ceil_div(n_tiles, ranges), 2) * 2;
@@ -291,6 +307,22 @@ int trait_range(const Variant& v, int64_t n_rows, int64_t n_snp_tiles, int n_cu)
 int use_ring(const Variant& v, int64_t n_rows) {
     const int64_t bytes = ceil_div(n_rows, kx::kTile) * (int64_t)v.ks * kx::kWave * 16;
     return !v.tiled && bytes > ((int64_t)16 << 20) ? 1 : 0;
+}
+
+// Launch parameters of a scan: the autotuned configuration for (K,
+// precision) if krux_autotune or krux_load_tuning provided one, else the rules
+// above.
+void apply_tuning(krux_ctx* c, int K, int precision, const Variant& v, int64_t n_rows,
+                  int64_t n_snp_tiles, kx::ScanArgs* a) {
+    Tuning t;
+    auto it = c->tuned.find({K, precision});
+    if (it != c->tuned.end()) t = it->second;
+    a->tiles_per_range = trait_range(v, n_rows, n_snp_tiles, c->n_cu,
+                                     t.range_kb > 0 ? t.range_kb : 2560);
+    a->ring = t.ring >= 0 ? t.ring : use_ring(v, n_rows);
+    // the tuner preferred row-major item order at every K of the cohort
+    // workload (150..1000), so that is the default
+    a->group_items = t.grouped >= 0 ? t.grouped : 0;
 }
 
 // Work items of one scan launch (an upper bound; the kernels stop early).
@@ -480,8 +512,8 @@ krux_status test_impl(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum,
     a.A = rk.A; a.theta = rk.theta; a.row_v = rk.row_v; a.d_nrows = nullptr; a.n_rows = T;
     a.T = std::max<int64_t>(T, 1); a.tiesum = tiesum; a.ranks2 = ranks2; a.perms = nullptr;
     a.G = sn.G; a.gstride = sn.gstride; a.info = sn.info; a.tile_flags = sn.flags;
-    a.M = M; a.n_snp_tiles = sn.n_snp_tiles; a.K = K; a.tiles_per_range = trait_range(v, T, sn.n_snp_tiles, c->n_cu);
-    a.ring = use_ring(v, T);
+    a.M = M; a.n_snp_tiles = sn.n_snp_tiles; a.K = K;
+    apply_tuning(c, K, precision, v, T, sn.n_snp_tiles, &a);
     a.snp_base = snp_base;
 
     if (mode != KRUX_MODE_HITS) {
@@ -575,6 +607,7 @@ krux_status krux_create(krux_ctx** out, int device) {
     krux_ctx* c = new krux_ctx();
     c->device = device;
     c->n_cu = prop.multiProcessorCount;
+    std::snprintf(c->arch, sizeof c->arch, "%.6s", prop.gcnArchName);
     *out = c;
     return KRUX_OK;
 }
@@ -689,8 +722,8 @@ krux_status krux_permute(krux_ctx* c, const int16_t* ranks2, const int64_t* ties
     a.A = rk.A; a.theta = rk.theta; a.row_v = rk.row_v; a.d_nrows = nullptr; a.n_rows = V;
     a.T = std::max<int64_t>(T, 1); a.tiesum = tiesum; a.ranks2 = ranks2; a.perms = perms;
     a.G = sn.G; a.gstride = sn.gstride; a.info = sn.info; a.tile_flags = sn.flags;
-    a.M = M; a.n_snp_tiles = sn.n_snp_tiles; a.K = K; a.tiles_per_range = trait_range(v, V, sn.n_snp_tiles, c->n_cu);
-    a.ring = use_ring(v, V);
+    a.M = M; a.n_snp_tiles = sn.n_snp_tiles; a.K = K;
+    apply_tuning(c, K, KRUX_PREC_FP16, v, V, sn.n_snp_tiles, &a);
     a.hits = nullptr; a.counts = (unsigned long long*)counts;
     a.minp_bits = min_p ? minp : nullptr;
     set_levels(&a, p_cs, n_thr);
@@ -718,6 +751,152 @@ krux_status krux_test_batched(krux_ctx* c, const krux_cohort* co, int32_t n, int
                                   nullptr, (hipStream_t)stream);
         if (s != KRUX_OK) return s;
     }
+    return KRUX_OK;
+}
+
+// ---------------------------------------------------------------- autotuning
+namespace {
+
+const char* prec_name(int p) {
+    return p == KRUX_PREC_FP16 ? "fp16" : p == KRUX_PREC_INT8 ? "int8" : "fp64";
+}
+
+// Candidate configurations of the kernel family serving (K, precision).
+std::vector<Tuning> tuning_candidates(const Variant& v) {
+    std::vector<Tuning> out;
+    if (!v.tiled) {
+        for (int ring = 0; ring <= 1; ++ring)
+            for (int kb : {640, 1280, 2560, 5120}) {
+                Tuning t;
+                t.ring = ring;
+                t.range_kb = kb;
+                out.push_back(t);
+            }
+    } else {
+        for (int g = 0; g <= 1; ++g) {
+            Tuning t;
+            t.grouped = g;
+            out.push_back(t);
+        }
+    }
+    return out;
+}
+
+// One line of the cache file: {"arch": "gfx950", "K": 102, "precision": "fp16",
+// "mode": "hits", "ring": 0, "range_kb": 2560, "grouped": -1, "ms": 3.41}
+bool parse_tuning_line(const char* line, const char* arch, int* K, int* prec, Tuning* t) {
+    char a[32] = {0}, p[16] = {0}, m[16] = {0};
+    int k = 0, ring = -1, kb = 0, grouped = -1;
+    double ms = 0.0;
+    const int n = std::sscanf(line,
+                              " {\"arch\": \"%31[^\"]\", \"K\": %d, \"precision\": \"%15[^\"]\", "
+                              "\"mode\": \"%15[^\"]\", \"ring\": %d, \"range_kb\": %d, "
+                              "\"grouped\": %d, \"ms\": %lf",
+                              a, &k, p, m, &ring, &kb, &grouped, &ms);
+    if (n != 8 || std::strcmp(a, arch) != 0 || std::strcmp(m, "hits") != 0) return false;
+    if (std::strcmp(p, "fp16") == 0) *prec = KRUX_PREC_FP16;
+    else if (std::strcmp(p, "int8") == 0) *prec = KRUX_PREC_INT8;
+    else return false;
+    *K = k;
+    t->ring = ring; t->range_kb = kb; t->grouped = grouped; t->ms = ms;
+    return true;
+}
+
+}  // namespace
+
+krux_status krux_autotune(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum, int64_t T,
+                          int32_t K, const int8_t* geno, int64_t M, int64_t ld_geno,
+                          int32_t precision, const char* cache_path, double* best_ms,
+                          void* stream) {
+    if (!c) return fail(nullptr, KRUX_ERR_ARG, "ctx is NULL");
+    krux_status s = check_ranks(c, ranks2, tiesum, T, K);
+    if (s != KRUX_OK) return s;
+    if ((s = check_geno(c, geno, M, ld_geno, K)) != KRUX_OK) return s;
+    if (precision != KRUX_PREC_FP16 && precision != KRUX_PREC_INT8)
+        return fail(c, KRUX_ERR_UNSUPPORTED, "only the MFMA paths are tuned");
+    if (T <= 0 || M <= 0) return fail(c, KRUX_ERR_ARG, "empty tuning input");
+    Variant v;
+    if ((s = choose_variant(c, K, precision, &v)) != KRUX_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t cap = 1 << 16;
+    krux_hit* hits = (krux_hit*)ws(c, S_TUNE_HITS, (size_t)cap * sizeof(krux_hit), &s);
+    int64_t* nh = (int64_t*)ws(c, S_TUNE_N, 256, &s);
+    if (s != KRUX_OK) return s;
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    const std::pair<int, int> key{K, precision};
+    const bool had = c->tuned.count(key) != 0;
+    const Tuning before = had ? c->tuned[key] : Tuning();
+    Tuning best;
+    best.ms = -1.0;
+    krux_status err = KRUX_OK;
+    for (const Tuning& cand : tuning_candidates(v)) {
+        c->tuned[key] = cand;
+        auto run = [&]() {
+            return test_impl(c, ranks2, tiesum, T, K, geno, M, ld_geno, 0, 1e-5, KRUX_MODE_HITS,
+                             precision, hits, cap, nh, nullptr, nullptr, nullptr, nullptr, st);
+        };
+        if ((err = run()) != KRUX_OK) break;                 // warmup (grows buffers)
+        if (hipEventRecord(e0, st) != hipSuccess) { err = fail(c, KRUX_ERR_HIP, "event"); break; }
+        const int reps = 3;
+        for (int r = 0; r < reps && err == KRUX_OK; ++r) err = run();
+        if (err != KRUX_OK) break;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            err = fail(c, KRUX_ERR_HIP, "event");
+            break;
+        }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        Tuning t = cand;
+        t.ms = ms / reps;
+        if (best.ms < 0.0 || t.ms < best.ms) best = t;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != KRUX_OK) {
+        if (had) c->tuned[key] = before; else c->tuned.erase(key);
+        return err;
+    }
+    c->tuned[key] = best;
+    if (best_ms) *best_ms = best.ms;
+    if (cache_path) {
+        FILE* f = std::fopen(cache_path, "a");
+        if (!f) return fail(c, KRUX_ERR_ARG, "cannot open %s", cache_path);
+        std::fprintf(f,
+                     "{\"arch\": \"%s\", \"K\": %d, \"precision\": \"%s\", \"mode\": \"hits\", "
+                     "\"ring\": %d, \"range_kb\": %d, \"grouped\": %d, \"ms\": %.6f}\n",
+                     c->arch, K, prec_name(precision), best.ring, best.range_kb, best.grouped,
+                     best.ms);
+        std::fclose(f);
+    }
+    return KRUX_OK;
+}
+
+krux_status krux_load_tuning(krux_ctx* c, const char* cache_path) {
+    if (!c) return fail(nullptr, KRUX_ERR_ARG, "ctx is NULL");
+    if (!cache_path) return fail(c, KRUX_ERR_ARG, "cache_path is NULL");
+    FILE* f = std::fopen(cache_path, "r");
+    if (!f) return fail(c, KRUX_ERR_ARG, "cannot open %s", cache_path);
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+        int K = 0, prec = 0;
+        Tuning t;
+        if (parse_tuning_line(line, c->arch, &K, &prec, &t)) c->tuned[{K, prec}] = t;  // later lines win
+    }
+    std::fclose(f);
+    return KRUX_OK;
+}
+
+krux_status krux_tuning_of(krux_ctx* c, int32_t K, int32_t precision, int32_t* ring,
+                           int32_t* range_kb, int32_t* grouped) {
+    if (!c) return fail(nullptr, KRUX_ERR_ARG, "ctx is NULL");
+    Tuning t;
+    auto it = c->tuned.find({K, precision});
+    if (it != c->tuned.end()) t = it->second;
+    if (ring) *ring = t.ring;
+    if (range_kb) *range_kb = t.range_kb;
+    if (grouped) *grouped = t.grouped;
     return KRUX_OK;
 }
 

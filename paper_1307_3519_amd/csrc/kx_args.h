@@ -47,6 +47,7 @@ struct ScanArgs {
     int K;
     int tiles_per_range;
     int ring;                 // complete-SNP screen: A tiles through the block's LDS ring
+    int group_items;          // tiled kernel: XCD-grouped item order
     int want_flag;            // process SNP tiles with this flag; -1 = all
     float inv_hc[3];          // screen level: 1/H_c(df), [0] = 0
     double hc[kMaxLevels][2]; // exact thresholds per level, df = 1, 2

@@ -114,7 +114,7 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
     // (trait block, SNP block) items: the group's A and B slices stay in that
     // XCD's L2 while its blocks share them.  Without a multiple of 8 blocks,
     // plain row-major order.
-    const bool grouped = (gridDim.x % 8) == 0 && gridDim.x >= 64;
+    const bool grouped = a.group_items && (gridDim.x % 8) == 0 && gridDim.x >= 64;
     const int64_t per_xcd = gridDim.x / 8;
     const int64_t GT = 8, GS = grouped ? per_xcd / 8 : 1;
     const int64_t n_gt = (n_tb + GT - 1) / GT, n_gs = (n_sb + GS - 1) / GS;

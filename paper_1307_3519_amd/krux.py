@@ -22,7 +22,8 @@ _MODE = {"hits": MODE_HITS, "full": MODE_FULL, "sums": MODE_SUMS}
 
 EXPORTS = ("krux_create", "krux_destroy", "krux_last_error", "krux_threshold",
            "krux_rank", "krux_test", "krux_permute", "krux_test_batched",
-           "krux_timer_start", "krux_timer_read")
+           "krux_timer_start", "krux_timer_read", "krux_autotune", "krux_load_tuning",
+           "krux_tuning_of")
 
 
 class KruxError(RuntimeError):
@@ -77,6 +78,14 @@ def library():
     lib.krux_timer_read.restype = ctypes.c_int
     lib.krux_timer_read.argtypes = [P, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64)]
+    lib.krux_autotune.restype = ctypes.c_int
+    lib.krux_autotune.argtypes = [P, P, P, i64, i32, P, i64, i64, i32, ctypes.c_char_p,
+                                  ctypes.POINTER(ctypes.c_double), P]
+    lib.krux_load_tuning.restype = ctypes.c_int
+    lib.krux_load_tuning.argtypes = [P, ctypes.c_char_p]
+    lib.krux_tuning_of.restype = ctypes.c_int
+    lib.krux_tuning_of.argtypes = [P, i32, i32, ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     _lib = lib
     return lib
 
@@ -136,6 +145,29 @@ class Context:
         n = ctypes.c_int64()
         self._check(self.lib.krux_timer_read(self.h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    # ------------------------------------------------------------------ tuning
+    def autotune(self, ranks2, tiesum, geno, precision="fp16", cache_path=None):
+        """Times every launch configuration for (K, precision) on these inputs
+        and keeps the fastest in the context; -> best milliseconds per call."""
+        T, K = ranks2.shape
+        M = geno.shape[0]
+        ms = ctypes.c_double()
+        self._check(self.lib.krux_autotune(
+            self.h, _ptr(ranks2), _ptr(tiesum), T, K, _ptr(geno), M,
+            geno.stride(0) if M else K, _PREC[precision],
+            cache_path.encode() if cache_path else None, ctypes.byref(ms), _stream()))
+        return ms.value
+
+    def load_tuning(self, cache_path):
+        self._check(self.lib.krux_load_tuning(self.h, cache_path.encode()))
+
+    def tuning_of(self, K, precision="fp16"):
+        """-> dict(ring, range_kb, grouped) in use for (K, precision)."""
+        r, kb, g = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.lib.krux_tuning_of(self.h, K, _PREC[precision], ctypes.byref(r),
+                                            ctypes.byref(kb), ctypes.byref(g)))
+        return dict(ring=r.value, range_kb=kb.value, grouped=g.value)
 
     # ------------------------------------------------------------------ rank
     def rank(self, expr, out=None):

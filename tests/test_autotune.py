@@ -1,0 +1,64 @@
+"""Autotuner: the chosen launch configuration is reported, persisted in the
+cache file, reloaded by a fresh context, and does not change any result."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1307_3519_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _inputs(seed, T, K, M, p_missing=0.0):
+    rs = datagen.streams(seed)
+    x = datagen.inject_ties(rs["ties"], datagen.to_expression(
+        datagen.log_normal_z(rs["expr"], T, K)), 0.05)
+    g, _ = datagen.genotypes(rs["geno"], M, K)
+    g = datagen.set_missing(rs["missing"], g, p_missing)
+    return x, g
+
+
+@pytest.mark.parametrize("K,prec,pm", [(102, "fp16", 0.0), (77, "int8", 0.02), (233, "fp16", 0.01)])
+def test_autotune_choice_persists_and_keeps_results(tmp_path, K, prec, pm):
+    from paper_1307_3519_amd import krux
+    print("[case] autotune", K, prec, pm, flush=True)
+    T, M = 150, 700
+    x, g = _inputs(50 + K, T, K, M, pm)
+    cache = str(tmp_path / "tune.jsonl")
+    ctx = krux.Context(0)
+    try:
+        r, ts, _ = ctx.rank(_dev(x))
+        gd = _dev(g)
+        assert ctx.tuning_of(K, prec) == dict(ring=-1, range_kb=0, grouped=-1)
+        ms = ctx.autotune(r, ts, gd, precision=prec, cache_path=cache)
+        assert ms > 0.0
+        chosen = ctx.tuning_of(K, prec)
+        if K <= 128:
+            assert chosen["ring"] in (0, 1) and chosen["range_kb"] in (640, 1280, 2560, 5120)
+        else:
+            assert chosen["grouped"] in (0, 1)
+        res = ctx.test(r, ts, gd, p_c=0.01, precision=prec, hit_capacity=1 << 14, min_p=True)
+        torch.cuda.synchronize()
+        n, h = krux.unpack_hits(res)
+        o = oracle.scan(x, g, p_cs=(0.01,), hits=True, min_p=True)
+        assert n == o["n_hits"]
+        assert np.array_equal(h["trait"], o["hits"]["trait"])
+        assert np.array_equal(h["snp"], o["hits"]["snp"])
+        mp = res["min_p"].cpu().numpy()
+        assert np.all(np.abs(mp - o["min_p"]) <= np.maximum(1e-10 * np.abs(o["min_p"]), 1e-300))
+    finally:
+        ctx.close()
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 1 and '"K": %d' % K in lines[0]
+    ctx2 = krux.Context(0)
+    try:
+        ctx2.load_tuning(cache)
+        assert ctx2.tuning_of(K, prec) == chosen
+        assert ctx2.tuning_of(K + 1, prec) == dict(ring=-1, range_kb=0, grouped=-1)
+    finally:
+        ctx2.close()
