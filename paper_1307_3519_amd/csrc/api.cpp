@@ -38,7 +38,8 @@ struct Buf {
 // Launch configuration chosen by krux_autotune for one (K, precision).
 // -1 / 0: the built-in rule.
 struct Tuning {
-    int ring = -1;       // SNP-stationary kernel: 1 = LDS ring, 0 = register double buffer
+    int ring = -1;       // SNP-stationary kernel: 0 register double buffer, 1 LDS ring,
+                         // 2 LDS ring without the two-tile pipeline (3 waves per SIMD)
     int range_kb = 0;    // SNP-stationary kernel: trait-range operand budget
     int grouped = -1;    // tiled kernel: XCD-grouped item order
     double ms = 0.0;     // time of the tuning run
@@ -210,9 +211,12 @@ krux_status prep_ranks(krux_ctx* c, const Variant& v, const int16_t* ranks2, con
     a.ranks2 = ranks2; a.tiesum = tiesum; a.perms = perms; a.rows = rows; a.d_nrows = d_nrows;
     a.n_rows = n_rows; a.n_alloc_rows = n_alloc; a.T = T; a.K = K; a.ks = v.ks;
     a.A = out->A; a.A_hi = out->A_hi; a.theta = out->theta; a.row_v = out->row_v;
+    // the prep kernel also clears the candidate counters of the scan that follows it
+    a.zero = (unsigned long long*)ws(c, S_NCAND, 256, &s);
+    a.n_zero = 2;
+    if (s != KRUX_OK) return s;
     int64_t total = n_tiles * v.ks * kx::kWave;
     int grid = (int)std::min<int64_t>(ceil_div(total, 256), (int64_t)c->n_cu * 16);
-    HIP_TRY(c, kx_launch_fill_i32((int32_t*)out->theta, n_tiles, 0x7F800000, st));  // +inf
     HIP_TRY(c, kx_launch_prep(&a, v.elem == kx::I8 ? 1 : 0, std::max(grid, 1), st));
     return KRUX_OK;
 }
@@ -298,15 +302,14 @@ int trait_range(const Variant& v, int64_t n_rows, int64_t n_snp_tiles, int n_cu,
     return (int)std::min<int64_t>(tpr, 1 << 20);
 }
 
-// Pipeline of the SNP-stationary screen kernel.  Every wave reads each A
-// tile of its range from L2; when the operand is large (many trait ranges,
-// each shared by few blocks at a time) those reads dominate, and the block's
-// LDS ring, which reads a tile once per block, is faster (200 permutations x
-// 20,000 traits: 1.5x); for a few MB of operand the register double buffer
-// without block barriers is a few percent faster.
+// Pipeline of the SNP-stationary screen kernel: the A tiles come through
+// the block's LDS ring (one L2 read per block instead of one per wave), one
+// tile at a time with three waves per SIMD (2), which on the paper-scale
+// workload beats the register double buffer (0) by ~6 % and the two-tile
+// pipelined ring at two waves per SIMD (1) by ~7 %.
 int use_ring(const Variant& v, int64_t n_rows) {
-    const int64_t bytes = ceil_div(n_rows, kx::kTile) * (int64_t)v.ks * kx::kWave * 16;
-    return !v.tiled && bytes > ((int64_t)16 << 20) ? 1 : 0;
+    (void)n_rows;
+    return v.tiled ? 0 : 2;
 }
 
 // Launch parameters of a scan: the autotuned configuration for (K,
@@ -364,9 +367,8 @@ krux_status run_screen(krux_ctx* c, kx::ScanArgs a, const Variant& v, const Colu
     // the pairs, at most 2^26 entries (512 MB); the rest are evaluated in the scan
     a.mcand_cap = std::min<int64_t>(std::max<int64_t>(n_rows_max * a.M / 16, 1 << 16), 1LL << 26);
     a.mcand = (int2*)ws(c, S_MCAND, (size_t)a.mcand_cap * sizeof(int2), &s);
-    a.n_mcand = a.n_cand + 1;
+    a.n_mcand = a.n_cand + 1;      // both counters were cleared by the preceding prep kernel
     if (s != KRUX_OK) return s;
-    HIP_TRY(c, kx_launch_fill_u64(a.n_cand, 2, 0ull, st));
     a.want_flag = 0;
     // timed: one event pair around each of the two scan launches
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -386,9 +388,7 @@ krux_status run_screen(krux_ctx* c, kx::ScanArgs a, const Variant& v, const Colu
     if (ev[2]) HIP_TRY(c, hipEventRecord(ev[2], st));
     if ((s = launch_scan(c, a, v, col, A_hi, kx::MISS3, kx::SCREEN, grid, st)) != KRUX_OK) return s;
     if (ev[3]) HIP_TRY(c, hipEventRecord(ev[3], st));
-    HIP_TRY(c, kx_launch_candidates(&a, (int)std::min<int64_t>(ceil_div(a.cand_cap, 256),
-                                                                 (int64_t)c->n_cu * 8), st));
-    HIP_TRY(c, kx_launch_missing(&a, c->n_cu * 8, st));
+    HIP_TRY(c, kx_launch_exact(&a, c->n_cu * 8, st));
     return KRUX_OK;
 }
 
@@ -765,7 +765,7 @@ const char* prec_name(int p) {
 std::vector<Tuning> tuning_candidates(const Variant& v) {
     std::vector<Tuning> out;
     if (!v.tiled) {
-        for (int ring = 0; ring <= 1; ++ring)
+        for (int ring = 0; ring <= 2; ++ring)
             for (int kb : {640, 1280, 2560, 5120}) {
                 Tuning t;
                 t.ring = ring;

@@ -20,6 +20,8 @@ struct PrepArgs {
     void* A_hi;              // int8 byte split: high plane, else null
     float* theta;            // [tiles] min over the tile's rows of K^3 - K - sumT
     int32_t* row_v;          // [tiles * 32]
+    unsigned long long* zero;  // counters cleared by the kernel (the next scan's), or null
+    int n_zero;
 };
 
 enum { DIAG = 0, PLAIN = 1, MISS3 = 2 };
@@ -46,7 +48,8 @@ struct ScanArgs {
     int64_t n_snp_tiles;
     int K;
     int tiles_per_range;
-    int ring;                 // complete-SNP screen: A tiles through the block's LDS ring
+    int ring;                 // complete-SNP screen: 0 register double buffer, 1 block LDS
+                              // ring (pipelined), 2 LDS ring, one tile at a time, 3 waves/SIMD
     int group_items;          // tiled kernel: XCD-grouped item order
     int want_flag;            // process SNP tiles with this flag; -1 = all
     float inv_hc[3];          // screen level: 1/H_c(df), [0] = 0

@@ -32,8 +32,7 @@ hipError_t kx_launch_bits_to_double(const unsigned long long* bits, int64_t n, d
                                     hipStream_t st);
 hipError_t kx_launch_scan(const kx::ScanArgs* a, int elem, int ks, int form, int mode, int grid,
                           hipStream_t st);
-hipError_t kx_launch_candidates(const kx::ScanArgs* a, int grid, hipStream_t st);
-hipError_t kx_launch_missing(const kx::ScanArgs* a, int grid, hipStream_t st);
+hipError_t kx_launch_exact(const kx::ScanArgs* a, int grid, hipStream_t st);
 hipError_t kx_launch_tiled_f16(const kx::ScanArgs* a, const kx::TiledArgs* ta, int form, int mode,
                                int grid, hipStream_t st);
 hipError_t kx_launch_tiled_i8(const kx::ScanArgs* a, const kx::TiledArgs* ta, int form, int mode,

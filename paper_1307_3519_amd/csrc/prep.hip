@@ -65,6 +65,8 @@ __device__ inline void count_codes(uint32_t w, int& c0, int& c1, int& c2, int& c
 constexpr int kPackRows = 256;
 constexpr int kPackCols = 128;
 constexpr int kPackLds = kPackCols + 4;     // padded LDS row: conflict-free dword reads
+constexpr int kPackUnroll = 16;
+static_assert((kPackRows * kPackCols) % (256 * kPackUnroll) == 0, "whole batches");
 
 __global__ __launch_bounds__(256) void pack_snps(const int8_t* __restrict__ geno, int64_t M,
                                                  int64_t ld, int K, int64_t m_pad, int gstride,
@@ -79,18 +81,33 @@ __global__ __launch_bounds__(256) void pack_snps(const int8_t* __restrict__ geno
     int c0 = 0, c1 = 0, c2 = 0, c3 = 0;
     for (int col0 = 0; col0 < gstride; col0 += kPackCols) {
         const int w = gstride - col0 < kPackCols ? gstride - col0 : kPackCols;
-        for (int idx = tid; idx < kPackRows * kPackCols; idx += 256) {
-            const int r = idx / kPackCols, cc = idx % kPackCols;
-            if (cc >= w) continue;
-            const int64_t m = m0 + r;
-            const int col = col0 + cc;
-            int8_t code = kMissingCode;
-            if (m < M && col < K) {
-                const int8_t g = geno[m * ld + col];
-                code = (g >= 0 && g <= 2) ? g : kMissingCode;
+        // batches of kPackUnroll independent byte loads per thread, so that a
+        // thread waits once per batch rather than once per byte
+        for (int base = 0; M > 0 && base < kPackRows * kPackCols; base += 256 * kPackUnroll) {
+            int8_t g[kPackUnroll];
+#pragma unroll
+            for (int u = 0; u < kPackUnroll; ++u) {
+                // branch-free: the address is clamped into the matrix (M >= 1
+                // here) and out-of-range elements are replaced afterwards
+                const int idx = base + u * 256 + tid;
+                const int r = idx / kPackCols, cc = idx % kPackCols;
+                const int64_t m = m0 + r;
+                const int col = col0 + cc;
+                const int64_t mc = m < M ? m : M - 1;
+                const int colc = col < K ? col : K - 1;
+                const int8_t raw = geno[mc * ld + colc];
+                g[u] = (cc < w && m < M && col < K) ? raw : (int8_t)kMissingCode;
             }
-            s_bytes[r * kPackLds + cc] = (uint8_t)code;
-            if (m < m_pad) gp[m * (int64_t)gstride + col] = code;
+#pragma unroll
+            for (int u = 0; u < kPackUnroll; ++u) {
+                const int idx = base + u * 256 + tid;
+                const int r = idx / kPackCols, cc = idx % kPackCols;
+                if (cc >= w) continue;
+                const int64_t m = m0 + r;
+                const int8_t code = (g[u] >= 0 && g[u] <= 2) ? g[u] : (int8_t)kMissingCode;
+                s_bytes[r * kPackLds + cc] = (uint8_t)code;
+                if (m < m_pad) gp[m * (int64_t)gstride + col0 + cc] = code;
+            }
         }
         __syncthreads();
         // this thread's row: only the K real columns count
@@ -148,8 +165,21 @@ __device__ inline int64_t count_rows(const PrepArgs& a) {
     return a.n_rows;
 }
 
-// fp16 operand: one thread per (tile, k-step, lane) writes 8 halves.
+__device__ inline float wave_min(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ inline void clear_counters(const PrepArgs& a) {
+    if (a.zero && blockIdx.x == 0 && (int)threadIdx.x < a.n_zero) a.zero[threadIdx.x] = 0ull;
+}
+
+// fp16 operand: one thread per (tile, k-step, lane) writes 8 halves.  The
+// grid-stride loop keeps the 64 threads of one (tile, k-step) in one wave
+// (the stride is a multiple of 64).
 __global__ __launch_bounds__(256) void prep_ranks_f16(PrepArgs a) {
+    clear_counters(a);
     const int64_t n_tiles = (a.n_alloc_rows + kTile - 1) / kTile;
     const int64_t total = n_tiles * a.ks * kWave;
     const int64_t nr = count_rows(a);
@@ -172,17 +202,20 @@ __global__ __launch_bounds__(256) void prep_ranks_f16(PrepArgs a) {
             }
         }
         A[i] = h;
-        if (s == 0 && lane < 32) {
+        if (s == 0) {
+            // the 64 threads of (tile, k-step 0) are one wave: lanes 0..31 hold
+            // the tile's rows; the wave's minimum is the tile's threshold
             float th = __builtin_inff();
-            int32_t rv = -1;
-            if (r < nr) {
+            if (lane < 32 && r < nr) {
                 int64_t v = a.rows ? a.rows[r] : r;
                 int64_t E = cube_minus(a.K) - a.tiesum[v % a.T];
                 if (E > 0) th = (float)E;
-                rv = (int32_t)v;
+                a.row_v[r] = (int32_t)v;
+            } else if (lane < 32) {
+                a.row_v[r] = -1;
             }
-            atomicMin((unsigned int*)&a.theta[tile], __float_as_uint(th));  // th > 0
-            a.row_v[r] = rv;
+            th = wave_min(th);
+            if (lane == 0) a.theta[tile] = th;
         }
     }
 }
@@ -190,6 +223,7 @@ __global__ __launch_bounds__(256) void prep_ranks_f16(PrepArgs a) {
 // int8 operand: 16 samples per lane per k-step of 32.  With A_hi set, the
 // centred rank is split c = 128 h + l, l in [0, 127].
 __global__ __launch_bounds__(256) void prep_ranks_i8(PrepArgs a) {
+    clear_counters(a);
     const int64_t n_tiles = (a.n_alloc_rows + kTile - 1) / kTile;
     const int64_t total = n_tiles * a.ks * kWave;
     const int64_t nr = count_rows(a);
@@ -232,17 +266,20 @@ __global__ __launch_bounds__(256) void prep_ranks_i8(PrepArgs a) {
         }
         A[i] = wl;
         if (Ah) Ah[i] = wh;
-        if (s == 0 && lane < 32) {
+        if (s == 0) {
+            // the 64 threads of (tile, k-step 0) are one wave: lanes 0..31 hold
+            // the tile's rows; the wave's minimum is the tile's threshold
             float th = __builtin_inff();
-            int32_t rv = -1;
-            if (r < nr) {
+            if (lane < 32 && r < nr) {
                 int64_t v = a.rows ? a.rows[r] : r;
                 int64_t E = cube_minus(a.K) - a.tiesum[v % a.T];
                 if (E > 0) th = (float)E;
-                rv = (int32_t)v;
+                a.row_v[r] = (int32_t)v;
+            } else if (lane < 32) {
+                a.row_v[r] = -1;
             }
-            atomicMin((unsigned int*)&a.theta[tile], __float_as_uint(th));  // th > 0
-            a.row_v[r] = rv;
+            th = wave_min(th);
+            if (lane == 0) a.theta[tile] = th;
         }
     }
 }

@@ -1,10 +1,14 @@
-// scan_cand.hip -- launcher of the exact evaluation of screened pairs.
+// scan_cand.hip -- exact evaluation of the pairs that passed the screen.
 #include "scan_kernel.h"
 
 namespace kx {
 
-// Exact evaluation of the screened pairs collected by scan_kernel.
-__global__ __launch_bounds__(256) void scan_candidates(ScanArgs a) {
+// One launch evaluates both buffers filled by the scan kernels:
+//  * candidates of complete SNPs, one lane each: exact H from the pair's
+//    exact MFMA column values (eq. (2) with the tie factor), p, hit / min p;
+//  * pairs of SNPs with missing genotypes, one wave each: the ranks are
+//    re-derived over the kept samples (coop_exact), then the same.
+__global__ __launch_bounds__(256) void scan_exact(ScanArgs a) {
     int64_t n = (int64_t)*a.n_cand;
     if (n > a.cand_cap) n = a.cand_cap;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -13,19 +17,15 @@ __global__ __launch_bounds__(256) void scan_candidates(ScanArgs a) {
         eval_candidate(a, (int64_t)e.x, (int64_t)(e.y & kCandSnp), __uint_as_float(e.z),
                        __uint_as_float(e.w), e.y & ~kCandSnp);
     }
-}
-
-// Exact evaluation of the screened pairs of SNPs with missing genotypes
-// (re-ranking over the kept samples), one pair per wave at a time.
-__global__ __launch_bounds__(256) void scan_missing(ScanArgs a) {
+    if (!a.mcand) return;
     extern __shared__ int16_t s_buf[];   // per wave 2K entries
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int16_t* sb = s_buf + wave * 2 * a.K;
-    int64_t n = (int64_t)*a.n_mcand;
-    if (n > a.mcand_cap) n = a.mcand_cap;
+    int64_t nm = (int64_t)*a.n_mcand;
+    if (nm > a.mcand_cap) nm = a.mcand_cap;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    for (int64_t e = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; e < n; e += waves) {
+    for (int64_t e = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; e < nm; e += waves) {
         const int2 q = a.mcand[e];
         const int64_t v = a.row_v[q.x];
         if (v < 0) continue;             // padding row (uniform per wave)
@@ -38,13 +38,8 @@ __global__ __launch_bounds__(256) void scan_missing(ScanArgs a) {
 
 }  // namespace kx
 
-extern "C" hipError_t kx_launch_missing(const kx::ScanArgs* a, int grid, hipStream_t st) {
+extern "C" hipError_t kx_launch_exact(const kx::ScanArgs* a, int grid, hipStream_t st) {
     const size_t lds = (size_t)4 * 2 * a->K * sizeof(int16_t);
-    hipLaunchKernelGGL(kx::scan_missing, dim3(grid), dim3(256), lds, st, *a);
-    return hipGetLastError();
-}
-
-extern "C" hipError_t kx_launch_candidates(const kx::ScanArgs* a, int grid, hipStream_t st) {
-    hipLaunchKernelGGL(kx::scan_candidates, dim3(grid), dim3(256), 0, st, *a);
+    hipLaunchKernelGGL(kx::scan_exact, dim3(grid), dim3(256), lds, st, *a);
     return hipGetLastError();
 }

@@ -386,7 +386,7 @@ void scan_kernel(ScanArgs a) {
     using acc_t = typename T_::acc;
     constexpr int NC = FORM == MISS3 ? 3 : 2;
     constexpr bool QUEUE = FORM == MISS3;
-    constexpr bool RING = PF == 3 && MODE == SCREEN && FORM != MISS3;
+    constexpr bool RING = (PF == 3 || PF == 4) && MODE == SCREEN && FORM != MISS3;
     // fp16 DIAG: second column scaled by q (diag_zscale), screen Y^2 + Z^2
     constexpr bool ZS = E == F16 && FORM == DIAG;
     constexpr uint32_t kDiagFlags = ZS ? kCandZs : 0u;
@@ -396,7 +396,7 @@ void scan_kernel(ScanArgs a) {
     // copy of the arguments for the out-of-line fallback (taking the address
     // of the kernel argument itself would move it to the stack)
     __shared__ ScanArgs s_args;
-    // LDS ring of A tiles shared by the block's waves (PF == 3): 4 slots
+    // LDS ring of A tiles shared by the block's waves (PF == 3, 4): 4 slots
     __shared__ frag s_ring[RING ? 4 * KS * kWave : 1];
     if (threadIdx.x == 0) s_args = a;
     __syncthreads();
@@ -664,13 +664,27 @@ void scan_kernel(ScanArgs a) {
             };
             auto thr = [&](const int64_t tt) { return cload(a.theta + (tt < t1 ? tt : t1 - 1)); };
             frag Af[KS];
-            acc_t c0[NC], c1[NC];
             // every wave is done with the ring of the previous item (its last
             // reads fed MFMAs that have issued)
             __builtin_amdgcn_s_waitcnt(0);
             block_barrier();
             issue(t0);
             issue(t0 + 1);
+            if constexpr (PF == 4) {
+                // one accumulator set, tile after tile: the MFMA / screen overlap
+                // comes from the other waves of the SIMD (three per SIMD)
+                for (int64_t t = t0; t < t1; ++t) {
+                    issue(t + 2);
+                    arrive();
+                    lread(t, Af);
+                    const float th = thr(t);
+                    acc_t c[NC];
+                    mma_tile(Af, c);
+                    if (__any(screen_max(c, th) > 0.0f)) screen_cands(t, c, th);
+                }
+                __builtin_amdgcn_s_waitcnt(0);
+            } else {
+            acc_t c0[NC], c1[NC];
             issue(t0 + 2);
             arrive();
             lread(t0, Af);
@@ -706,6 +720,7 @@ void scan_kernel(ScanArgs a) {
             }
             // the copies past the range end are still landing in the ring
             __builtin_amdgcn_s_waitcnt(0);
+            }
         } else if constexpr (PF == 2 && MODE == SCREEN && FORM != MISS3) {
             // Software pipeline over pairs of tiles: the MFMA chain of the next
             // tile is issued in the same basic block as the fp32 screen of the

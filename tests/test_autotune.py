@@ -62,3 +62,34 @@ def test_autotune_choice_persists_and_keeps_results(tmp_path, K, prec, pm):
         assert ctx2.tuning_of(K + 1, prec) == dict(ring=-1, range_kb=0, grouped=-1)
     finally:
         ctx2.close()
+
+
+@pytest.mark.parametrize("ring", [0, 1, 2])
+@pytest.mark.parametrize("prec", ["fp16", "int8"])
+def test_every_pipeline_matches_oracle(tmp_path, ring, prec):
+    # each SNP-stationary pipeline forced through a cache entry: register
+    # double buffer, LDS ring (pipelined), LDS ring one tile at a time
+    from paper_1307_3519_amd import krux
+    print("[case] pipeline", ring, prec, flush=True)
+    K, T, M = 102, 300, 900
+    x, g = _inputs(70 + ring, T, K, M, 0.01)
+    cache = tmp_path / "tune.jsonl"
+    cache.write_text('{"arch": "gfx950", "K": %d, "precision": "%s", "mode": "hits", '
+                     '"ring": %d, "range_kb": 640, "grouped": -1, "ms": 0}\n' % (K, prec, ring))
+    ctx = krux.Context(0)
+    try:
+        ctx.load_tuning(str(cache))
+        assert ctx.tuning_of(K, prec)["ring"] == ring
+        r, ts, _ = ctx.rank(_dev(x))
+        res = ctx.test(r, ts, _dev(g), p_c=0.01, precision=prec, hit_capacity=1 << 14, min_p=True)
+        torch.cuda.synchronize()
+        n, h = krux.unpack_hits(res)
+        o = oracle.scan(x, g, p_cs=(0.01,), hits=True, min_p=True)
+        assert n == o["n_hits"] and n > 0
+        assert np.array_equal(h["trait"], o["hits"]["trait"])
+        assert np.array_equal(h["snp"], o["hits"]["snp"])
+        assert np.array_equal(h["H"], o["hits"]["H"])
+        mp = res["min_p"].cpu().numpy()
+        assert np.all(np.abs(mp - o["min_p"]) <= np.maximum(1e-10 * np.abs(o["min_p"]), 1e-300))
+    finally:
+        ctx.close()
