@@ -1,7 +1,7 @@
 // rank.hip -- per-trait doubled midranks and tie term (the ranking step of
 // the paper's input-data section and the tie term of its tied-data section).
 //
-// One workgroup per trait row.  The row is sorted in LDS as 64-bit words
+// K > 256: one workgroup per trait row.  The row is sorted in LDS as 64-bit words
 // (order-preserving 32-bit key of the value << 32 | sample index) by a
 // bitonic network; a value's tie run [lo, hi) in the sorted row then gives
 //   less = lo, eq = hi - lo,  a = 2 less + eq + 1 = lo + hi + 1,
@@ -89,12 +89,93 @@ __global__ __launch_bounds__(NT) void rank_rows(const float* __restrict__ expr, 
     }
 }
 
+// K <= 256: one wave per row, ranks by counting.  The row's keys sit in
+// LDS; every lane takes up to four samples and counts, over all samples,
+// the keys below and equal to each (a broadcast LDS read per sample), so
+//   a = 2 less + eq + 1,  sumT += eq^2 - 1,
+// the same numbers as the sort above.  NaN (the largest key) is neither
+// below nor equal to an observed value.
+constexpr int kCountMaxK = 256;
+
+template <int NJ>   // samples per lane: ceil(K / 64)
+__global__ __launch_bounds__(256) void rank_rows_count(const float* __restrict__ expr,
+                                                       int64_t T, int K, int64_t ld,
+                                                       int16_t* __restrict__ ranks2,
+                                                       int64_t* __restrict__ tiesum,
+                                                       int32_t* __restrict__ nvalid) {
+    __shared__ uint4 s_keys[4][kCountMaxK / 4];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint32_t* keys = (uint32_t*)s_keys[wave];
+    const int K4 = (K + 3) & ~3;          // padded with the NaN key (never below or equal)
+    const int64_t n_waves = (int64_t)gridDim.x * 4;
+    for (int64_t row = (int64_t)blockIdx.x * 4 + wave; row < T; row += n_waves) {
+        const float* x = expr + row * ld;
+        uint32_t mine[NJ];
+        int n_valid = 0;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const int k = lane + 64 * j;
+            const uint32_t key = k < K ? order_key(x[k]) : 0xFFFFFFFFu;
+            if (k < K4) keys[k] = key;
+            mine[j] = key;
+            n_valid += __popcll(__ballot(k < K && key != 0xFFFFFFFFu));
+        }
+        __builtin_amdgcn_wave_barrier();
+        int less[NJ], eq[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) { less[j] = 0; eq[j] = 0; }
+        const uint4* k4 = s_keys[wave];
+        for (int i = 0; i < K4 / 4; ++i) {
+            const uint4 q = k4[i];        // broadcast read of four keys
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                less[j] += (q.x < mine[j]) + (q.y < mine[j]) + (q.z < mine[j]) + (q.w < mine[j]);
+                eq[j] += (q.x == mine[j]) + (q.y == mine[j]) + (q.z == mine[j]) + (q.w == mine[j]);
+            }
+        }
+        unsigned long long ts = 0;
+        int16_t* r = ranks2 + row * (int64_t)K;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const int k = lane + 64 * j;
+            if (k < K) {
+                if (mine[j] == 0xFFFFFFFFu) {
+                    r[k] = 0;
+                } else {
+                    r[k] = (int16_t)(2 * less[j] + eq[j] + 1);
+                    ts += (unsigned long long)((long long)eq[j] * eq[j] - 1);
+                }
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) ts += __shfl_xor(ts, o, 64);
+        if (lane == 0) {
+            tiesum[row] = (int64_t)ts;
+            if (nvalid) nvalid[row] = n_valid;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 }  // namespace kx
 
 // Host launcher (called from the C ABI layer).
 extern "C" hipError_t kx_launch_rank(const float* expr, int64_t T, int K, int64_t ld,
                                      int16_t* ranks2, int64_t* tiesum, int32_t* nvalid,
                                      int max_blocks, hipStream_t stream) {
+    if (T <= 0) return hipSuccess;
+    if (K <= kx::kCountMaxK) {
+        int64_t grid = (T + 3) / 4;
+        grid = grid < max_blocks ? grid : max_blocks;
+        const int nj = (K + 63) / 64;
+        auto kern = nj == 1 ? kx::rank_rows_count<1>
+                  : nj == 2 ? kx::rank_rows_count<2>
+                  : nj == 3 ? kx::rank_rows_count<3> : kx::rank_rows_count<4>;
+        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), 0, stream, expr, T, K, ld, ranks2,
+                           tiesum, nvalid);
+        return hipGetLastError();
+    }
     int kp2 = 2;
     while (kp2 < K) kp2 <<= 1;
     size_t lds = (size_t)kp2 * sizeof(uint64_t);

@@ -39,7 +39,7 @@ def test_autotune_choice_persists_and_keeps_results(tmp_path, K, prec, pm):
         assert ms > 0.0
         chosen = ctx.tuning_of(K, prec)
         if K <= 128:
-            assert chosen["ring"] in (0, 1) and chosen["range_kb"] in (640, 1280, 2560, 5120)
+            assert chosen["ring"] in (0, 1, 2) and chosen["range_kb"] in (640, 1280, 2560, 5120)
         else:
             assert chosen["grouped"] in (0, 1)
         res = ctx.test(r, ts, gd, p_c=0.01, precision=prec, hit_capacity=1 << 14, min_p=True)
