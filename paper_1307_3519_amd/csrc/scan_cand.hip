@@ -18,10 +18,10 @@ __global__ __launch_bounds__(256) void scan_exact(ScanArgs a) {
                        __uint_as_float(e.w), e.y & ~kCandSnp);
     }
     if (!a.mcand) return;
-    extern __shared__ int16_t s_buf[];   // per wave 2K entries
+    extern __shared__ __attribute__((aligned(16))) int16_t s_buf[];   // per wave coop_lds_entries(K)
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    int16_t* sb = s_buf + wave * 2 * a.K;
+    int16_t* sb = s_buf + wave * coop_lds_entries(a.K);
     int64_t nm = (int64_t)*a.n_mcand;
     if (nm > a.mcand_cap) nm = a.mcand_cap;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
@@ -39,7 +39,7 @@ __global__ __launch_bounds__(256) void scan_exact(ScanArgs a) {
 }  // namespace kx
 
 extern "C" hipError_t kx_launch_exact(const kx::ScanArgs* a, int grid, hipStream_t st) {
-    const size_t lds = (size_t)4 * 2 * a->K * sizeof(int16_t);
+    const size_t lds = (size_t)4 * kx::coop_lds_entries(a->K) * sizeof(int16_t);
     hipLaunchKernelGGL(kx::scan_exact, dim3(grid), dim3(256), lds, st, *a);
     return hipGetLastError();
 }

@@ -258,6 +258,24 @@ __device__ inline void stage_candidates(const ScanArgs& a, const ScanArgs* a_lds
 // ranks are below 2^13 for K <= 4095) and the ranks of its missing samples.
 constexpr int kCodeShift = 13;
 constexpr int kRankMask = (1 << kCodeShift) - 1;
+// per-wave LDS of coop_exact, in int16 entries: K samples, max(K, 64) missing
+// ranks, 64 int32 tie counters
+__host__ __device__ inline int coop_lds_entries(int K) { return 2 * K + 64 + 128; }
+
+// Ascending sort of one value per lane across the wave (bitonic network).
+__device__ inline int wave_sort(int v, int lane) {
+#pragma unroll
+    for (int k = 2; k <= kWave; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const int o = __shfl_xor(v, j, 64);
+            const bool up = (lane & k) == 0;
+            const bool lower = (lane & j) == 0;
+            v = (lower == up) ? min(v, o) : max(v, o);
+        }
+    }
+    return v;
+}
 
 __device__ inline double coop_exact(const ScanArgs& a, int64_t v, int64_t m, int16_t* sbuf,
                                     int lane, int* df_out, int64_t* s_out) {
@@ -268,6 +286,7 @@ __device__ inline double coop_exact(const ScanArgs& a, int64_t v, int64_t m, int
     const int8_t* gr = a.G + m * (int64_t)a.gstride;
     uint16_t* sr = (uint16_t*)sbuf;
     int16_t* qb = sbuf + K;
+    int32_t* tc = (int32_t*)(sbuf + 2 * K + 64);   // 4-byte aligned: 2K + 64 is even
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     // one pass over global memory: rank and genotype code of every sample
     for (int k0 = 0; k0 < K; k0 += kWave) {
@@ -290,6 +309,56 @@ __device__ inline double coop_exact(const ScanArgs& a, int64_t v, int64_t m, int
     }
     __builtin_amdgcn_wave_barrier();
     long long ts = a.tiesum[trait];
+    long long s0 = 0, s1 = 0, s2 = 0;
+    if (nq <= kWave) {
+        // Up to 64 missing samples: sort their ranks across the wave, then one
+        // pass over the samples: for sample k, lt / le = number of missing
+        // ranks below / at most a_k (binary search), so its shift is
+        // 2 lt + (le - lt); a sample equal to a missing rank adds one to that
+        // rank's tie-group counter.  A tie group of size t that loses r
+        // members takes (t^3 - t) - ((t-r)^3 - (t-r)) off the tie term.
+        const int qv = wave_sort(lane < nq ? (int)qb[lane] : 0x7FFF, lane);
+        __builtin_amdgcn_wave_barrier();
+        qb[lane] = (int16_t)qv;
+        tc[lane] = 0;
+        __builtin_amdgcn_wave_barrier();
+        for (int k0 = 0; k0 < K; k0 += kWave) {
+            const int k = k0 + lane;
+            if (k < K) {
+                const int x = sr[k];
+                const int code = x >> kCodeShift;
+                const int ak = x & kRankMask;
+                int lo = 0, hi = nq;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (qb[mid] < ak) lo = mid + 1; else hi = mid;
+                }
+                const int below = lo;
+                hi = nq;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (qb[mid] <= ak) lo = mid + 1; else hi = mid;
+                }
+                const int equal = lo - below;
+                if (code != kMissingCode) {
+                    const int ap = ak - 2 * below - equal;
+                    if (code == 0) s0 += ap; else if (code == 1) s1 += ap; else s2 += ap;
+                }
+                if (equal && ts != 0) atomicAdd(&tc[below], 1);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (ts != 0) {
+            long long corr = 0;
+            if (lane < nq && (lane == 0 || qb[lane - 1] != qv)) {
+                int r = 1;
+                while (lane + r < nq && qb[lane + r] == qv) ++r;
+                const long long t = tc[lane];
+                corr = (t * t * t - t) - ((t - r) * (t - r) * (t - r) - (t - r));
+            }
+            ts -= wave_sum64(corr);
+        }
+    } else {
     if (ts != 0) {
         for (int qi = 0; qi < nq; ++qi) {
             const int aj = qb[qi];
@@ -306,7 +375,6 @@ __device__ inline double coop_exact(const ScanArgs& a, int64_t v, int64_t m, int
             ts -= 3ll * t * (t - 1);
         }
     }
-    long long s0 = 0, s1 = 0, s2 = 0;
     for (int k0 = 0; k0 < K; k0 += kWave) {
         const int k = k0 + lane;
         const int x = k < K ? sr[k] : (kMissingCode << kCodeShift);
@@ -322,6 +390,7 @@ __device__ inline double coop_exact(const ScanArgs& a, int64_t v, int64_t m, int
             if (code == 0) s0 += ap; else if (code == 1) s1 += ap; else s2 += ap;
         }
     }
+    }
     s0 = wave_sum64(s0); s1 = wave_sum64(s1); s2 = wave_sum64(s2);
     const SnpInfo inf = a.info[m];
     const int64_t kp = K - nq;
@@ -332,6 +401,14 @@ __device__ inline double coop_exact(const ScanArgs& a, int64_t v, int64_t m, int
     s_out[0] = s0; s_out[1] = s1; s_out[2] = s2;
     __builtin_amdgcn_wave_barrier();
     return exact_H(D0, D1, D2, inf.n0, inf.n1, inf.n2, kp, ts, snp_df(inf));
+}
+
+// Out-of-line entry for the scan kernels' own (rare, or FULL / SUMS) use, so
+// that the re-rank's registers do not weigh on the scan loop.
+__device__ __attribute__((noinline)) double coop_exact_call(const ScanArgs& a, int64_t v,
+                                                            int64_t m, int16_t* sbuf, int lane,
+                                                            int* df_out, int64_t* s_out) {
+    return coop_exact(a, v, m, sbuf, lane, df_out, s_out);
 }
 
 // Empties a wave's queue of screened pairs of SNPs with missing genotypes.
@@ -362,7 +439,7 @@ __device__ inline void drain(const ScanArgs& a, int2* queue, int& qn, int16_t* q
         int64_t m = q.y;
         int df;
         int64_t s[3];
-        double H = coop_exact(a, v, m, qbuf, lane, &df, s);
+        double H = coop_exact_call(a, v, m, qbuf, lane, &df, s);
         if (lane == 0) {
             if (MODE == SCREEN) record(a, v, m, H, df);
             else emit_full<MODE>(a, v, m, H, df, s[0], s[1], s[2]);
@@ -400,14 +477,14 @@ void scan_kernel(ScanArgs a) {
     __shared__ frag s_ring[RING ? 4 * KS * kWave : 1];
     if (threadIdx.x == 0) s_args = a;
     __syncthreads();
-    extern __shared__ int16_t s_qbuf[];   // MISS3: per wave 2K entries
+    extern __shared__ __attribute__((aligned(16))) int16_t s_qbuf[];   // MISS3: per wave coop_lds_entries(K)
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
     int2* queue = s_queue[QUEUE ? wave : 0];
     uint4* stage = s_stage[MODE == SCREEN ? wave : 0];
     int sn = 0;
-    int16_t* qbuf = s_qbuf + (QUEUE ? wave * 2 * a.K : 0);
+    int16_t* qbuf = s_qbuf + (QUEUE ? wave * coop_lds_entries(a.K) : 0);
     int qn = 0;
 
     // tile_flags[n_snp_tiles] is set when any SNP has a missing genotype
@@ -798,7 +875,7 @@ namespace kx {
 template <int E, int KS, int FORM, int MODE,
           int PF = (MODE == kx::SCREEN && FORM != kx::MISS3) ? 2 : 0, int WPE = 2>
 inline hipError_t launch_one(const kx::ScanArgs& a, int grid, hipStream_t st) {
-    size_t lds = FORM == kx::MISS3 ? (size_t)kx::kWavesPerBlock * 2 * a.K * sizeof(int16_t) : 0;
+    size_t lds = FORM == kx::MISS3 ? (size_t)kx::kWavesPerBlock * kx::coop_lds_entries(a.K) * sizeof(int16_t) : 0;
     auto kern = kx::scan_kernel<E, KS, FORM, MODE, PF, WPE>;
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 256, lds) != hipSuccess || occ < 1)

@@ -82,7 +82,7 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
     __shared__ int2 s_queue[QUEUE ? kWavesPerBlock : 1][QUEUE ? kQueueCap : 1];
     __shared__ uint4 s_stage[MODE == SCREEN ? kWavesPerBlock : 1][kStageCap];
     __shared__ ScanArgs s_args;
-    extern __shared__ int16_t s_qbuf[];
+    extern __shared__ __attribute__((aligned(16))) int16_t s_qbuf[];
     if (threadIdx.x == 0) s_args = a;
     __syncthreads();
 
@@ -91,7 +91,7 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
     int2* queue = s_queue[QUEUE ? wave : 0];
     uint4* stage = s_stage[MODE == SCREEN ? wave : 0];
     int sn = 0, qn = 0;
-    int16_t* qbuf = s_qbuf + (QUEUE ? wave * 2 * a.K : 0);
+    int16_t* qbuf = s_qbuf + (QUEUE ? wave * coop_lds_entries(a.K) : 0);
 
     if (a.want_flag == 1 && a.tile_flags[a.n_snp_tiles] == 0) return;
     int64_t n_rows = a.n_rows;
@@ -355,7 +355,7 @@ __global__ __launch_bounds__(256) void expand_columns(const int8_t* __restrict__
 
 template <int E, int FORM, int MODE, bool SPLIT>
 inline hipError_t launch_tiled(const ScanArgs& a, const TiledArgs& ta, int grid, hipStream_t st) {
-    size_t lds = FORM == MISS3 ? (size_t)kWavesPerBlock * 2 * a.K * sizeof(int16_t) : 0;
+    size_t lds = FORM == MISS3 ? (size_t)kWavesPerBlock * coop_lds_entries(a.K) * sizeof(int16_t) : 0;
     auto kern = scan_tiled<E, FORM, MODE, SPLIT>;
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 256, lds) != hipSuccess || occ < 1)

@@ -239,3 +239,23 @@ def test_small_workload_full_matrices(kx):
     assert_H(res["H"].cpu().numpy(), o["H"], "H")
     assert_p(res["p"].cpu().numpy(), o["p"], "p")
     assert np.array_equal(res["H"].cpu().numpy(), o["H"])   # correctly rounded on both sides
+
+
+def test_heavy_missing_per_snp(kx):
+    # SNPs with 0 .. 150 missing samples: the sorted-rank re-rank (up to 64
+    # missing) and the pairwise one (more than 64), ties in every trait
+    say("heavy missing")
+    K, T, M = 233, 50, 40
+    x, g = _inputs(61, T, K, M, tie_frac=0.2)
+    rs = datagen.streams(62)["missing"]
+    for m, nmiss in enumerate([0, 1, 5, 30, 63, 64, 65, 100, 150, 200] * 4):
+        idx = rs.choice(K, size=nmiss, replace=False)
+        g[m, idx] = -1
+    r, ts = _ranks(kx, x)
+    o = oracle.scan(x, g, full=True, p_cs=(0.05,), hits=True, min_p=True)
+    for prec in ("fp16", "int8"):
+        res = kx.test(r, ts, _dev(g), mode="full", precision=prec)
+        torch.cuda.synchronize()
+        assert_H(res["H"].cpu().numpy(), o["H"], prec)
+        assert_p(res["p"].cpu().numpy(), o["p"], prec)
+        _check_hits(kx, x, g, 0.05, prec)
