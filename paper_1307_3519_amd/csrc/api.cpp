@@ -198,8 +198,8 @@ krux_status prep_ranks(krux_ctx* c, const Variant& v, const int16_t* ranks2, con
                        const int32_t* d_nrows, int64_t n_rows, int slotA, int slotTh, int slotRv,
                        hipStream_t st, RankSide* out, int slotAh = -1) {
     krux_status s = KRUX_OK;
-    // the tiled kernel reads whole blocks of 4 trait tiles
-    const int64_t n_alloc = v.tiled ? ceil_div(std::max<int64_t>(n_rows, 1), 128) * 128
+    // the tiled kernel reads whole blocks of up to 8 trait tiles
+    const int64_t n_alloc = v.tiled ? ceil_div(std::max<int64_t>(n_rows, 1), 256) * 256
                                     : std::max<int64_t>(n_rows, 1);
     int64_t n_tiles = ceil_div(n_alloc, kx::kTile);
     out->A = ws(c, slotA, (size_t)n_tiles * v.ks * kx::kWave * 16, &s);

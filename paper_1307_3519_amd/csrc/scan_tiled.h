@@ -3,14 +3,15 @@
 //
 // Same computation as scan_kernel (eq. (1), eq. (2) with the tie factor, the
 // chi-square screen and exact evaluation of candidates), organised as a
-// classic two-operand tiled GEMM: a block computes 128 traits x (64 or 128)
-// SNPs; the K loop runs over chunks of two 16-sample (fp16) or 32-sample
-// (int8) k-steps whose A (centred ranks) and B (genotype columns, expanded
-// once into MFMA fragment order) fragments are staged through a
-// double-buffered LDS ring with one block barrier per chunk.  Each wave owns
-// 64 traits x (32 or 64) SNPs of accumulators.  With int8 and K > 127 the
-// centred rank is split into bytes, c = 128 h + l, and two accumulator sets
-// give D = 128 D_h + D_l exactly.
+// classic two-operand tiled GEMM: a block computes 128 or 256 traits x 64 or
+// 128 SNPs, each wave 2 or 4 trait tiles x 1 or 2 SNP tiles (as many
+// accumulators as fit in 256 registers, which sets how often an operand
+// fragment read from LDS is reused).  The K loop runs over chunks of two
+// 16-sample (fp16) or 32-sample (int8) k-steps whose A (centred ranks) and B
+// (genotype columns, expanded once into MFMA fragment order) fragments are
+// copied into an LDS ring by LDS-DMA loads, with one block barrier per chunk.
+// With int8 and K > 127 the centred rank is split into bytes,
+// c = 128 h + l, and two accumulator sets give D = 128 D_h + D_l exactly.
 #pragma once
 #include "scan_kernel.h"
 
@@ -65,7 +66,11 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
     constexpr int WS = (NC == 2 && !SPLIT) ? 2 : 1;    // SNP tiles per wave
     constexpr int NP = SPLIT ? 2 : 1;                  // A planes
     constexpr int KC = 2;                              // k-steps per chunk
-    constexpr int BT = 4;                              // trait tiles per block
+    // trait tiles per wave: 4 for the complete-SNP forms when the accumulators
+    // fit in 256 registers (fewer LDS reads per MFMA); the missing-genotype
+    // form measured faster with 2
+    constexpr int WT = (FORM != MISS3 && NP * 4 * WS * NC * 16 <= 256) ? 4 : 2;
+    constexpr int BT = 2 * WT;                         // trait tiles per block
     constexpr int BS = 2 * WS;                         // SNP tiles per block
     constexpr int NFA = BT * KC * NP;                  // A fragments per chunk
     constexpr int NFB = BS * KC * NC;                  // B fragments per chunk
@@ -75,6 +80,7 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
     constexpr bool QUEUE = FORM == MISS3;
     // ring of R chunk slots filled D = R - 1 chunks ahead by LDS-DMA copies
     constexpr int R = NF * kWave * 16 * 4 <= 100 * 1024 ? 4 : 3;
+    static_assert(NF * kWave * 16 * R <= 128 * 1024, "ring fits the LDS budget");
     constexpr int D = R - 1;
     static_assert((D - 1) * FPW <= 15, "wait count fits the vmcnt field");
 
@@ -179,11 +185,11 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
                              : "memory");
             }
         };
-        acc_t acc[NP][2][WS][NC];
+        acc_t acc[NP][WT][WS][NC];
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
-            for (int ti = 0; ti < 2; ++ti)
+            for (int ti = 0; ti < WT; ++ti)
 #pragma unroll
                 for (int j = 0; j < WS; ++j)
 #pragma unroll
@@ -205,12 +211,12 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
             const int buf = ch % R;
 #pragma unroll
             for (int kk = 0; kk < KC; ++kk) {
-                frag fa[NP][2], fb[WS][NC];
+                frag fa[NP][WT], fb[WS][NC];
 #pragma unroll
                 for (int p = 0; p < NP; ++p)
 #pragma unroll
-                    for (int ti = 0; ti < 2; ++ti)
-                        fa[p][ti] = s_buf[buf][p * BT * KC + ((wave >> 1) * 2 + ti) * KC + kk][lane];
+                    for (int ti = 0; ti < WT; ++ti)
+                        fa[p][ti] = s_buf[buf][p * BT * KC + ((wave >> 1) * WT + ti) * KC + kk][lane];
 #pragma unroll
                 for (int j = 0; j < WS; ++j)
 #pragma unroll
@@ -219,7 +225,7 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
 #pragma unroll
                 for (int p = 0; p < NP; ++p)
 #pragma unroll
-                    for (int ti = 0; ti < 2; ++ti)
+                    for (int ti = 0; ti < WT; ++ti)
 #pragma unroll
                         for (int j = 0; j < WS; ++j)
 #pragma unroll
@@ -238,8 +244,8 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
             const SnpInfo inf = gload(a.info + m);
             const LaneK lk = lane_constants(inf, a.K, a.inv_hc);
 #pragma unroll
-            for (int ti = 0; ti < 2; ++ti) {
-                const int64_t tt = tb * BT + (wave >> 1) * 2 + ti;
+            for (int ti = 0; ti < WT; ++ti) {
+                const int64_t tt = tb * BT + (wave >> 1) * WT + ti;
                 if (tt >= n_tiles) continue;
                 const int64_t rb = tt * kTile + 4 * (lane >> 5);
                 auto colv = [&](int c, int r) -> float {
