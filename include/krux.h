@@ -183,9 +183,8 @@ krux_status krux_timer_read(krux_ctx* ctx, double* total_ms, int64_t* launches);
 
 /* Autotuner of the launch configuration (Data slicing: the work is tiled
  * over traits and SNP blocks; how large a trait range each work item covers,
- * whether the A tiles of the K <= 128 kernel go through the block's LDS ring,
- * and the XCD-grouped item order of the K > 128 kernel are machine- and
- * shape-dependent).  Times krux_test (hit mode, P_c = 1e-5, no minimum p) on
+ * the pipeline of the K <= 128 kernel, and the tile shape and item order of
+ * the K > 128 kernel are machine- and shape-dependent).  Times krux_test (hit mode, P_c = 1e-5, no minimum p) on
  * the caller's inputs -- device arrays as for krux_test; a representative
  * slice of a few 1e9 pairs is enough -- for every candidate configuration of
  * the kernel that serves (K, precision), and keeps the fastest in the context:
@@ -205,12 +204,14 @@ krux_status krux_autotune(krux_ctx* ctx, const int16_t* ranks2, const int64_t* t
  * device's architecture (later lines win; other lines are ignored). */
 krux_status krux_load_tuning(krux_ctx* ctx, const char* cache_path);
 
-/* The configuration in use for (K, precision): ring (1 LDS ring, 0 register
- * double buffer), range_kb (trait-range operand budget) and grouped (XCD-
- * grouped item order); -1 / 0 mean the built-in rule.  Host outputs,
- * each nullable. */
+/* The configuration in use for (K, precision).  K <= 128 kernel: ring
+ * (0 register double buffer, 1 LDS ring with the two-tile pipeline, 2 LDS
+ * ring one tile at a time) and range_kb (trait-range operand budget).
+ * K > 128 kernel: grouped (XCD-grouped item order) and shape (0 wide tiles,
+ * one wave per SIMD; 1 two waves per SIMD).  -1 / 0 mean the built-in rule.
+ * Host outputs, each nullable. */
 krux_status krux_tuning_of(krux_ctx* ctx, int32_t K, int32_t precision, int32_t* ring,
-                           int32_t* range_kb, int32_t* grouped);
+                           int32_t* range_kb, int32_t* grouped, int32_t* shape);
 
 #ifdef __cplusplus
 }

@@ -42,6 +42,7 @@ struct Tuning {
                          // 2 LDS ring without the two-tile pipeline (3 waves per SIMD)
     int range_kb = 0;    // SNP-stationary kernel: trait-range operand budget
     int grouped = -1;    // tiled kernel: XCD-grouped item order
+    int shape = -1;      // tiled kernel: tile shape (0 wide, 1 two waves per SIMD)
     double ms = 0.0;     // time of the tuning run
 };
 
@@ -277,6 +278,7 @@ krux_status launch_scan(krux_ctx* c, const kx::ScanArgs& a, const Variant& v, co
     ta.Bf = form == kx::MISS3 ? col.Bf3 : col.Bf;
     ta.A_hi = A_hi;
     ta.ks = v.ks;
+    ta.shape = a.tile_shape;
     if (v.elem == kx::F16) HIP_TRY(c, kx_launch_tiled_f16(&a, &ta, form, mode, grid, st));
     else HIP_TRY(c, kx_launch_tiled_i8(&a, &ta, form, mode, grid, st));
     return KRUX_OK;
@@ -326,6 +328,9 @@ void apply_tuning(krux_ctx* c, int K, int precision, const Variant& v, int64_t n
     // the tuner preferred row-major item order at every K of the cohort
     // workload (150..1000), so that is the default
     a->group_items = t.grouped >= 0 ? t.grouped : 0;
+    // two waves per SIMD (shape 1) measured 25-35 % faster than the wide
+    // tiles at K = 200 and 500, fp16 and int8
+    a->tile_shape = t.shape >= 0 ? t.shape : 1;
 }
 
 // Work items of one scan launch (an upper bound; the kernels stop early).
@@ -773,32 +778,34 @@ std::vector<Tuning> tuning_candidates(const Variant& v) {
                 out.push_back(t);
             }
     } else {
-        for (int g = 0; g <= 1; ++g) {
-            Tuning t;
-            t.grouped = g;
-            out.push_back(t);
-        }
+        for (int shape = 0; shape <= 1; ++shape)
+            for (int g = 0; g <= 1; ++g) {
+                Tuning t;
+                t.grouped = g;
+                t.shape = shape;
+                out.push_back(t);
+            }
     }
     return out;
 }
 
 // One line of the cache file: {"arch": "gfx950", "K": 102, "precision": "fp16",
-// "mode": "hits", "ring": 0, "range_kb": 2560, "grouped": -1, "ms": 3.41}
+// "mode": "hits", "ring": 0, "range_kb": 2560, "grouped": -1, "shape": -1, "ms": 3.41}
 bool parse_tuning_line(const char* line, const char* arch, int* K, int* prec, Tuning* t) {
     char a[32] = {0}, p[16] = {0}, m[16] = {0};
-    int k = 0, ring = -1, kb = 0, grouped = -1;
+    int k = 0, ring = -1, kb = 0, grouped = -1, shape = -1;
     double ms = 0.0;
     const int n = std::sscanf(line,
                               " {\"arch\": \"%31[^\"]\", \"K\": %d, \"precision\": \"%15[^\"]\", "
                               "\"mode\": \"%15[^\"]\", \"ring\": %d, \"range_kb\": %d, "
-                              "\"grouped\": %d, \"ms\": %lf",
-                              a, &k, p, m, &ring, &kb, &grouped, &ms);
-    if (n != 8 || std::strcmp(a, arch) != 0 || std::strcmp(m, "hits") != 0) return false;
+                              "\"grouped\": %d, \"shape\": %d, \"ms\": %lf",
+                              a, &k, p, m, &ring, &kb, &grouped, &shape, &ms);
+    if (n != 9 || std::strcmp(a, arch) != 0 || std::strcmp(m, "hits") != 0) return false;
     if (std::strcmp(p, "fp16") == 0) *prec = KRUX_PREC_FP16;
     else if (std::strcmp(p, "int8") == 0) *prec = KRUX_PREC_INT8;
     else return false;
     *K = k;
-    t->ring = ring; t->range_kb = kb; t->grouped = grouped; t->ms = ms;
+    t->ring = ring; t->range_kb = kb; t->grouped = grouped; t->shape = shape; t->ms = ms;
     return true;
 }
 
@@ -865,9 +872,10 @@ krux_status krux_autotune(krux_ctx* c, const int16_t* ranks2, const int64_t* tie
         if (!f) return fail(c, KRUX_ERR_ARG, "cannot open %s", cache_path);
         std::fprintf(f,
                      "{\"arch\": \"%s\", \"K\": %d, \"precision\": \"%s\", \"mode\": \"hits\", "
-                     "\"ring\": %d, \"range_kb\": %d, \"grouped\": %d, \"ms\": %.6f}\n",
+                     "\"ring\": %d, \"range_kb\": %d, \"grouped\": %d, \"shape\": %d, "
+                     "\"ms\": %.6f}\n",
                      c->arch, K, prec_name(precision), best.ring, best.range_kb, best.grouped,
-                     best.ms);
+                     best.shape, best.ms);
         std::fclose(f);
     }
     return KRUX_OK;
@@ -889,7 +897,7 @@ krux_status krux_load_tuning(krux_ctx* c, const char* cache_path) {
 }
 
 krux_status krux_tuning_of(krux_ctx* c, int32_t K, int32_t precision, int32_t* ring,
-                           int32_t* range_kb, int32_t* grouped) {
+                           int32_t* range_kb, int32_t* grouped, int32_t* shape) {
     if (!c) return fail(nullptr, KRUX_ERR_ARG, "ctx is NULL");
     Tuning t;
     auto it = c->tuned.find({K, precision});
@@ -897,6 +905,7 @@ krux_status krux_tuning_of(krux_ctx* c, int32_t K, int32_t precision, int32_t* r
     if (ring) *ring = t.ring;
     if (range_kb) *range_kb = t.range_kb;
     if (grouped) *grouped = t.grouped;
+    if (shape) *shape = t.shape;
     return KRUX_OK;
 }
 

@@ -51,6 +51,7 @@ struct ScanArgs {
     int ring;                 // complete-SNP screen: 0 register double buffer, 1 block LDS
                               // ring (pipelined), 2 LDS ring, one tile at a time, 3 waves/SIMD
     int group_items;          // tiled kernel: XCD-grouped item order
+    int tile_shape;           // tiled kernel: TiledShape variant
     int want_flag;            // process SNP tiles with this flag; -1 = all
     float inv_hc[3];          // screen level: 1/H_c(df), [0] = 0
     double hc[kMaxLevels][2]; // exact thresholds per level, df = 1, 2
@@ -81,6 +82,7 @@ struct TiledArgs {
     const void* Bf;      // [snp tiles][ks][NC][64] fragments
     const void* A_hi;    // int8 byte split: high plane of A, else null
     int ks;              // k-steps of both operands (even)
+    int shape;           // tile shape: 0 wide (one wave per SIMD), 1 two waves per SIMD
 };
 
 // candidate entry flags (high bits of the SNP word): column values are

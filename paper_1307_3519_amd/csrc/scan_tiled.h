@@ -4,9 +4,10 @@
 // Same computation as scan_kernel (eq. (1), eq. (2) with the tie factor, the
 // chi-square screen and exact evaluation of candidates), organised as a
 // classic two-operand tiled GEMM: a block computes 128 or 256 traits x 64 or
-// 128 SNPs, each wave 2 or 4 trait tiles x 1 or 2 SNP tiles (as many
-// accumulators as fit in 256 registers, which sets how often an operand
-// fragment read from LDS is reused).  The K loop runs over chunks of two
+// 128 SNPs, each wave 2 or 4 trait tiles x 1 or 2 SNP tiles (see TiledShape:
+// either as many accumulators as fit in 256 registers, one wave per SIMD, or
+// half as many with two waves per SIMD, whose epilogues then overlap the other
+// wave's MFMAs; the second is the faster one measured).  The K loop runs over chunks of two
 // 16-sample (fp16) or 32-sample (int8) k-steps whose A (centred ranks) and B
 // (genotype columns, expanded once into MFMA fragment order) fragments are
 // copied into an LDS ring by LDS-DMA loads, with one block barrier per chunk.
@@ -56,20 +57,37 @@ __device__ inline float screen_value(const LaneK& c, float th, float v0, float v
     }
 }
 
-template <int E, int FORM, int MODE, bool SPLIT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
+// Tile shape of the tiled kernel.
+//  V = 0 ("wide"): up to 4 trait tiles x 2 SNP tiles per wave (accumulators up
+//        to 256 registers, fewest LDS reads per MFMA), one wave per SIMD;
+//  V = 1 ("two waves"): 4 (or 2) trait tiles x 1 SNP tile per wave, so that
+//        two waves share each SIMD and one wave's epilogue overlaps the
+//        other's MFMAs; its LDS ring is kept small enough for two blocks.
+template <int FORM, bool SPLIT, int V>
+struct TiledShape {
+    static constexpr int NC = FORM == MISS3 ? 3 : 2;
+    static constexpr int NP = SPLIT ? 2 : 1;
+    static constexpr int WS = V == 0 ? ((NC == 2 && !SPLIT) ? 2 : 1) : 1;
+    static constexpr int WT = V == 0 ? ((FORM != MISS3 && NP * 4 * WS * NC * 16 <= 256) ? 4 : 2)
+                                     : (NP * NC <= 2 ? 4 : 2);
+    static constexpr int ACC = NP * WT * WS * NC * 16;   // accumulator registers
+    static constexpr int WPE_MIN = (V == 1 && ACC <= 128) ? 2 : 1;
+    static constexpr int RING_BYTES = V == 0 ? 128 * 1024 : 72 * 1024;
+};
+
+template <int E, int FORM, int MODE, bool SPLIT, int V>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(TiledShape<FORM, SPLIT, V>::WPE_MIN, 2)))
 void scan_tiled(ScanArgs a, TiledArgs ta) {
     using T_ = ET<E>;
     using frag = typename T_::frag;
     using acc_t = typename T_::acc;
-    constexpr int NC = FORM == MISS3 ? 3 : 2;
-    constexpr int WS = (NC == 2 && !SPLIT) ? 2 : 1;    // SNP tiles per wave
-    constexpr int NP = SPLIT ? 2 : 1;                  // A planes
+    using SH = TiledShape<FORM, SPLIT, V>;
+    constexpr int NC = SH::NC;
+    constexpr int WS = SH::WS;                         // SNP tiles per wave
+    constexpr int NP = SH::NP;                         // A planes
     constexpr int KC = 2;                              // k-steps per chunk
-    // trait tiles per wave: 4 for the complete-SNP forms when the accumulators
-    // fit in 256 registers (fewer LDS reads per MFMA); the missing-genotype
-    // form measured faster with 2
-    constexpr int WT = (FORM != MISS3 && NP * 4 * WS * NC * 16 <= 256) ? 4 : 2;
+    constexpr int WT = SH::WT;                         // trait tiles per wave
     constexpr int BT = 2 * WT;                         // trait tiles per block
     constexpr int BS = 2 * WS;                         // SNP tiles per block
     constexpr int NFA = BT * KC * NP;                  // A fragments per chunk
@@ -79,10 +97,11 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
     static_assert(NF % kWavesPerBlock == 0, "every wave copies the same number of fragments");
     constexpr bool QUEUE = FORM == MISS3;
     // ring of R chunk slots filled D = R - 1 chunks ahead by LDS-DMA copies
-    constexpr int R = NF * kWave * 16 * 4 <= 100 * 1024 ? 4 : 3;
+    constexpr int R = NF * kWave * 16 * 4 <= SH::RING_BYTES ? 4 : 3;
     static_assert(NF * kWave * 16 * R <= 128 * 1024, "ring fits the LDS budget");
     constexpr int D = R - 1;
-    static_assert((D - 1) * FPW <= 15, "wait count fits the vmcnt field");
+    constexpr int kWaitVm = (D - 1) * FPW;
+    static_assert(kWaitVm <= 63, "wait count fits the vmcnt field");
 
     __shared__ frag s_buf[R][NF][kWave];
     __shared__ int2 s_queue[QUEUE ? kWavesPerBlock : 1][QUEUE ? kQueueCap : 1];
@@ -205,7 +224,10 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
             // chunks may still be in flight); the barrier publishes every
             // wave's copies and certifies that chunk ch - 1, whose slot the
             // next copy reuses, has been read by all waves
-            __builtin_amdgcn_s_waitcnt(((D - 1) * FPW) | (0x7 << 4) | (0xF << 8));
+            // vmcnt: low four bits in [3:0], high two in [15:14]; no wait on
+            // the export and LDS/scalar counters
+            __builtin_amdgcn_s_waitcnt((kWaitVm & 0xF) | ((kWaitVm >> 4) << 14) | (0x7 << 4) |
+                                       (0xF << 8));
             block_barrier();
             issue_chunk(ch + D);
             const int buf = ch % R;
@@ -362,7 +384,7 @@ __global__ __launch_bounds__(256) void expand_columns(const int8_t* __restrict__
 template <int E, int FORM, int MODE, bool SPLIT>
 inline hipError_t launch_tiled(const ScanArgs& a, const TiledArgs& ta, int grid, hipStream_t st) {
     size_t lds = FORM == MISS3 ? (size_t)kWavesPerBlock * coop_lds_entries(a.K) * sizeof(int16_t) : 0;
-    auto kern = scan_tiled<E, FORM, MODE, SPLIT>;
+    auto kern = ta.shape ? scan_tiled<E, FORM, MODE, SPLIT, 1> : scan_tiled<E, FORM, MODE, SPLIT, 0>;
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 256, lds) != hipSuccess || occ < 1)
         occ = 1;

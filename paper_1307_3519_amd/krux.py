@@ -85,7 +85,8 @@ def library():
     lib.krux_load_tuning.argtypes = [P, ctypes.c_char_p]
     lib.krux_tuning_of.restype = ctypes.c_int
     lib.krux_tuning_of.argtypes = [P, i32, i32, ctypes.POINTER(ctypes.c_int32),
-                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.POINTER(ctypes.c_int32)]
     _lib = lib
     return lib
 
@@ -163,11 +164,11 @@ class Context:
         self._check(self.lib.krux_load_tuning(self.h, cache_path.encode()))
 
     def tuning_of(self, K, precision="fp16"):
-        """-> dict(ring, range_kb, grouped) in use for (K, precision)."""
-        r, kb, g = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        """-> dict(ring, range_kb, grouped, shape) in use for (K, precision)."""
+        r, kb, g, sh = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         self._check(self.lib.krux_tuning_of(self.h, K, _PREC[precision], ctypes.byref(r),
-                                            ctypes.byref(kb), ctypes.byref(g)))
-        return dict(ring=r.value, range_kb=kb.value, grouped=g.value)
+                                            ctypes.byref(kb), ctypes.byref(g), ctypes.byref(sh)))
+        return dict(ring=r.value, range_kb=kb.value, grouped=g.value, shape=sh.value)
 
     # ------------------------------------------------------------------ rank
     def rank(self, expr, out=None):

@@ -34,14 +34,14 @@ def test_autotune_choice_persists_and_keeps_results(tmp_path, K, prec, pm):
     try:
         r, ts, _ = ctx.rank(_dev(x))
         gd = _dev(g)
-        assert ctx.tuning_of(K, prec) == dict(ring=-1, range_kb=0, grouped=-1)
+        assert ctx.tuning_of(K, prec) == dict(ring=-1, range_kb=0, grouped=-1, shape=-1)
         ms = ctx.autotune(r, ts, gd, precision=prec, cache_path=cache)
         assert ms > 0.0
         chosen = ctx.tuning_of(K, prec)
         if K <= 128:
             assert chosen["ring"] in (0, 1, 2) and chosen["range_kb"] in (640, 1280, 2560, 5120)
         else:
-            assert chosen["grouped"] in (0, 1)
+            assert chosen["grouped"] in (0, 1) and chosen["shape"] in (0, 1)
         res = ctx.test(r, ts, gd, p_c=0.01, precision=prec, hit_capacity=1 << 14, min_p=True)
         torch.cuda.synchronize()
         n, h = krux.unpack_hits(res)
@@ -59,7 +59,7 @@ def test_autotune_choice_persists_and_keeps_results(tmp_path, K, prec, pm):
     try:
         ctx2.load_tuning(cache)
         assert ctx2.tuning_of(K, prec) == chosen
-        assert ctx2.tuning_of(K + 1, prec) == dict(ring=-1, range_kb=0, grouped=-1)
+        assert ctx2.tuning_of(K + 1, prec) == dict(ring=-1, range_kb=0, grouped=-1, shape=-1)
     finally:
         ctx2.close()
 
@@ -75,7 +75,7 @@ def test_every_pipeline_matches_oracle(tmp_path, ring, prec):
     x, g = _inputs(70 + ring, T, K, M, 0.01)
     cache = tmp_path / "tune.jsonl"
     cache.write_text('{"arch": "gfx950", "K": %d, "precision": "%s", "mode": "hits", '
-                     '"ring": %d, "range_kb": 640, "grouped": -1, "ms": 0}\n' % (K, prec, ring))
+                     '"ring": %d, "range_kb": 640, "grouped": -1, "shape": -1, "ms": 0}\n' % (K, prec, ring))
     ctx = krux.Context(0)
     try:
         ctx.load_tuning(str(cache))
