@@ -39,7 +39,8 @@ struct Buf {
 // -1 / 0: the built-in rule.
 struct Tuning {
     int ring = -1;       // SNP-stationary kernel: 0 register double buffer, 1 LDS ring,
-                         // 2 LDS ring without the two-tile pipeline (3 waves per SIMD)
+                         // 2 LDS ring without the two-tile pipeline (3 waves per SIMD),
+                         // 3 LDS ring, two tiles per step
     int range_kb = 0;    // SNP-stationary kernel: trait-range operand budget
     int grouped = -1;    // tiled kernel: XCD-grouped item order
     int shape = -1;      // tiled kernel: tile shape (0 wide, 1 two waves per SIMD)
@@ -351,9 +352,11 @@ void set_levels(kx::ScanArgs* a, const double* p_cs, int n) {
 
 void set_screen(kx::ScanArgs* a, double p_screen) {
     a->inv_hc[0] = 0.0f;
+    a->hc_screen[0] = 0.0;
     for (int df = 1; df <= 2; ++df) {
         double h = threshold_of(p_screen, df);
         a->inv_hc[df] = (float)(1.0 / h);
+        a->hc_screen[df] = h;
     }
 }
 
@@ -369,9 +372,9 @@ krux_status run_screen(krux_ctx* c, kx::ScanArgs a, const Variant& v, const Colu
     a.cand = (uint4*)ws(c, S_CAND, (size_t)a.cand_cap * sizeof(uint4), &s);
     a.n_cand = (unsigned long long*)ws(c, S_NCAND, 256, &s);
     // pairs of SNPs with missing genotypes that pass the bound: up to 1/16 of
-    // the pairs, at most 2^26 entries (512 MB); the rest are evaluated in the scan
-    a.mcand_cap = std::min<int64_t>(std::max<int64_t>(n_rows_max * a.M / 16, 1 << 16), 1LL << 26);
-    a.mcand = (int2*)ws(c, S_MCAND, (size_t)a.mcand_cap * sizeof(int2), &s);
+    // the pairs, at most 2^25 entries (512 MB); the rest are evaluated in the scan
+    a.mcand_cap = std::min<int64_t>(std::max<int64_t>(n_rows_max * a.M / 16, 1 << 16), 1LL << 25);
+    a.mcand = (int4*)ws(c, S_MCAND, (size_t)a.mcand_cap * sizeof(int4), &s);
     a.n_mcand = a.n_cand + 1;      // both counters were cleared by the preceding prep kernel
     if (s != KRUX_OK) return s;
     a.want_flag = 0;
@@ -770,7 +773,7 @@ const char* prec_name(int p) {
 std::vector<Tuning> tuning_candidates(const Variant& v) {
     std::vector<Tuning> out;
     if (!v.tiled) {
-        for (int ring = 0; ring <= 2; ++ring)
+        for (int ring = 0; ring <= 3; ++ring)
             for (int kb : {640, 1280, 2560, 5120}) {
                 Tuning t;
                 t.ring = ring;

@@ -49,11 +49,13 @@ struct ScanArgs {
     int K;
     int tiles_per_range;
     int ring;                 // complete-SNP screen: 0 register double buffer, 1 block LDS
-                              // ring (pipelined), 2 LDS ring, one tile at a time, 3 waves/SIMD
+                              // ring (pipelined), 2 LDS ring, one tile at a time, 3 waves/SIMD,
+                              // 3 LDS ring, two tiles per step
     int group_items;          // tiled kernel: XCD-grouped item order
     int tile_shape;           // tiled kernel: TiledShape variant
     int want_flag;            // process SNP tiles with this flag; -1 = all
     float inv_hc[3];          // screen level: 1/H_c(df), [0] = 0
+    double hc_screen[3];      // screen level: H_c(df) in double, [0] unused
     double hc[kMaxLevels][2]; // exact thresholds per level, df = 1, 2
     int n_lev;
     HitRec* hits;
@@ -71,8 +73,10 @@ struct ScanArgs {
     int64_t cand_cap;
     unsigned long long* n_cand;
     // screen mode: pairs of SNPs with missing genotypes that passed the
-    // bound, {operand row, SNP}, evaluated by scan_missing (null: in the scan)
-    int2* mcand;
+    // bound, {operand row, SNP, D~1, D~2} (the group-1 and group-2 sums of
+    // centred full-sample ranks over the observed samples), evaluated by
+    // scan_exact (null: in the scan)
+    int4* mcand;
     int64_t mcand_cap;
     unsigned long long* n_mcand;
 };

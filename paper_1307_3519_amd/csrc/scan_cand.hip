@@ -3,10 +3,116 @@
 
 namespace kx {
 
+// Rank-aware bound for a pair (row v, SNP m) whose SNP has missing genotypes
+// (sample exclusion with re-ranking over the rest, section 2).  With D~_i the
+// sums of full-sample centred ranks over the observed members of group i (the
+// scan's columns; D~_0 = -D~_1 - D~_2 - sum of the missing samples' centred
+// ranks), the re-ranked sums are D'_i = D~_i - sum_q s_i(q), where for each
+// missing sample q, s_i(q) = #{kept k in group i above q} - #{kept k in group i
+// below q}.  At most L_q = (a_q - 2) / 2 samples lie below q and at most
+// G_q = K - a_q / 2 above it (a_q: doubled midrank, its tie group holds q), so
+// s_i(q) lies in [-min(N_i, L_q), min(N_i, G_q)].  The largest f over these
+// intervals, with E' >= K'^3 - K' - sumT, bounds H'.  Returns false when the
+// bound stays below the pass's screen level (never for a level of 0).  All
+// lanes of the wave take part; the result is uniform.
+__device__ inline bool missing_pair_may_pass(const ScanArgs& a, int64_t v, int64_t m, int d1,
+                                             int d2, int lane) {
+    const int K = a.K;
+    const int64_t trait = v % a.T, perm = v / a.T;
+    const int16_t* rk = a.ranks2 + trait * K;
+    const int32_t* pm = a.perms ? a.perms + perm * K : nullptr;
+    const int8_t* gr = a.G + m * (int64_t)a.gstride;
+    const SnpInfo inf = a.info[m];
+    const int n[3] = {inf.n0, inf.n1, inf.n2};
+    int nq = 0, sq = 0, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    auto add_missing = [&](int aq) {
+        const int below = (aq - 2) >> 1, above = K - ((aq + 1) >> 1);
+        ++nq;
+        sq += aq - (K + 1);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            lo[i] -= min(n[i], below);
+            hi[i] += min(n[i], above);
+        }
+    };
+    // each lane scans 16 consecutive codes per 16-byte load (the packed row
+    // stride is a multiple of 32 bytes, so the load stays inside the row);
+    // bytes equal to the missing code are found four at a time.  The first
+    // four missing samples of a lane have their ranks loaded together, any
+    // further ones one by one.
+    for (int k0 = 0; k0 < K; k0 += 16 * kWave) {
+        const int kb = k0 + 16 * lane;
+        const uint4 w = kb < K ? *(const uint4*)(gr + kb) : make_uint4(0u, 0u, 0u, 0u);
+        const uint32_t words[4] = {w.x, w.y, w.z, w.w};
+        int np = 0, p0 = 0, p1 = 0, p2 = 0, p3 = 0;
+        bool more = false;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t x = words[j] ^ (0x01010101u * (uint32_t)kMissingCode);
+            // high bit of each byte of z set iff that byte of x is zero
+            uint32_t z = ~((((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x)) & 0x80808080u;
+            while (z) {
+                const int k = kb + 4 * j + (__builtin_ctz(z) >> 3);
+                z &= z - 1u;
+                if (k >= K) continue;
+                if (np == 4) { more = true; break; }
+                p0 = np == 0 ? k : p0; p1 = np == 1 ? k : p1;
+                p2 = np == 2 ? k : p2; p3 = np == 3 ? k : p3;
+                ++np;
+            }
+        }
+        // unused slots load sample 0 (no branches around the loads)
+        int i0 = p0, i1 = p1, i2 = p2, i3 = p3;
+        if (pm) {
+            i0 = pm[p0]; i1 = pm[p1]; i2 = pm[p2]; i3 = pm[p3];
+        }
+        const int a0 = rk[i0], a1 = rk[i1], a2 = rk[i2], a3 = rk[i3];
+        if (np > 0) add_missing(a0);
+        if (np > 1) add_missing(a1);
+        if (np > 2) add_missing(a2);
+        if (np > 3) add_missing(a3);
+        if (more) {
+            // the lane's missing samples after its fourth
+            int seen = 0;
+            for (int e = 0; e < 16; ++e) {
+                const int k = kb + e;
+                if (k >= K) break;
+                if (gr[k] != kMissingCode) continue;
+                if (++seen <= 4) continue;
+                add_missing(rk[pm ? pm[k] : k]);
+            }
+        }
+    }
+    nq = wave_sum(nq);
+    sq = wave_sum(sq);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        lo[i] = wave_sum(lo[i]);
+        hi[i] = wave_sum(hi[i]);
+    }
+    const int df = snp_df(inf);
+    if (df <= 0) return false;                  // never recorded
+    const int64_t kp = K - nq;
+    const int64_t E = cube_minus(kp) - a.tiesum[trait];
+    if (kp < 2 || E <= 0) return true;          // no bound: evaluate
+    const int64_t D[3] = {-(int64_t)d1 - d2 - sq, d1, d2};
+    double f = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        if (n[i] == 0) continue;
+        const int64_t x0 = D[i] - hi[i], x1 = D[i] - lo[i];
+        const int64_t x = max(x0 < 0 ? -x0 : x0, x1 < 0 ? -x1 : x1);
+        f += (double)(x * x) / (double)n[i];
+    }
+    const double Hup = 3.0 * (double)(kp - 1) * f / (double)E;
+    return !(Hup * (1.0 + 1e-9) < a.hc_screen[df]);
+}
+
 // One launch evaluates both buffers filled by the scan kernels:
 //  * candidates of complete SNPs, one lane each: exact H from the pair's
 //    exact MFMA column values (eq. (2) with the tie factor), p, hit / min p;
-//  * pairs of SNPs with missing genotypes, one wave each: the ranks are
+//  * pairs of SNPs with missing genotypes, one wave each: a rank-aware bound
+//    (missing_pair_may_pass) drops most of them; for the rest the ranks are
 //    re-derived over the kept samples (coop_exact), then the same.
 __global__ __launch_bounds__(256) void scan_exact(ScanArgs a) {
     int64_t n = (int64_t)*a.n_cand;
@@ -26,9 +132,10 @@ __global__ __launch_bounds__(256) void scan_exact(ScanArgs a) {
     if (nm > a.mcand_cap) nm = a.mcand_cap;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
     for (int64_t e = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; e < nm; e += waves) {
-        const int2 q = a.mcand[e];
+        const int4 q = a.mcand[e];
         const int64_t v = a.row_v[q.x];
         if (v < 0) continue;             // padding row (uniform per wave)
+        if (!missing_pair_may_pass(a, v, q.y, q.z, q.w, lane)) continue;
         int df;
         int64_t s[3];
         const double H = coop_exact(a, v, q.y, sb, lane, &df, s);

@@ -29,6 +29,7 @@
 //          ranks re-derived over the remaining samples.
 #pragma once
 #include "kx_args.h"
+#include <type_traits>
 
 namespace kx {
 
@@ -254,13 +255,15 @@ __device__ inline void stage_candidates(const ScanArgs& a, const ScanArgs* a_lds
 //   a'_k = a_k - sum_{j missing} (2 [a_j < a_k] + [a_j == a_k]),
 // the tie term loses 3 t (t - 1) for each removal from a tie group of
 // current size t.  All 64 lanes of the wave take part; the result is uniform.
-// sbuf: 2K entries of this wave's LDS: the pair's samples (rank | code << 13,
-// ranks are below 2^13 for K <= 4095) and the ranks of its missing samples.
+// sbuf (coop_lds_entries(K) int16 entries of this wave's LDS, 16-byte
+// aligned): [0, K) the pair's samples (rank | code << 13, ranks are below 2^13
+// for K <= 4095), [K, 2K + 64) the ranks of its missing samples (the rank
+// bitmap of the fast path sits past the first 64), then 64 int32 counters.
 constexpr int kCodeShift = 13;
 constexpr int kRankMask = (1 << kCodeShift) - 1;
-// per-wave LDS of coop_exact, in int16 entries: K samples, max(K, 64) missing
-// ranks, 64 int32 tie counters
-__host__ __device__ inline int coop_lds_entries(int K) { return 2 * K + 64 + 128; }
+__host__ __device__ inline int coop_lds_entries(int K) { return (2 * K + 64 + 128 + 7) & ~7; }
+// int16 offset of the fast path's rank bitmap (16-byte aligned)
+__device__ inline int coop_bitmap_offset(int K) { return (K + 64 + 7) & ~7; }
 
 // Ascending sort of one value per lane across the wave (bitonic network).
 __device__ inline int wave_sort(int v, int lane) {
@@ -277,6 +280,20 @@ __device__ inline int wave_sort(int v, int lane) {
     return v;
 }
 
+__device__ inline int wave_incl_scan(int v, int lane) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+// U: samples per lane whose loads are in flight together in the first pass;
+// BITMAP: rank-bitmap lookups instead of binary searches when the missing
+// ranks are distinct (the out-of-line copy called from the scan kernels takes
+// U = 1 and no bitmap, to stay small).
+template <int U = 8, bool BITMAP = true>
 __device__ inline double coop_exact(const ScanArgs& a, int64_t v, int64_t m, int16_t* sbuf,
                                     int lane, int* df_out, int64_t* s_out) {
     const int K = a.K;
@@ -288,40 +305,122 @@ __device__ inline double coop_exact(const ScanArgs& a, int64_t v, int64_t m, int
     int16_t* qb = sbuf + K;
     int32_t* tc = (int32_t*)(sbuf + 2 * K + 64);   // 4-byte aligned: 2K + 64 is even
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    // one pass over global memory: rank and genotype code of every sample
-    for (int k0 = 0; k0 < K; k0 += kWave) {
-        const int k = k0 + lane;
-        if (k < K) {
-            const int code = gr[k];
-            const int ak = rk[pm ? pm[k] : k];
-            sr[k] = (uint16_t)(ak | (code << kCodeShift));
-        }
-    }
-    __builtin_amdgcn_wave_barrier();
+    // one pass over global memory, eight loads of each kind in flight per lane:
+    // rank and genotype code of every sample into LDS, the ranks of the
+    // missing samples compacted into qb
     int nq = 0;
-    for (int k0 = 0; k0 < K; k0 += kWave) {
-        const int k = k0 + lane;
-        const int x = k < K ? sr[k] : 0;
-        const bool miss = k < K && (x >> kCodeShift) == kMissingCode;
-        const unsigned long long msk = __ballot(miss);
-        if (miss) qb[nq + __popcll(msk & lt)] = (int16_t)(x & kRankMask);
-        nq += __popcll(msk);
-    }
+    auto pass = [&](auto with_perm) {
+        for (int k0 = 0; k0 < K; k0 += U * kWave) {
+            // loads at clamped indices (no branches, so all are in flight
+            // together); lanes past K are masked afterwards
+            int code[U], ak[U], idx[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) idx[u] = min(k0 + u * kWave + lane, K - 1);
+#pragma unroll
+            for (int u = 0; u < U; ++u) code[u] = (int)gr[idx[u]];
+            if constexpr (decltype(with_perm)::value) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) idx[u] = pm[idx[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) ak[u] = (int)rk[idx[u]];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = k0 + u * kWave + lane;
+                if (k < K) sr[k] = (uint16_t)(ak[u] | (code[u] << kCodeShift));
+                const bool miss = k < K && code[u] == kMissingCode;
+                const unsigned long long msk = __ballot(miss);
+                if (miss) qb[nq + __popcll(msk & lt)] = (int16_t)ak[u];
+                nq += __popcll(msk);
+            }
+        }
+    };
+    if (pm) pass(std::true_type{});
+    else pass(std::false_type{});
     __builtin_amdgcn_wave_barrier();
     long long ts = a.tiesum[trait];
     long long s0 = 0, s1 = 0, s2 = 0;
+    const int W = ((2 * K) >> 6) + 1;      // 64-bit words covering doubled ranks 0..2K
+    int qv = 0x7FFF;
+    bool dup = false;
     if (nq <= kWave) {
-        // Up to 64 missing samples: sort their ranks across the wave, then one
-        // pass over the samples: for sample k, lt / le = number of missing
-        // ranks below / at most a_k (binary search), so its shift is
-        // 2 lt + (le - lt); a sample equal to a missing rank adds one to that
-        // rank's tie-group counter.  A tie group of size t that loses r
-        // members takes (t^3 - t) - ((t-r)^3 - (t-r)) off the tie term.
-        const int qv = wave_sort(lane < nq ? (int)qb[lane] : 0x7FFF, lane);
+        qv = wave_sort(lane < nq ? (int)qb[lane] : 0x7FFF, lane);
+        const int prev = __shfl_up(qv, 1, 64);
+        dup = __any(lane > 0 && lane < nq && prev == qv);
         __builtin_amdgcn_wave_barrier();
         qb[lane] = (int16_t)qv;
         tc[lane] = 0;
         __builtin_amdgcn_wave_barrier();
+    }
+    if (BITMAP && nq <= kWave && !dup && W <= kWave && K >= 32) {
+        // Up to 64 missing samples with distinct ranks: a bitmap of their ranks
+        // with per-word prefix counts gives, for sample k, the number of
+        // missing ranks below a_k (lt) and whether one equals it, in one LDS
+        // read.  The shift of a_k is 2 lt + eq; a sample equal to a missing
+        // rank adds one to that rank's tie-group counter (index lt in sorted
+        // order).  A tie group of size t that loses its one missing member
+        // takes 3 t (t - 1) off the tie term.
+        uint4* bm = (uint4*)(sbuf + coop_bitmap_offset(K));
+        if (lane < W) bm[lane] = make_uint4(0u, 0u, 0u, 0u);
+        __builtin_amdgcn_wave_barrier();
+        if (lane < nq) atomicOr((uint32_t*)&bm[qv >> 6] + ((qv >> 5) & 1), 1u << (qv & 31));
+        __builtin_amdgcn_wave_barrier();
+        {
+            const uint4 e = lane < W ? bm[lane] : make_uint4(0u, 0u, 0u, 0u);
+            const int c = __popc(e.x) + __popc(e.y);
+            const int incl = wave_incl_scan(c, lane);
+            __builtin_amdgcn_wave_barrier();
+            if (lane < W) bm[lane].z = (uint32_t)(incl - c);
+        }
+        __builtin_amdgcn_wave_barrier();
+        constexpr int V4 = 4;
+        for (int k0 = 0; k0 < K; k0 += V4 * kWave) {
+            int x[V4];
+            uint4 e[V4];
+#pragma unroll
+            for (int u = 0; u < V4; ++u) {
+                const int k = k0 + u * kWave + lane;
+                x[u] = k < K ? (int)sr[k] : (kMissingCode << kCodeShift);
+            }
+#pragma unroll
+            for (int u = 0; u < V4; ++u) e[u] = bm[(x[u] & kRankMask) >> 6];
+            int eqi[V4];
+#pragma unroll
+            for (int u = 0; u < V4; ++u) {
+                const int k = k0 + u * kWave + lane;
+                const int ak = x[u] & kRankMask;
+                const int b = ak & 63;
+                const unsigned long long bits = (unsigned long long)e[u].x |
+                                                ((unsigned long long)e[u].y << 32);
+                const int below = (int)e[u].z + __popcll(bits & ((1ull << b) - 1ull));
+                const int eq = (int)((bits >> b) & 1ull);
+                const int code = x[u] >> kCodeShift;
+                if (k < K && code != kMissingCode) {
+                    const int ap = ak - 2 * below - eq;
+                    if (code == 0) s0 += ap; else if (code == 1) s1 += ap; else s2 += ap;
+                }
+                eqi[u] = (k < K && eq) ? below : -1;
+            }
+            if (ts != 0) {
+#pragma unroll
+                for (int u = 0; u < V4; ++u)
+                    if (eqi[u] >= 0) atomicAdd(&tc[eqi[u]], 1);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (ts != 0) {
+            long long corr = 0;
+            if (lane < nq) {
+                const long long t = tc[lane];
+                corr = 3 * t * (t - 1);
+            }
+            ts -= wave_sum64(corr);
+        }
+    } else if (nq <= kWave) {
+        // Up to 64 missing samples, some tied: binary search in the sorted
+        // missing ranks for lt / le = number below / at most a_k; the shift is
+        // 2 lt + (le - lt).  A tie group of size t that loses r members takes
+        // (t^3 - t) - ((t-r)^3 - (t-r)) off the tie term.
         for (int k0 = 0; k0 < K; k0 += kWave) {
             const int k = k0 + lane;
             if (k < K) {
@@ -408,7 +507,7 @@ __device__ inline double coop_exact(const ScanArgs& a, int64_t v, int64_t m, int
 __device__ __attribute__((noinline)) double coop_exact_call(const ScanArgs& a, int64_t v,
                                                             int64_t m, int16_t* sbuf, int lane,
                                                             int* df_out, int64_t* s_out) {
-    return coop_exact(a, v, m, sbuf, lane, df_out, s_out);
+    return coop_exact<1, false>(a, v, m, sbuf, lane, df_out, s_out);
 }
 
 // Empties a wave's queue of screened pairs of SNPs with missing genotypes.
@@ -417,7 +516,7 @@ __device__ __attribute__((noinline)) double coop_exact_call(const ScanArgs& a, i
 // scan; pairs beyond its capacity, and the FULL / SUMS outputs, are
 // evaluated here.
 template <int MODE>
-__device__ inline void drain(const ScanArgs& a, int2* queue, int& qn, int16_t* qbuf, int lane) {
+__device__ inline void drain(const ScanArgs& a, int4* queue, int& qn, int16_t* qbuf, int lane) {
     int e0 = 0;
     if constexpr (MODE == SCREEN) {
         if (a.mcand) {
@@ -431,7 +530,7 @@ __device__ inline void drain(const ScanArgs& a, int2* queue, int& qn, int16_t* q
         }
     }
     for (int e = e0; e < qn; ++e) {
-        int2 q = queue[e];
+        int4 q = queue[e];
         int64_t v = a.row_v[q.x];
         // padding rows (zero operand) can pass the missing-genotype bound; the
         // entry is the same for the whole wave, so the skip is uniform
@@ -453,7 +552,8 @@ __device__ inline void drain(const ScanArgs& a, int2* queue, int& qn, int16_t* q
 // PF: 0 = load-then-compute per tile; 1 = next tile prefetched into a second
 // register buffer; 2 = software pipeline (MFMAs of the next tile interleaved
 // with the screen of the current one; screen mode, complete SNPs only);
-// 3 = the same pipeline fed from an LDS ring shared by the block.
+// 3 = the same pipeline fed from an LDS ring shared by the block; 4 = the
+// LDS ring, one tile at a time; 5 = the LDS ring, two tiles per step.
 template <int E, int KS, int FORM, int MODE,
           int PF = (MODE == SCREEN && FORM != MISS3) ? 2 : 0, int WPE = 2>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
@@ -463,25 +563,27 @@ void scan_kernel(ScanArgs a) {
     using acc_t = typename T_::acc;
     constexpr int NC = FORM == MISS3 ? 3 : 2;
     constexpr bool QUEUE = FORM == MISS3;
-    constexpr bool RING = (PF == 3 || PF == 4) && MODE == SCREEN && FORM != MISS3;
+    constexpr bool RING = (PF == 3 || PF == 4 || PF == 5) && MODE == SCREEN && FORM != MISS3;
+    // ring slots (a power of two): two tiles per step with PF == 5
+    constexpr int NSLOT = PF == 5 ? 8 : 4;
     // fp16 DIAG: second column scaled by q (diag_zscale), screen Y^2 + Z^2
     constexpr bool ZS = E == F16 && FORM == DIAG;
     constexpr uint32_t kDiagFlags = ZS ? kCandZs : 0u;
 
-    __shared__ int2 s_queue[QUEUE ? kWavesPerBlock : 1][QUEUE ? kQueueCap : 1];
+    __shared__ int4 s_queue[QUEUE ? kWavesPerBlock : 1][QUEUE ? kQueueCap : 1];
     __shared__ uint4 s_stage[MODE == SCREEN ? kWavesPerBlock : 1][kStageCap];
     // copy of the arguments for the out-of-line fallback (taking the address
     // of the kernel argument itself would move it to the stack)
     __shared__ ScanArgs s_args;
-    // LDS ring of A tiles shared by the block's waves (PF == 3, 4): 4 slots
-    __shared__ frag s_ring[RING ? 4 * KS * kWave : 1];
+    // LDS ring of A tiles shared by the block's waves (PF == 3, 4, 5)
+    __shared__ frag s_ring[RING ? NSLOT * KS * kWave : 1];
     if (threadIdx.x == 0) s_args = a;
     __syncthreads();
     extern __shared__ __attribute__((aligned(16))) int16_t s_qbuf[];   // MISS3: per wave coop_lds_entries(K)
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
-    int2* queue = s_queue[QUEUE ? wave : 0];
+    int4* queue = s_queue[QUEUE ? wave : 0];
     uint4* stage = s_stage[MODE == SCREEN ? wave : 0];
     int sn = 0;
     int16_t* qbuf = s_qbuf + (QUEUE ? wave * coop_lds_entries(a.K) : 0);
@@ -604,7 +706,10 @@ void scan_kernel(ScanArgs a) {
                         if (qn + 64 > kQueueCap) drain<MODE>(a, queue, qn, qbuf, lane);
                         const unsigned long long lt =
                             (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-                        if (qpush) queue[qn + __popcll(msk & lt)] = make_int2((int)row, (int)m);
+                        if (qpush)
+                            queue[qn + __popcll(msk & lt)] =
+                                make_int4((int)row, (int)m, (int)T_::val(acc[1], r),
+                                          (int)T_::val(acc[2], r));
                         qn += __popcll(msk);
                     }
                     cand = cand && !lane_miss;
@@ -668,7 +773,7 @@ void scan_kernel(ScanArgs a) {
                             if (qn + 64 > kQueueCap) drain<MODE>(a, queue, qn, qbuf, lane);
                             const unsigned long long lt =
                                 (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-                            if (qpush) queue[qn + __popcll(msk & lt)] = make_int2((int)row, (int)m);
+                            if (qpush) queue[qn + __popcll(msk & lt)] = make_int4((int)row, (int)m, 0, 0);
                             qn += __popcll(msk);
                         }
                         want = want && !lane_miss;
@@ -721,7 +826,7 @@ void scan_kernel(ScanArgs a) {
                     ks = ks < KS ? ks : KS - 1;     // the spare copy repeats the last k-step
                     const frag* src = A + (tc * KS + ks) * kWave + lane;
                     const uint32_t dst = (uint32_t)(uintptr_t)(
-                        (__attribute__((address_space(3))) frag*)&s_ring[((tt & 3) * KS + ks) * kWave]);
+                        (__attribute__((address_space(3))) frag*)&s_ring[((tt & (NSLOT - 1)) * KS + ks) * kWave]);
                     asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
                                  :
                                  : "s"(__builtin_amdgcn_readfirstlane(dst)), "v"(src)
@@ -737,7 +842,7 @@ void scan_kernel(ScanArgs a) {
             };
             auto lread = [&](const int64_t tt, frag (&Af)[KS]) {
 #pragma unroll
-                for (int s = 0; s < KS; ++s) Af[s] = s_ring[((tt & 3) * KS + s) * kWave + lane];
+                for (int s = 0; s < KS; ++s) Af[s] = s_ring[((tt & (NSLOT - 1)) * KS + s) * kWave + lane];
             };
             auto thr = [&](const int64_t tt) { return cload(a.theta + (tt < t1 ? tt : t1 - 1)); };
             frag Af[KS];
@@ -747,7 +852,32 @@ void scan_kernel(ScanArgs a) {
             block_barrier();
             issue(t0);
             issue(t0 + 1);
-            if constexpr (PF == 4) {
+            if constexpr (PF == 5) {
+                // two tiles per step (two accumulator sets, one barrier per
+                // step), four tiles in flight: the copies issued in a step go
+                // into the slots read two steps before, which every wave has
+                // finished reading once it has passed the previous barrier
+                issue(t0 + 2);
+                issue(t0 + 3);
+                frag Ag[KS];
+                for (int64_t t = t0; t < t1; t += 2) {
+                    issue(t + 4);
+                    issue(t + 5);
+                    // tiles t and t+1 landed; t+2 .. t+5 may be in flight
+                    __builtin_amdgcn_s_waitcnt((4 * LPW) | (0x7 << 4) | (0xF << 8));
+                    block_barrier();
+                    lread(t, Af);
+                    lread(t + 1, Ag);
+                    const float th0 = thr(t), th1 = thr(t + 1);
+                    acc_t c0[NC], c1[NC];
+                    mma_tile(Af, c0);
+                    mma_tile(Ag, c1);
+                    if (__any(screen_max(c0, th0) > 0.0f)) screen_cands(t, c0, th0);
+                    if (t + 1 < t1 && __any(screen_max(c1, th1) > 0.0f))
+                        screen_cands(t + 1, c1, th1);
+                }
+                __builtin_amdgcn_s_waitcnt(0);
+            } else if constexpr (PF == 4) {
                 // one accumulator set, tile after tile: the MFMA / screen overlap
                 // comes from the other waves of the SIMD (three per SIMD)
                 for (int64_t t = t0; t < t1; ++t) {
@@ -887,5 +1017,19 @@ inline hipError_t launch_one(const kx::ScanArgs& a, int grid, hipStream_t st) {
     int g = (int)(grid < resident ? grid : resident);
     hipLaunchKernelGGL(kern, dim3(g), dim3(256), lds, st, a);
     return hipGetLastError();
+}
+
+// Complete-SNP screen pass with the A-operand pipeline selected by a.ring:
+// 0 register double buffer (2 waves per SIMD), 1 LDS ring with the two-tile
+// software pipeline, 2 LDS ring one tile at a time (3 waves per SIMD),
+// 3 LDS ring two tiles per step (2 waves per SIMD).
+template <int E, int KS>
+inline hipError_t launch_diag_screen(const kx::ScanArgs& a, int grid, hipStream_t st) {
+    switch (a.ring) {
+        case 3: return launch_one<E, KS, kx::DIAG, kx::SCREEN, 5, 2>(a, grid, st);
+        case 2: return launch_one<E, KS, kx::DIAG, kx::SCREEN, 4, 3>(a, grid, st);
+        case 1: return launch_one<E, KS, kx::DIAG, kx::SCREEN, 3>(a, grid, st);
+        default: return launch_one<E, KS, kx::DIAG, kx::SCREEN, 2>(a, grid, st);
+    }
 }
 }  // namespace kx

@@ -73,7 +73,21 @@ struct TiledShape {
     static constexpr int ACC = NP * WT * WS * NC * 16;   // accumulator registers
     static constexpr int WPE_MIN = (V == 1 && ACC <= 128) ? 2 : 1;
     static constexpr int RING_BYTES = V == 0 ? 128 * 1024 : 72 * 1024;
+    static constexpr int KC = 2;                         // k-steps per chunk
+    static constexpr int NF = 2 * WT * KC * NP + 2 * WS * KC * NC;   // fragments per chunk
+    // ring of R chunk slots of NF fragments (64 lanes x 16 bytes each)
+    static constexpr int R = NF * kWave * 16 * 4 <= RING_BYTES ? 4 : 3;
+    static constexpr int RING_USED = R * NF * kWave * 16;
 };
+
+// The missing-genotype form re-ranks pairs in its epilogue with per-wave LDS
+// scratch (coop_lds_entries); the ring is idle then and holds it when large
+// enough, else the launch adds dynamic LDS.
+template <int FORM, bool SPLIT, int V>
+__host__ __device__ inline bool tiled_scratch_in_ring(int K) {
+    return (int64_t)kWavesPerBlock * coop_lds_entries(K) * (int64_t)sizeof(int16_t) <=
+           TiledShape<FORM, SPLIT, V>::RING_USED;
+}
 
 template <int E, int FORM, int MODE, bool SPLIT, int V>
 __global__ __launch_bounds__(256)
@@ -86,25 +100,26 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
     constexpr int NC = SH::NC;
     constexpr int WS = SH::WS;                         // SNP tiles per wave
     constexpr int NP = SH::NP;                         // A planes
-    constexpr int KC = 2;                              // k-steps per chunk
+    constexpr int KC = SH::KC;                         // k-steps per chunk
     constexpr int WT = SH::WT;                         // trait tiles per wave
     constexpr int BT = 2 * WT;                         // trait tiles per block
     constexpr int BS = 2 * WS;                         // SNP tiles per block
     constexpr int NFA = BT * KC * NP;                  // A fragments per chunk
     constexpr int NFB = BS * KC * NC;                  // B fragments per chunk
     constexpr int NF = NFA + NFB;
+    static_assert(NF == SH::NF, "fragment count");
     constexpr int FPW = NF / kWavesPerBlock;           // copies per wave per chunk (NF % 4 == 0)
     static_assert(NF % kWavesPerBlock == 0, "every wave copies the same number of fragments");
     constexpr bool QUEUE = FORM == MISS3;
     // ring of R chunk slots filled D = R - 1 chunks ahead by LDS-DMA copies
-    constexpr int R = NF * kWave * 16 * 4 <= SH::RING_BYTES ? 4 : 3;
+    constexpr int R = SH::R;
     static_assert(NF * kWave * 16 * R <= 128 * 1024, "ring fits the LDS budget");
     constexpr int D = R - 1;
     constexpr int kWaitVm = (D - 1) * FPW;
     static_assert(kWaitVm <= 63, "wait count fits the vmcnt field");
 
     __shared__ frag s_buf[R][NF][kWave];
-    __shared__ int2 s_queue[QUEUE ? kWavesPerBlock : 1][QUEUE ? kQueueCap : 1];
+    __shared__ int4 s_queue[QUEUE ? kWavesPerBlock : 1][QUEUE ? kQueueCap : 1];
     __shared__ uint4 s_stage[MODE == SCREEN ? kWavesPerBlock : 1][kStageCap];
     __shared__ ScanArgs s_args;
     extern __shared__ __attribute__((aligned(16))) int16_t s_qbuf[];
@@ -113,10 +128,12 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
-    int2* queue = s_queue[QUEUE ? wave : 0];
+    int4* queue = s_queue[QUEUE ? wave : 0];
     uint4* stage = s_stage[MODE == SCREEN ? wave : 0];
     int sn = 0, qn = 0;
-    int16_t* qbuf = s_qbuf + (QUEUE ? wave * coop_lds_entries(a.K) : 0);
+    int16_t* qbuf = (QUEUE && tiled_scratch_in_ring<FORM, SPLIT, V>(a.K) ? (int16_t*)&s_buf[0][0][0]
+                                                                          : s_qbuf) +
+                    (QUEUE ? wave * coop_lds_entries(a.K) : 0);
 
     if (a.want_flag == 1 && a.tile_flags[a.n_snp_tiles] == 0) return;
     int64_t n_rows = a.n_rows;
@@ -255,8 +272,10 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
                                 acc[p][ti][j][c] = T_::mma(fa[p][ti], fb[j][c], acc[p][ti][j][c]);
             }
         }
-        // the clamped copies past the last chunk are still landing
+        // the clamped copies past the last chunk are still landing; with the
+        // re-rank scratch in the ring, every wave's copies must have landed
         __builtin_amdgcn_s_waitcnt(0);
+        if constexpr (QUEUE) block_barrier();
 
         // epilogue over the wave's 2 x WS output tiles
 #pragma unroll
@@ -297,7 +316,9 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
                                 if (qn + 64 > kQueueCap) drain<MODE>(a, queue, qn, qbuf, lane);
                                 const unsigned long long lt =
                                     (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-                                if (qpush) queue[qn + __popcll(msk & lt)] = make_int2((int)row, (int)m);
+                                if (qpush)
+                                    queue[qn + __popcll(msk & lt)] =
+                                        make_int4((int)row, (int)m, (int)v1, (int)v2);
                                 qn += __popcll(msk);
                             }
                             cand = cand && !lk.miss;
@@ -321,7 +342,7 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
                         if (msk) {
                             if (qn + 64 > kQueueCap) drain<MODE>(a, queue, qn, qbuf, lane);
                             const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-                            if (qpush) queue[qn + __popcll(msk & lt)] = make_int2((int)row, (int)m);
+                            if (qpush) queue[qn + __popcll(msk & lt)] = make_int4((int)row, (int)m, 0, 0);
                             qn += __popcll(msk);
                         }
                         want = want && !lk.miss;
@@ -383,7 +404,10 @@ __global__ __launch_bounds__(256) void expand_columns(const int8_t* __restrict__
 
 template <int E, int FORM, int MODE, bool SPLIT>
 inline hipError_t launch_tiled(const ScanArgs& a, const TiledArgs& ta, int grid, hipStream_t st) {
-    size_t lds = FORM == MISS3 ? (size_t)kWavesPerBlock * coop_lds_entries(a.K) * sizeof(int16_t) : 0;
+    const bool in_ring = ta.shape ? tiled_scratch_in_ring<FORM, SPLIT, 1>(a.K)
+                                  : tiled_scratch_in_ring<FORM, SPLIT, 0>(a.K);
+    size_t lds = FORM == MISS3 && !in_ring
+                     ? (size_t)kWavesPerBlock * coop_lds_entries(a.K) * sizeof(int16_t) : 0;
     auto kern = ta.shape ? scan_tiled<E, FORM, MODE, SPLIT, 1> : scan_tiled<E, FORM, MODE, SPLIT, 0>;
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 256, lds) != hipSuccess || occ < 1)
