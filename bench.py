@@ -191,8 +191,8 @@ def paper_scale_hits(args, ctx, torch, np, datagen, krux):
                             "speedup_of_fp16": (pairs / (ms / 1e3)) / (pairs / (ms64 / 1e3)),
                             "peak_fp64_tflops": PEAK_FP64_TFLOPS}
         n8 = max(3, args.steps // 2)
-        log("int8 path: 1 warmup + %d timed steps" % n8)
-        ms8, res8, k8ms, _ = runner.run(step_for("int8"), n8, 1)
+        log("int8 path: %d warmup + %d timed steps" % (max(1, args.warmup // 2), n8))
+        ms8, res8, k8ms, _ = runner.run(step_for("int8"), n8, max(1, args.warmup // 2))
         same8 = same_hits(krux.unpack_hits(res8), hits16)
         out["int8"] = {"value": pairs / (ms8 / 1e3), "unit": "pairs/s", "ms_per_step": ms8,
                        "kernel_ms": k8ms,
@@ -405,8 +405,8 @@ WORKLOADS = {"paper_scale_hits": paper_scale_hits, "precision_K500": precision_k
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="paper_scale_hits")
     ap.add_argument("--T", type=int, default=None, help="override trait count")
     ap.add_argument("--M", type=int, default=None, help="override SNP count")

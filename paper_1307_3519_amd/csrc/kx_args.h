@@ -67,7 +67,7 @@ struct ScanArgs {
     double* H_out;            // FULL: [T][M]
     double* p_out;
     int32_t* sums_out;        // SUMS: [3][T][M]
-    // pairs that passed the fp32 screen, evaluated exactly by scan_candidates:
+    // pairs that passed the fp32 screen, evaluated exactly by scan_exact:
     // {operand row, SNP | form << 31, column-1 value, column-2 value}
     uint4* cand;
     int64_t cand_cap;

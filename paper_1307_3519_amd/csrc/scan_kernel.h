@@ -512,7 +512,7 @@ __device__ __attribute__((noinline)) double coop_exact_call(const ScanArgs& a, i
 
 // Empties a wave's queue of screened pairs of SNPs with missing genotypes.
 // In screen mode the pairs go to the global buffer (one atomic per burst) for
-// scan_missing, which runs them at full occupancy instead of stalling the
+// scan_exact, which runs them at full occupancy instead of stalling the
 // scan; pairs beyond its capacity, and the FULL / SUMS outputs, are
 // evaluated here.
 template <int MODE>
@@ -884,6 +884,10 @@ void scan_kernel(ScanArgs a) {
                     issue(t + 2);
                     arrive();
                     lread(t, Af);
+                    // all k-steps of the tile are read before the first MFMA
+                    // (one LDS latency per tile; left to itself the scheduler
+                    // interleaves pairs of reads with the MFMAs)
+                    __builtin_amdgcn_sched_barrier(0);
                     const float th = thr(t);
                     acc_t c[NC];
                     mma_tile(Af, c);
