@@ -372,8 +372,10 @@ krux_status run_screen(krux_ctx* c, kx::ScanArgs a, const Variant& v, const Colu
     a.cand = (uint4*)ws(c, S_CAND, (size_t)a.cand_cap * sizeof(uint4), &s);
     a.n_cand = (unsigned long long*)ws(c, S_NCAND, 256, &s);
     // pairs of SNPs with missing genotypes that pass the bound: up to 1/16 of
-    // the pairs, at most 2^25 entries (512 MB); the rest are evaluated in the scan
-    a.mcand_cap = std::min<int64_t>(std::max<int64_t>(n_rows_max * a.M / 16, 1 << 16), 1LL << 25);
+    // the pairs, at most 2^27 entries (2 GB of the 288 GB); the rest are
+    // evaluated in the scan kernel itself, which is several times slower (at
+    // the 64/M screen level of a min-p run, a few percent of the pairs pass)
+    a.mcand_cap = std::min<int64_t>(std::max<int64_t>(n_rows_max * a.M / 16, 1 << 16), 1LL << 27);
     a.mcand = (int4*)ws(c, S_MCAND, (size_t)a.mcand_cap * sizeof(int4), &s);
     a.n_mcand = a.n_cand + 1;      // both counters were cleared by the preceding prep kernel
     if (s != KRUX_OK) return s;

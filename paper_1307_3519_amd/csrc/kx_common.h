@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <utility>
 
 namespace kx {
 
@@ -65,6 +66,19 @@ struct HitRec {
 static_assert(sizeof(HitRec) == 24, "hit record is 24 bytes");
 
 __host__ __device__ inline int64_t cube_minus(int64_t k) { return k * k * k - k; }
+
+// f(std::integral_constant<int, i>) for i = 0 .. N-1, expanded at compile
+// time: loop indices that select registers (accumulator tiles, vector
+// elements) stay constants even where the compiler would not unroll a large
+// loop body, which would otherwise put the whole array in scratch memory.
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 __device__ inline int bitlen64(uint64_t v) { return v ? 64 - __builtin_clzll(v) : 0; }
 

@@ -277,37 +277,42 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
         __builtin_amdgcn_s_waitcnt(0);
         if constexpr (QUEUE) block_barrier();
 
-        // epilogue over the wave's 2 x WS output tiles
-#pragma unroll
-        for (int j = 0; j < WS; ++j) {
-            if (!act[j]) continue;
+        // epilogue over the wave's 2 x WS output tiles (compile-time indices
+        // throughout: see static_for)
+        static_for<WS>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            if (!act[j]) return;
             const int64_t m = stl[j] * kTile + (lane & 31);
             const SnpInfo inf = gload(a.info + m);
             const LaneK lk = lane_constants(inf, a.K, a.inv_hc);
-#pragma unroll
-            for (int ti = 0; ti < WT; ++ti) {
+            static_for<WT>([&](auto tic) {
+                constexpr int ti = decltype(tic)::value;
                 const int64_t tt = tb * BT + (wave >> 1) * WT + ti;
-                if (tt >= n_tiles) continue;
+                if (tt >= n_tiles) return;
                 const int64_t rb = tt * kTile + 4 * (lane >> 5);
-                auto colv = [&](int c, int r) -> float {
+                auto colv = [&](auto cc, auto rc) -> float {
+                    constexpr int c = decltype(cc)::value, r = decltype(rc)::value;
                     if constexpr (SPLIT)
                         return (float)(128 * acc[1][ti][j][c][r] + acc[0][ti][j][c][r]);
                     else
                         return T_::val(acc[0][ti][j][c], r);
                 };
+                using C0 = std::integral_constant<int, 0>;
+                using C1 = std::integral_constant<int, 1>;
+                using CL = std::integral_constant<int, NC - 1>;
                 if constexpr (MODE == SCREEN) {
                     const float th = cload(a.theta + tt);
                     float gmax = -__builtin_inff();
-#pragma unroll
-                    for (int r = 0; r < 16; ++r)
-                        gmax = fmaxf(gmax, screen_value<FORM>(lk, th, colv(0, r), colv(1, r),
-                                                              NC == 3 ? colv(NC - 1, r) : 0.0f));
-                    if (!__any(gmax > 0.0f)) continue;
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) {
+                    static_for<16>([&](auto rc) {
+                        gmax = fmaxf(gmax, screen_value<FORM>(lk, th, colv(C0{}, rc), colv(C1{}, rc),
+                                                              NC == 3 ? colv(CL{}, rc) : 0.0f));
+                    });
+                    if (!__any(gmax > 0.0f)) return;
+                    static_for<16>([&](auto rc) {
+                        constexpr int r = decltype(rc)::value;
                         const int64_t row = rb + 8 * (r >> 2) + (r & 3);
-                        const float v0 = colv(0, r), v1 = colv(1, r);
-                        const float v2 = NC == 3 ? colv(NC - 1, r) : 0.0f;
+                        const float v0 = colv(C0{}, rc), v1 = colv(C1{}, rc);
+                        const float v2 = NC == 3 ? colv(CL{}, rc) : 0.0f;
                         bool cand = screen_value<FORM>(lk, th, v0, v1, v2) > 0.0f;
                         if constexpr (QUEUE) {
                             const bool qpush = cand && lk.miss;
@@ -329,11 +334,11 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
                             stage_candidates(a, &s_args, stage, sn, lane, cand, row, m, v0, v1, kCandPlain);
                         else
                             stage_candidates(a, &s_args, stage, sn, lane, cand, row, m, v1, v2, kCandPlain);
-                    }
+                    });
                     if (QUEUE && qn) drain<MODE>(a, queue, qn, qbuf, lane);
                 } else if constexpr (FORM == MISS3) {
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) {
+                    static_for<16>([&](auto rc) {
+                        constexpr int r = decltype(rc)::value;
                         const int64_t row = rb + 8 * (r >> 2) + (r & 3);
                         const int64_t v = a.row_v[row];
                         bool want = v >= 0 && m < a.M;
@@ -347,19 +352,19 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
                         }
                         want = want && !lk.miss;
                         if (want) {
-                            const int64_t D0 = (int64_t)colv(0, r), D1 = (int64_t)colv(1, r),
-                                          D2 = (int64_t)colv(2, r);
+                            const int64_t D0 = (int64_t)colv(C0{}, rc), D1 = (int64_t)colv(C1{}, rc),
+                                          D2 = (int64_t)colv(CL{}, rc);
                             const double H = exact_H(D0, D1, D2, inf.n0, inf.n1, inf.n2, a.K,
                                                      a.tiesum[v % a.T], snp_df(inf));
                             const int64_t k1 = a.K + 1;
                             emit_full<MODE>(a, v, m, H, snp_df(inf), D0 + inf.n0 * k1,
                                             D1 + inf.n1 * k1, D2 + inf.n2 * k1);
                         }
-                    }
+                    });
                     if (qn) drain<MODE>(a, queue, qn, qbuf, lane);
                 }
-            }
-        }
+            });
+        });
     }
     if constexpr (MODE == SCREEN) flush_stage(a, &s_args, stage, sn, lane);
 }
