@@ -724,7 +724,9 @@ void scan_kernel(ScanArgs a) {
                     stage_candidates(a, &s_args, stage, sn, lane, cand, row, m, T_::val(acc[1], r),
                                      T_::val(acc[2], r), kCandPlain);
             }
-            if (QUEUE && qn) drain<MODE>(a, queue, qn, qbuf, lane);
+            // screen mode: the queue carries over to the next tile and is
+            // drained when nearly full and at the end of the kernel (one
+            // atomic per burst of up to 128 pairs, not one per tile)
         };
         // largest screen value of a tile (VALU only, no branches)
         auto screen_max = [&](const acc_t (&acc)[NC], const float th) -> float {
@@ -993,6 +995,9 @@ void scan_kernel(ScanArgs a) {
                 }
             }
         }
+    }
+    if constexpr (QUEUE && MODE == SCREEN) {
+        if (qn) drain<MODE>(a, queue, qn, qbuf, lane);
     }
     if constexpr (MODE == SCREEN) flush_stage(a, &s_args, stage, sn, lane);
 }

@@ -335,7 +335,8 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
                         else
                             stage_candidates(a, &s_args, stage, sn, lane, cand, row, m, v1, v2, kCandPlain);
                     });
-                    if (QUEUE && qn) drain<MODE>(a, queue, qn, qbuf, lane);
+                    // the queue carries over to the next tile (drained when
+                    // nearly full and at the end of the kernel)
                 } else if constexpr (FORM == MISS3) {
                     static_for<16>([&](auto rc) {
                         constexpr int r = decltype(rc)::value;
@@ -365,6 +366,9 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
                 }
             });
         });
+    }
+    if constexpr (QUEUE && MODE == SCREEN) {
+        if (qn) drain<MODE>(a, queue, qn, qbuf, lane);
     }
     if constexpr (MODE == SCREEN) flush_stage(a, &s_args, stage, sn, lane);
 }
