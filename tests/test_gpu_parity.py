@@ -93,7 +93,11 @@ CASES = [  # (K, T, M, p_missing)
     # tiled large-K kernels: ragged trait blocks (T % 128) and SNP blocks (M % 128),
     # the DIAG / PLAIN boundary at K = 400 / 401, byte-split int8 ranks
     (129, 70, 100, 0.0), (150, 140, 161, 0.0), (233, 65, 97, 0.02), (400, 40, 70, 0.0),
-    (401, 36, 45, 0.0), (500, 37, 70, 0.01), (1000, 33, 40, 0.0)]
+    (401, 36, 45, 0.0), (500, 37, 70, 0.01), (1000, 33, 40, 0.0),
+    # missing genotypes at large K: re-rank scratch in the LDS ring, and at
+    # the fp16 limit K = 2049 the rank bitmap no longer fits one wave (binary
+    # search path)
+    (1000, 40, 60, 0.02), (2049, 33, 40, 0.02)]
 
 
 @pytest.mark.parametrize("prec", ["fp16", "int8", "fp64"])
