@@ -108,12 +108,9 @@ __device__ inline bool missing_pair_may_pass(const ScanArgs& a, int64_t v, int64
     return !(Hup * (1.0 + 1e-9) < a.hc_screen[df]);
 }
 
-// One launch evaluates both buffers filled by the scan kernels:
-//  * candidates of complete SNPs, one lane each: exact H from the pair's
-//    exact MFMA column values (eq. (2) with the tie factor), p, hit / min p;
-//  * pairs of SNPs with missing genotypes, one wave each: a rank-aware bound
-//    (missing_pair_may_pass) drops most of them; for the rest the ranks are
-//    re-derived over the kept samples (coop_exact), then the same.
+// Exact evaluation of the candidates of complete SNPs, one lane each: exact
+// H from the pair's exact MFMA column values (eq. (2) with the tie factor),
+// p, hit / min p.
 __global__ __launch_bounds__(256) void scan_exact(ScanArgs a) {
     int64_t n = (int64_t)*a.n_cand;
     if (n > a.cand_cap) n = a.cand_cap;
@@ -123,7 +120,19 @@ __global__ __launch_bounds__(256) void scan_exact(ScanArgs a) {
         eval_candidate(a, (int64_t)e.x, (int64_t)(e.y & kCandSnp), __uint_as_float(e.z),
                        __uint_as_float(e.w), e.y & ~kCandSnp);
     }
-    if (!a.mcand) return;
+}
+
+// Pairs of SNPs with missing genotypes, one wave each: a rank-aware bound
+// (missing_pair_may_pass) drops most of them; for the rest the ranks are
+// re-derived over the kept samples (coop_exact), then as above.  The next
+// entry of the wave's stride is loaded one iteration ahead.  The pass is
+// bound by the latency of each pair's dependent gathers, so it runs at six
+// waves per SIMD (80 registers; the spills stay outside the sample loops;
+// measured on the cohort workload: 3 waves 19.5 ms, 4 16.3, 5 15.3, 6 14.9),
+// as a kernel of its own so that the complete-SNP path does not set its
+// register budget.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6)))
+void scan_exact_missing(ScanArgs a) {
     extern __shared__ __attribute__((aligned(16))) int16_t s_buf[];   // per wave coop_lds_entries(K)
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -131,22 +140,30 @@ __global__ __launch_bounds__(256) void scan_exact(ScanArgs a) {
     int64_t nm = (int64_t)*a.n_mcand;
     if (nm > a.mcand_cap) nm = a.mcand_cap;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    for (int64_t e = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; e < nm; e += waves) {
-        const int4 q = a.mcand[e];
+    int64_t e = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    int4 q = e < nm ? a.mcand[e] : make_int4(0, 0, 0, 0);
+    for (; e < nm; e += waves) {
+        const int4 qn = e + waves < nm ? a.mcand[e + waves] : make_int4(0, 0, 0, 0);
         const int64_t v = a.row_v[q.x];
-        if (v < 0) continue;             // padding row (uniform per wave)
-        if (!missing_pair_may_pass(a, v, q.y, q.z, q.w, lane)) continue;
-        int df;
-        int64_t s[3];
-        const double H = coop_exact(a, v, q.y, sb, lane, &df, s);
-        if (lane == 0) record(a, v, q.y, H, df);
+        if (v >= 0 &&                    // padding row (uniform per wave)
+            missing_pair_may_pass(a, v, q.y, q.z, q.w, lane)) {
+            int df;
+            int64_t s[3];
+            const double H = coop_exact<4>(a, v, q.y, sb, lane, &df, s);
+            if (lane == 0) record(a, v, q.y, H, df);
+        }
+        q = qn;
     }
 }
 
 }  // namespace kx
 
+// Both exact-evaluation launches of one scan (the second only when the
+// missing-genotype buffer is in use).
 extern "C" hipError_t kx_launch_exact(const kx::ScanArgs* a, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(kx::scan_exact, dim3(grid), dim3(256), 0, st, *a);
+    if (!a->mcand) return hipGetLastError();
     const size_t lds = (size_t)4 * kx::coop_lds_entries(a->K) * sizeof(int16_t);
-    hipLaunchKernelGGL(kx::scan_exact, dim3(grid), dim3(256), lds, st, *a);
+    hipLaunchKernelGGL(kx::scan_exact_missing, dim3(grid), dim3(256), lds, st, *a);
     return hipGetLastError();
 }
