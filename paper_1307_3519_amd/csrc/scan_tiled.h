@@ -135,6 +135,10 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
                                                                           : s_qbuf) +
                     (QUEUE ? wave * coop_lds_entries(a.K) : 0);
 
+    // LDS address of the ring (the LDS-DMA destination operand)
+    const uint32_t ring_lds =
+        (uint32_t)(uintptr_t)(__attribute__((address_space(3))) frag*)&s_buf[0][0][0];
+
     if (a.want_flag == 1 && a.tile_flags[a.n_snp_tiles] == 0) return;
     int64_t n_rows = a.n_rows;
     if (a.d_nrows) {
@@ -189,37 +193,53 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
         }
         if (!__syncthreads_or(any)) continue;   // block-uniform skip
 
-        // LDS-DMA copy of chunk ch (clamped into range) into slot ch % R:
-        // this wave's FPW fragments, each 64 lanes x 16 bytes, contiguous in
-        // global memory and in the slot.  Issued from inline assembly so
+        // LDS-DMA copies: the k-th round of an item fetches chunk
+        // min(k, nchunks - 1) into slot k % R, this wave's FPW fragments,
+        // each 64 lanes x 16 bytes, contiguous in global memory and in the
+        // slot.  Issued from inline assembly so
         // that the compiler does not wait for every copy in flight before
         // reading the ring; the waits below are exact.
-        auto issue_chunk = [&](int ch) {
-            const int chc = ch < nchunks ? ch : nchunks - 1;
-            const int slot = ch % R;
+        // The wave's FPW copies per chunk: per-lane source pointers at the
+        // item's first chunk, advanced by a fixed stride per chunk (up to the
+        // last chunk, which the copies past the end repeat), so that a chunk
+        // costs one 64-bit add per copy instead of the address arithmetic.
+        const frag* cp[FPW];
+        int cstride[FPW];                              // fragments per chunk
+#pragma unroll
+        for (int i = 0; i < FPW; ++i) {
+            const int f = wave * FPW + i;
+            if (f < NFA) {
+                const int p = f / (BT * KC), r = f % (BT * KC);
+                const int tt = r / KC, kk = r % KC;
+                const int64_t tile = tb * BT + tt;
+                cp[i] = (p ? Ah : A) + (tile * KS + kk) * kWave + lane;
+                cstride[i] = KC * kWave;
+            } else {
+                const int g = f - NFA;
+                const int s2 = g / (KC * NC), r = g % (KC * NC);
+                const int kk = r / NC, c = r % NC;
+                const int64_t st = sb * BS + s2;
+                cp[i] = Bf + ((st * KS + kk) * NC + c) * kWave + lane;
+                cstride[i] = KC * NC * kWave;
+            }
+        }
+        int n_issued = 0;                              // chunks issued for this item
+        auto issue_next = [&]() {
+            const uint32_t sbase = ring_lds + (uint32_t)((n_issued % R) * NF * kWave * 16) +
+                                   (uint32_t)(wave * FPW * kWave * 16);
 #pragma unroll
             for (int i = 0; i < FPW; ++i) {
-                const int f = wave * FPW + i;
-                const frag* src;
-                if (f < NFA) {
-                    const int p = f / (BT * KC), r = f % (BT * KC);
-                    const int tt = r / KC, kk = r % KC;
-                    const int64_t tile = tb * BT + tt;
-                    src = (p ? Ah : A) + (tile * KS + chc * KC + kk) * kWave + lane;
-                } else {
-                    const int g = f - NFA;
-                    const int s2 = g / (KC * NC), r = g % (KC * NC);
-                    const int kk = r / NC, c = r % NC;
-                    const int64_t st = sb * BS + s2;
-                    src = Bf + ((st * KS + chc * KC + kk) * NC + c) * kWave + lane;
-                }
-                const uint32_t dst = (uint32_t)(uintptr_t)(
-                    (__attribute__((address_space(3))) frag*)&s_buf[slot][f][0]);
+                const uint32_t dst = sbase + (uint32_t)(i * kWave * 16);
                 asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
                              :
-                             : "s"(__builtin_amdgcn_readfirstlane(dst)), "v"(src)
+                             : "s"(__builtin_amdgcn_readfirstlane(dst)), "v"(cp[i])
                              : "memory");
             }
+            if (n_issued < nchunks - 1) {
+#pragma unroll
+                for (int i = 0; i < FPW; ++i) cp[i] += cstride[i];
+            }
+            ++n_issued;
         };
         acc_t acc[NP][WT][WS][NC];
 #pragma unroll
@@ -235,7 +255,7 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
         __builtin_amdgcn_s_waitcnt(0);
         block_barrier();
 #pragma unroll
-        for (int d = 0; d < D; ++d) issue_chunk(d);
+        for (int d = 0; d < D; ++d) issue_next();
         for (int ch = 0; ch < nchunks; ++ch) {
             // this wave's copies of chunk ch have landed (the D - 1 younger
             // chunks may still be in flight); the barrier publishes every
@@ -246,7 +266,7 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
             __builtin_amdgcn_s_waitcnt((kWaitVm & 0xF) | ((kWaitVm >> 4) << 14) | (0x7 << 4) |
                                        (0xF << 8));
             block_barrier();
-            issue_chunk(ch + D);
+            issue_next();
             const int buf = ch % R;
 #pragma unroll
             for (int kk = 0; kk < KC; ++kk) {
