@@ -13,7 +13,8 @@ namespace kx {
 // G_q = K - a_q / 2 above it (a_q: doubled midrank, its tie group holds q), so
 // s_i(q) lies in [-min(N_i, L_q), min(N_i, G_q)].  The largest f over these
 // intervals, with E' >= K'^3 - K' - sumT, bounds H'.  Returns false when the
-// bound stays below the pass's screen level (never for a level of 0).  All
+// bound stays below the pass's screen level (never for a level of 0), or when
+// the pair can only matter for its row's minimum p and cannot lower it.  All
 // lanes of the wave take part; the result is uniform.
 __device__ inline bool missing_pair_may_pass(const ScanArgs& a, int64_t v, int64_t m, int d1,
                                              int d2, int lane) {
@@ -104,8 +105,17 @@ __device__ inline bool missing_pair_may_pass(const ScanArgs& a, int64_t v, int64
         const int64_t x = max(x0 < 0 ? -x0 : x0, x1 < 0 ? -x1 : x1);
         f += (double)(x * x) / (double)n[i];
     }
-    const double Hup = 3.0 * (double)(kp - 1) * f / (double)E;
-    return !(Hup * (1.0 + 1e-9) < a.hc_screen[df]);
+    const double Hup = 3.0 * (double)(kp - 1) * f / (double)E * (1.0 + 1e-9);
+    if (Hup < a.hc_screen[df]) return false;
+    // Below every count level and the hit level the pair matters only for
+    // its row's minimum p: skip it when even its bound cannot lower the
+    // minimum found so far (read without synchronisation: a stale, larger
+    // value only skips less)
+    bool counted = false;
+    for (int l = 0; l < a.n_lev; ++l) counted = counted || !(Hup < a.hc[l][df - 1]);
+    if (counted || !a.minp_bits) return true;
+    const double cur = __longlong_as_double((long long)a.minp_bits[v]);
+    return pvalue(Hup, df) < cur;
 }
 
 // Exact evaluation of the candidates of complete SNPs, one lane each: exact
