@@ -279,6 +279,33 @@ def test_missing_genotype_equals_kept_samples():
         assert oracle.one_pair(x[t], g2)["H"] == o["H"]
 
 
+def test_missing_expression_equals_kept_samples():
+    # a NaN expression value removes the sample from the pair ("Handling
+    # missing values"): same as scipy on the samples observed on both sides,
+    # and same as the oracle on the reduced sample set
+    K = 50
+    x, g, rs = _random_pairs(19, K, 40)
+    g = datagen.set_missing(rs["missing"], g, 0.1)
+    rng = np.random.default_rng(19)
+    x = x.copy()
+    x[rng.random(x.shape) < 0.12] = np.nan
+    x[0, :] = np.nan
+    x[1, 1:] = np.nan
+    for t in range(40):
+        o = oracle.one_pair(x[t], g[t])
+        keep = (g[t] >= 0) & ~np.isnan(x[t])
+        H, p, df = _scipy_kw(x[t][keep], g[t][keep])
+        assert o["kobs"] == keep.sum()
+        assert o["df"] == df
+        if keep.sum() < 2 or df == 0:
+            assert o["H"] == 0.0 and o["p"] == 1.0
+            continue
+        tol = 1e-14 * 3 * (K + 1) / max(H, 1e-300) + 1e-13
+        assert o["H"] == pytest.approx(H, rel=tol, abs=1e-12)
+        sub = oracle.one_pair(x[t][keep], g[t][keep])
+        assert sub["H"] == o["H"] and sub["p"] == o["p"] and sub["tiesum"] == o["tiesum"]
+
+
 # ---------------------------------------------------------------- rounding
 def test_rational_to_double_matches_fraction():
     rng = np.random.default_rng(16)
