@@ -110,8 +110,12 @@ krux_status krux_rank(krux_ctx* ctx, const float* expr, int64_t T, int32_t K,
 
 /* Kruskal-Wallis test of every trait against every SNP of a slice
  * (eq. (1), eq. (2), tie factor, P-value calculation; data slicing).
- *   ranks2, tiesum  from krux_rank; every row must be complete (no 0 rank:
- *                   missing expression values are not handled by this call).
+ *   ranks2, tiesum  from krux_rank.  A 0 rank marks a missing (NaN)
+ *                   expression value: such a sample is left out of every pair
+ *                   of its trait, as a missing genotype is, and the ranks,
+ *                   tie term, group sizes and df of the pair are taken over
+ *                   the samples observed on both sides (traits with a 0 rank
+ *                   are evaluated exactly per pair, outside the MFMA scan).
  *   geno            M x K int8, row stride ld_geno >= K (bytes).
  *   snp_base        added to the SNP index of every hit (slice start).
  *   p_c             p-value threshold, (0, 1] (HITS mode).

@@ -24,7 +24,7 @@ enum Slot {
     S_LIST_A, S_LIST_B, S_COUNT_A, S_COUNT_B, S_MINP, S_STAGE, S_NHITS, S_KEYS, S_IDX,
     S_SORT_TMP, S_F64_R, S_F64_I, S_F64_S, S_COUNT_PREV, S_CAND, S_NCAND, S_MCAND, S_NMCAND,
     S_TUNE_HITS, S_TUNE_N,
-    S_AH, S_AH2, S_BF, S_BF3,
+    S_AH, S_AH2, S_BF, S_BF3, S_NAN_FLAG, S_NAN_LIST, S_NAN_N,
     S_N_SLOTS
 };
 
@@ -198,7 +198,7 @@ struct Columns {
 krux_status prep_ranks(krux_ctx* c, const Variant& v, const int16_t* ranks2, const int64_t* tiesum,
                        int64_t T, int K, const int32_t* perms, const int32_t* rows,
                        const int32_t* d_nrows, int64_t n_rows, int slotA, int slotTh, int slotRv,
-                       hipStream_t st, RankSide* out, int slotAh = -1) {
+                       hipStream_t st, RankSide* out, int slotAh, const uint8_t* nan_flag) {
     krux_status s = KRUX_OK;
     // the tiled kernel reads whole blocks of up to 8 trait tiles
     const int64_t n_alloc = v.tiled ? ceil_div(std::max<int64_t>(n_rows, 1), 256) * 256
@@ -216,10 +216,43 @@ krux_status prep_ranks(krux_ctx* c, const Variant& v, const int16_t* ranks2, con
     // the prep kernel also clears the candidate counters of the scan that follows it
     a.zero = (unsigned long long*)ws(c, S_NCAND, 256, &s);
     a.n_zero = 2;
+    a.nan_flag = nan_flag;
     if (s != KRUX_OK) return s;
     int64_t total = n_tiles * v.ks * kx::kWave;
     int grid = (int)std::min<int64_t>(ceil_div(total, 256), (int64_t)c->n_cu * 16);
     HIP_TRY(c, kx_launch_prep(&a, v.elem == kx::I8 ? 1 : 0, std::max(grid, 1), st));
+    return KRUX_OK;
+}
+
+// Traits with missing expression values (a rank of 0): a flag per trait for
+// the operand preparation, which turns their rows into padding, and the list
+// that scan_nan_traits walks after the scan.  Stream-ordered, no host sync.
+struct NanSide {
+    uint8_t* flag = nullptr;
+    int32_t* list = nullptr;
+    int32_t* n = nullptr;
+};
+
+krux_status flag_nan(krux_ctx* c, const int16_t* ranks2, int64_t T, int K, hipStream_t st,
+                     NanSide* out) {
+    krux_status s = KRUX_OK;
+    out->flag = (uint8_t*)ws(c, S_NAN_FLAG, (size_t)std::max<int64_t>(T, 1), &s);
+    out->list = (int32_t*)ws(c, S_NAN_LIST, (size_t)std::max<int64_t>(T, 1) * 4, &s);
+    out->n = (int32_t*)ws(c, S_NAN_N, 256, &s);
+    if (s != KRUX_OK) return s;
+    HIP_TRY(c, kx_launch_fill_i32(out->n, 1, 0, st));
+    if (T > 0) {
+        const int grid = (int)std::min<int64_t>(ceil_div(T, 4), (int64_t)c->n_cu * 8);
+        HIP_TRY(c, kx_launch_flag_nan(ranks2, T, K, out->flag, out->list, out->n, grid, st));
+    }
+    return KRUX_OK;
+}
+
+// Exact evaluation of every pair of the flagged traits (P permutations).
+krux_status run_nan_traits(krux_ctx* c, const kx::ScanArgs& a, const NanSide& ns, int P,
+                           int mode, hipStream_t st) {
+    if (a.M <= 0) return KRUX_OK;
+    HIP_TRY(c, kx_launch_nan_traits(&a, ns.list, ns.n, P, mode, c->n_cu * 8, st));
     return KRUX_OK;
 }
 
@@ -418,7 +451,7 @@ double screen_level_for_min_p(double p_c, int64_t M) {
 krux_status resolve_min_p(krux_ctx* c, kx::ScanArgs base, const Variant& v, const Columns& col,
                           const int16_t* ranks2, const int64_t* tiesum, int64_t T, int K,
                           const int32_t* perms, int64_t V, double p_main, int64_t M,
-                          hipStream_t st) {
+                          const uint8_t* nan_flag, hipStream_t st) {
     std::vector<double> levels;
     double p_mid = std::min(1.0, std::max(p_main * 16.0, 1024.0 / std::max<int64_t>(M, 1)));
     if (p_mid > p_main && p_mid < 1.0) levels.push_back(p_mid);
@@ -443,7 +476,7 @@ krux_status resolve_min_p(krux_ctx* c, kx::ScanArgs base, const Variant& v, cons
         p_prev = levels[li];
         RankSide r2;
         s = prep_ranks(c, v, ranks2, tiesum, T, K, perms, rows_out, n_out, V, S_A2, S_THETA2,
-                       S_ROWV2, st, &r2, S_AH2);
+                       S_ROWV2, st, &r2, S_AH2, nan_flag);
         if (s != KRUX_OK) return s;
         kx::ScanArgs a = base;
         a.A = r2.A; a.theta = r2.theta; a.row_v = r2.row_v;
@@ -513,9 +546,11 @@ krux_status test_impl(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum,
     if ((s = pack_snps(c, geno, M, ld_geno, K, v.form == kx::DIAG, row_bytes(v), st, &sn)) != KRUX_OK) return s;
     Columns col;
     if ((s = expand_columns(c, v, sn, st, &col)) != KRUX_OK) return s;
+    NanSide ns;
+    if ((s = flag_nan(c, ranks2, T, K, st, &ns)) != KRUX_OK) return s;
     RankSide rk;
     if ((s = prep_ranks(c, v, ranks2, tiesum, T, K, nullptr, nullptr, nullptr, T, S_A, S_THETA,
-                        S_ROWV, st, &rk, S_AH)) != KRUX_OK)
+                        S_ROWV, st, &rk, S_AH, ns.flag)) != KRUX_OK)
         return s;
 
     kx::ScanArgs a{};
@@ -534,8 +569,9 @@ krux_status test_impl(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum,
         if (items <= 0) return KRUX_OK;
         int grid = (int)std::min<int64_t>(items, (int64_t)INT32_MAX);
         a.want_flag = -1;
-        return launch_scan(c, a, v, col, rk.A_hi, kx::MISS3,
-                           mode == KRUX_MODE_FULL ? kx::FULL : kx::SUMS, grid, st);
+        const int km = mode == KRUX_MODE_FULL ? kx::FULL : kx::SUMS;
+        if ((s = launch_scan(c, a, v, col, rk.A_hi, kx::MISS3, km, grid, st)) != KRUX_OK) return s;
+        return run_nan_traits(c, a, ns, 1, km, st);
     }
 
     int64_t cap = hit_capacity;
@@ -557,8 +593,10 @@ krux_status test_impl(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum,
     set_screen(&a, p_screen);
     a.cand_cap = candidate_capacity(T, M, p_screen);
     if ((s = run_screen(c, a, v, col, rk.A_hi, st, T, true)) != KRUX_OK) return s;
+    if ((s = run_nan_traits(c, a, ns, 1, kx::SCREEN, st)) != KRUX_OK) return s;
     if (min_p && T > 0) {
-        if ((s = resolve_min_p(c, a, v, col, ranks2, tiesum, T, K, nullptr, T, p_screen, M, st)) != KRUX_OK)
+        if ((s = resolve_min_p(c, a, v, col, ranks2, tiesum, T, K, nullptr, T, p_screen, M,
+                               ns.flag, st)) != KRUX_OK)
             return s;
         HIP_TRY(c, kx_launch_bits_to_double(minp, T, min_p, st));
     }
@@ -719,9 +757,11 @@ krux_status krux_permute(krux_ctx* c, const int16_t* ranks2, const int64_t* ties
     if ((s = pack_snps(c, geno, M, ld_geno, K, v.form == kx::DIAG, row_bytes(v), st, &sn)) != KRUX_OK) return s;
     Columns col;
     if ((s = expand_columns(c, v, sn, st, &col)) != KRUX_OK) return s;
+    NanSide ns;
+    if ((s = flag_nan(c, ranks2, T, K, st, &ns)) != KRUX_OK) return s;
     RankSide rk;
     if ((s = prep_ranks(c, v, ranks2, tiesum, T, K, perms, nullptr, nullptr, V, S_A, S_THETA,
-                        S_ROWV, st, &rk, S_AH)) != KRUX_OK)
+                        S_ROWV, st, &rk, S_AH, ns.flag)) != KRUX_OK)
         return s;
     unsigned long long* minp =
         (unsigned long long*)ws(c, S_MINP, (size_t)std::max<int64_t>(V, 1) * 8, &s);
@@ -742,8 +782,10 @@ krux_status krux_permute(krux_ctx* c, const int16_t* ranks2, const int64_t* ties
     set_screen(&a, loosest);
     a.cand_cap = candidate_capacity(V, M, loosest);
     if ((s = run_screen(c, a, v, col, rk.A_hi, st, V, true)) != KRUX_OK) return s;
+    if ((s = run_nan_traits(c, a, ns, P, kx::SCREEN, st)) != KRUX_OK) return s;
     if (min_p && V > 0) {
-        if ((s = resolve_min_p(c, a, v, col, ranks2, tiesum, T, K, perms, V, loosest, M, st)) != KRUX_OK)
+        if ((s = resolve_min_p(c, a, v, col, ranks2, tiesum, T, K, perms, V, loosest, M, ns.flag,
+                               st)) != KRUX_OK)
             return s;
         HIP_TRY(c, kx_launch_bits_to_double(minp, V, min_p, st));
     }

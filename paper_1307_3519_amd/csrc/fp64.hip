@@ -65,20 +65,26 @@ struct F64Args {
     double* H_out; double* p_out; int32_t* sums_out;
 };
 
-// Exact H of a pair with missing genotypes, one thread: the missing samples
-// are removed and the ranks re-derived over the rest.
-__device__ double rerank_pair(const F64Args& a, int64_t t, int64_t m, int4 c, int64_t* s_out) {
+// Exact H of a pair with missing genotypes or missing expression values, one
+// thread: the samples without a genotype are removed and the ranks re-derived
+// over the rest; samples without an expression value (rank 0) are not part of
+// the trait's ranking and drop out of the pair.  Group sizes, K' and df are
+// the pair's own.
+__device__ double rerank_pair(const F64Args& a, int64_t t, int64_t m, int64_t* s_out, int* df_out) {
     const int K = a.K;
     const int16_t* rk = a.ranks2 + t * K;
     const int8_t* gr = a.geno + m * a.ld;
     long long ts = a.tiesum[t];
-    int nq = 0;
+    int nq = 0, kobs = 0;
     long long s[3] = {0, 0, 0};
+    int n[3] = {0, 0, 0};
     // tie term: remove the missing samples one at a time
     for (int j = 0; j < K; ++j) {
+        const int aj = rk[j];
+        if (aj == 0) continue;
+        ++kobs;
         int8_t gj = gr[j];
         if (gj >= 0 && gj <= 2) continue;
-        int aj = rk[j];
         int tcnt = 0;
         for (int k = 0; k < K; ++k) {
             if (rk[k] != aj) continue;
@@ -91,28 +97,35 @@ __device__ double rerank_pair(const F64Args& a, int64_t t, int64_t m, int4 c, in
     }
     for (int k = 0; k < K; ++k) {
         int8_t gk = gr[k];
-        if (!(gk >= 0 && gk <= 2)) continue;
-        int ak = rk[k];
+        const int ak = rk[k];
+        if (!(gk >= 0 && gk <= 2) || ak == 0) continue;
         int w = 0;
         for (int j = 0; j < K; ++j) {
             int8_t gj = gr[j];
-            if (gj >= 0 && gj <= 2) continue;
-            int aj = rk[j];
+            const int aj = rk[j];
+            if ((gj >= 0 && gj <= 2) || aj == 0) continue;
             w += aj < ak ? 2 : (aj == ak ? 1 : 0);
         }
         s[gk] += ak - w;
+        ++n[gk];
     }
-    int64_t kp = K - nq;
+    int64_t kp = kobs - nq;
     s_out[0] = s[0]; s_out[1] = s[1]; s_out[2] = s[2];
-    int ne = (c.x > 0) + (c.y > 0) + (c.z > 0);
+    int ne = (n[0] > 0) + (n[1] > 0) + (n[2] > 0);
     int df = ne > 0 ? ne - 1 : 0;
-    return exact_H(s[0] - (int64_t)c.x * (kp + 1), s[1] - (int64_t)c.y * (kp + 1),
-                   s[2] - (int64_t)c.z * (kp + 1), c.x, c.y, c.z, kp, ts, df);
+    *df_out = df;
+    return exact_H(s[0] - (int64_t)n[0] * (kp + 1), s[1] - (int64_t)n[1] * (kp + 1),
+                   s[2] - (int64_t)n[2] * (kp + 1), n[0], n[1], n[2], kp, ts, df);
 }
 
 __global__ __launch_bounds__(256) void f64_epilogue(F64Args a) {
   for (int64_t t = blockIdx.y; t < a.T; t += gridDim.y) {
     double best[2] = {0.0, 0.0};
+    // a trait with missing expression values takes the re-rank path for
+    // every pair (its group sizes and K' depend on the pair)
+    bool zero = false;
+    for (int k = threadIdx.x; k < a.K; k += blockDim.x) zero = zero || a.ranks2[t * a.K + k] == 0;
+    const bool nan_t = __syncthreads_or(zero);
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < a.S_act; j += gridDim.x * blockDim.x) {
         const int4 c = a.cnt[j];
         const int64_t m = a.m0 + j;
@@ -121,12 +134,12 @@ __global__ __launch_bounds__(256) void f64_epilogue(F64Args a) {
         int ne = (c.x > 0) + (c.y > 0) + (c.z > 0);
         int df = ne > 0 ? ne - 1 : 0;
         double H;
-        if (c.w == 0) {
+        if (c.w == 0 && !nan_t) {
             const int64_t k1 = a.K + 1;
             H = exact_H(s[0] - c.x * k1, s[1] - c.y * k1, s[2] - c.z * k1, c.x, c.y, c.z, a.K,
                         a.tiesum[t], df);
         } else {
-            H = rerank_pair(a, t, m, c, s);
+            H = rerank_pair(a, t, m, s, &df);
         }
         if (a.H_out) {
             a.H_out[t * a.M + m] = H;

@@ -22,6 +22,8 @@ struct PrepArgs {
     int32_t* row_v;          // [tiles * 32]
     unsigned long long* zero;  // counters cleared by the kernel (the next scan's), or null
     int n_zero;
+    const uint8_t* nan_flag;  // [T] 1: the trait has missing expression values (its rows
+                              // become padding here; scan_nan_traits evaluates them), or null
 };
 
 enum { DIAG = 0, PLAIN = 1, MISS3 = 2 };

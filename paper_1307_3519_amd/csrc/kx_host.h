@@ -33,6 +33,10 @@ hipError_t kx_launch_bits_to_double(const unsigned long long* bits, int64_t n, d
 hipError_t kx_launch_scan(const kx::ScanArgs* a, int elem, int ks, int form, int mode, int grid,
                           hipStream_t st);
 hipError_t kx_launch_exact(const kx::ScanArgs* a, int grid, hipStream_t st);
+hipError_t kx_launch_flag_nan(const int16_t* ranks2, int64_t T, int K, uint8_t* flag,
+                              int32_t* list, int32_t* n_list, int grid, hipStream_t st);
+hipError_t kx_launch_nan_traits(const kx::ScanArgs* a, const int32_t* list, const int32_t* n_list,
+                                int P, int mode, int grid, hipStream_t st);
 hipError_t kx_launch_tiled_f16(const kx::ScanArgs* a, const kx::TiledArgs* ta, int form, int mode,
                                int grid, hipStream_t st);
 hipError_t kx_launch_tiled_i8(const kx::ScanArgs* a, const kx::TiledArgs* ta, int form, int mode,

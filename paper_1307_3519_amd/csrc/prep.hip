@@ -157,6 +157,15 @@ __device__ inline int rank_at(const PrepArgs& a, int64_t v, int k) {
     return a.ranks2[trait * a.K + kk];
 }
 
+// Operand row r belongs to a trait with missing expression values: it is
+// written as padding (zero operand, virtual row -1) and its pairs are left to
+// scan_nan_traits.
+__device__ inline bool nan_row(const PrepArgs& a, int64_t r) {
+    if (!a.nan_flag) return false;
+    const int64_t v = a.rows ? a.rows[r] : r;
+    return a.nan_flag[v % a.T] != 0;
+}
+
 __device__ inline int64_t count_rows(const PrepArgs& a) {
     if (a.d_nrows) {
         int64_t n = *a.d_nrows;
@@ -193,7 +202,8 @@ __global__ __launch_bounds__(256) void prep_ranks_f16(PrepArgs a) {
         int64_t r = tile * kTile + (lane & 31);
         half8 h;
         for (int e = 0; e < 8; ++e) h[e] = (_Float16)0.0f;
-        if (r < nr) {
+        const bool live = r < nr && !nan_row(a, r);
+        if (live) {
             int64_t v = a.rows ? a.rows[r] : r;
             int k0 = s * 16 + 8 * (lane >> 5);
             for (int e = 0; e < 8; ++e) {
@@ -206,7 +216,7 @@ __global__ __launch_bounds__(256) void prep_ranks_f16(PrepArgs a) {
             // the 64 threads of (tile, k-step 0) are one wave: lanes 0..31 hold
             // the tile's rows; the wave's minimum is the tile's threshold
             float th = __builtin_inff();
-            if (lane < 32 && r < nr) {
+            if (lane < 32 && live) {
                 int64_t v = a.rows ? a.rows[r] : r;
                 int64_t E = cube_minus(a.K) - a.tiesum[v % a.T];
                 if (E > 0) th = (float)E;
@@ -238,7 +248,8 @@ __global__ __launch_bounds__(256) void prep_ranks_i8(PrepArgs a) {
         int64_t r = tile * kTile + (lane & 31);
         int8_t lo[16], hi[16];
         for (int e = 0; e < 16; ++e) { lo[e] = 0; hi[e] = 0; }
-        if (r < nr) {
+        const bool live = r < nr && !nan_row(a, r);
+        if (live) {
             int64_t v = a.rows ? a.rows[r] : r;
             int k0 = s * 32 + 16 * (lane >> 5);
             for (int e = 0; e < 16; ++e) {
@@ -270,7 +281,7 @@ __global__ __launch_bounds__(256) void prep_ranks_i8(PrepArgs a) {
             // the 64 threads of (tile, k-step 0) are one wave: lanes 0..31 hold
             // the tile's rows; the wave's minimum is the tile's threshold
             float th = __builtin_inff();
-            if (lane < 32 && r < nr) {
+            if (lane < 32 && live) {
                 int64_t v = a.rows ? a.rows[r] : r;
                 int64_t E = cube_minus(a.K) - a.tiesum[v % a.T];
                 if (E > 0) th = (float)E;

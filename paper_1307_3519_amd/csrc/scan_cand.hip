@@ -166,7 +166,121 @@ void scan_exact_missing(ScanArgs a) {
     }
 }
 
+// Traits with missing expression values (a doubled midrank of 0, see
+// krux_rank): one wave per trait sets flag[t] and appends t to list.  Their
+// operand rows are padding in the scans (prep), and scan_nan_traits evaluates
+// their pairs.
+__global__ __launch_bounds__(256) void flag_nan_traits(const int16_t* __restrict__ ranks2,
+                                                       int64_t T, int K, uint8_t* flag,
+                                                       int32_t* list, int32_t* n_list) {
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t t = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); t < T;
+         t += waves) {
+        bool zero = false;
+        for (int k = lane; k < K; k += kWave) zero = zero || ranks2[t * K + k] == 0;
+        const bool any = __any(zero);
+        if (lane == 0) {
+            flag[t] = any ? 1 : 0;
+            if (any) list[atomicAdd(n_list, 1)] = (int32_t)t;
+        }
+    }
+}
+
+// Every pair of the flagged traits, exactly (missing expression values,
+// Handling missing values: each pair keeps the samples with both an
+// expression value and a genotype, with K' of them): one wave per (trait,
+// permutation, 64 SNPs), one lane per SNP.  A SNP without missing genotypes
+// needs no re-ranking (the trait's ranks are already over its observed
+// samples): the lane sums ranks and counts per group over the observed
+// samples.  SNPs with missing genotypes are re-ranked by the wave
+// (coop_exact), one after the other.
+template <int MODE>
+__global__ __launch_bounds__(256) void scan_nan_traits(ScanArgs a, const int32_t* list,
+                                                       const int32_t* n_list, int P) {
+    extern __shared__ __attribute__((aligned(16))) int16_t s_buf[];   // per wave coop_lds_entries(K)
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int16_t* sb = s_buf + wave * coop_lds_entries(a.K);
+    const int K = a.K;
+    const int64_t nb = (a.M + kWave - 1) / kWave;
+    const int64_t items = (int64_t)*n_list * P * nb;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t it = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; it < items; it += waves) {
+        const int64_t blk = it % nb;
+        const int64_t rest = it / nb;
+        const int perm = (int)(rest % P);
+        const int64_t trait = list[rest / P];
+        const int64_t v = (int64_t)perm * a.T + trait;
+        const int16_t* rk = a.ranks2 + trait * K;
+        const int32_t* pm = a.perms ? a.perms + (int64_t)perm * K : nullptr;
+        const int64_t m = blk * kWave + lane;
+        const bool active = m < a.M;
+        const SnpInfo inf = a.info[active ? m : 0];
+        const bool rerank = active && inf.nmiss > 0;
+        if (active && !rerank) {
+            const int8_t* gr = a.G + m * (int64_t)a.gstride;
+            int64_t s[3] = {0, 0, 0};
+            int n[3] = {0, 0, 0};
+            int kobs = 0;
+            for (int k = 0; k < K; ++k) {
+                const int ak = rk[pm ? pm[k] : k];       // the same for every lane
+                const int code = gr[k];
+                if (ak == 0) continue;
+                ++kobs;
+                if (code == 0) { s[0] += ak; ++n[0]; }
+                else if (code == 1) { s[1] += ak; ++n[1]; }
+                else if (code == 2) { s[2] += ak; ++n[2]; }
+            }
+            const int64_t k1 = kobs + 1;
+            const int ne = (n[0] > 0) + (n[1] > 0) + (n[2] > 0);
+            const int df = ne > 0 ? ne - 1 : 0;
+            const double H = exact_H(s[0] - n[0] * k1, s[1] - n[1] * k1, s[2] - n[2] * k1, n[0],
+                                     n[1], n[2], kobs, a.tiesum[trait], df);
+            if (MODE == SCREEN) record(a, v, m, H, df);
+            else emit_full<MODE>(a, v, m, H, df, s[0], s[1], s[2]);
+        }
+        unsigned long long todo = __ballot(rerank);
+        while (todo) {
+            const int j = __builtin_ctzll(todo);
+            todo &= todo - 1ull;
+            const int64_t mj = blk * kWave + j;
+            int df;
+            int64_t s[3];
+            const double H = coop_exact<4>(a, v, mj, sb, lane, &df, s);
+            if (lane == 0) {
+                if (MODE == SCREEN) record(a, v, mj, H, df);
+                else emit_full<MODE>(a, v, mj, H, df, s[0], s[1], s[2]);
+            }
+        }
+    }
+}
+
 }  // namespace kx
+
+extern "C" hipError_t kx_launch_flag_nan(const int16_t* ranks2, int64_t T, int K, uint8_t* flag,
+                                         int32_t* list, int32_t* n_list, int grid,
+                                         hipStream_t st) {
+    hipLaunchKernelGGL(kx::flag_nan_traits, dim3(grid), dim3(256), 0, st, ranks2, T, K, flag,
+                       list, n_list);
+    return hipGetLastError();
+}
+
+extern "C" hipError_t kx_launch_nan_traits(const kx::ScanArgs* a, const int32_t* list,
+                                           const int32_t* n_list, int P, int mode, int grid,
+                                           hipStream_t st) {
+    const size_t lds = (size_t)4 * kx::coop_lds_entries(a->K) * sizeof(int16_t);
+    if (mode == kx::SCREEN)
+        hipLaunchKernelGGL(kx::scan_nan_traits<kx::SCREEN>, dim3(grid), dim3(256), lds, st, *a,
+                           list, n_list, P);
+    else if (mode == kx::FULL)
+        hipLaunchKernelGGL(kx::scan_nan_traits<kx::FULL>, dim3(grid), dim3(256), lds, st, *a,
+                           list, n_list, P);
+    else
+        hipLaunchKernelGGL(kx::scan_nan_traits<kx::SUMS>, dim3(grid), dim3(256), lds, st, *a,
+                           list, n_list, P);
+    return hipGetLastError();
+}
 
 // Both exact-evaluation launches of one scan (the second only when the
 // missing-genotype buffer is in use).

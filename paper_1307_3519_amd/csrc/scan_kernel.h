@@ -261,6 +261,7 @@ __device__ inline void stage_candidates(const ScanArgs& a, const ScanArgs* a_lds
 // bitmap of the fast path sits past the first 64), then 64 int32 counters.
 constexpr int kCodeShift = 13;
 constexpr int kRankMask = (1 << kCodeShift) - 1;
+constexpr int kAbsentCode = 4;   // sample without an expression value (rank 0)
 __host__ __device__ inline int coop_lds_entries(int K) { return (2 * K + 64 + 128 + 7) & ~7; }
 // int16 offset of the fast path's rank bitmap (16-byte aligned)
 __device__ inline int coop_bitmap_offset(int K) { return (K + 64 + 7) & ~7; }
@@ -309,6 +310,7 @@ __device__ inline double coop_exact(const ScanArgs& a, int64_t v, int64_t m, int
     // rank and genotype code of every sample into LDS, the ranks of the
     // missing samples compacted into qb
     int nq = 0;
+    int kobs = 0;            // samples with an expression value
     auto pass = [&](auto with_perm) {
         for (int k0 = 0; k0 < K; k0 += U * kWave) {
             // loads at clamped indices (no branches, so all are in flight
@@ -327,11 +329,15 @@ __device__ inline double coop_exact(const ScanArgs& a, int64_t v, int64_t m, int
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int k = k0 + u * kWave + lane;
-                if (k < K) sr[k] = (uint16_t)(ak[u] | (code[u] << kCodeShift));
-                const bool miss = k < K && code[u] == kMissingCode;
+                // a missing expression value (rank 0) takes the sample out of
+                // the pair whatever its genotype
+                const int cu = ak[u] == 0 ? kAbsentCode : code[u];
+                if (k < K) sr[k] = (uint16_t)(ak[u] | (cu << kCodeShift));
+                const bool miss = k < K && cu == kMissingCode;
                 const unsigned long long msk = __ballot(miss);
                 if (miss) qb[nq + __popcll(msk & lt)] = (int16_t)ak[u];
                 nq += __popcll(msk);
+                kobs += __popcll(__ballot(k < K && cu != kAbsentCode));
             }
         }
     };
@@ -340,6 +346,10 @@ __device__ inline double coop_exact(const ScanArgs& a, int64_t v, int64_t m, int
     __builtin_amdgcn_wave_barrier();
     long long ts = a.tiesum[trait];
     long long s0 = 0, s1 = 0, s2 = 0;
+    int n0 = 0, n1 = 0, n2 = 0;              // kept samples per group
+    auto add = [&](int code, int ap) {
+        if (code == 0) { s0 += ap; ++n0; } else if (code == 1) { s1 += ap; ++n1; } else { s2 += ap; ++n2; }
+    };
     const int W = ((2 * K) >> 6) + 1;      // 64-bit words covering doubled ranks 0..2K
     int qv = 0x7FFF;
     bool dup = false;
@@ -395,10 +405,7 @@ __device__ inline double coop_exact(const ScanArgs& a, int64_t v, int64_t m, int
                 const int below = (int)e[u].z + __popcll(bits & ((1ull << b) - 1ull));
                 const int eq = (int)((bits >> b) & 1ull);
                 const int code = x[u] >> kCodeShift;
-                if (k < K && code != kMissingCode) {
-                    const int ap = ak - 2 * below - eq;
-                    if (code == 0) s0 += ap; else if (code == 1) s1 += ap; else s2 += ap;
-                }
+                if (k < K && code <= 2) add(code, ak - 2 * below - eq);
                 eqi[u] = (k < K && eq) ? below : -1;
             }
             if (ts != 0) {
@@ -439,10 +446,7 @@ __device__ inline double coop_exact(const ScanArgs& a, int64_t v, int64_t m, int
                     if (qb[mid] <= ak) lo = mid + 1; else hi = mid;
                 }
                 const int equal = lo - below;
-                if (code != kMissingCode) {
-                    const int ap = ak - 2 * below - equal;
-                    if (code == 0) s0 += ap; else if (code == 1) s1 += ap; else s2 += ap;
-                }
+                if (code <= 2) add(code, ak - 2 * below - equal);
                 if (equal && ts != 0) atomicAdd(&tc[below], 1);
             }
         }
@@ -478,28 +482,31 @@ __device__ inline double coop_exact(const ScanArgs& a, int64_t v, int64_t m, int
         const int k = k0 + lane;
         const int x = k < K ? sr[k] : (kMissingCode << kCodeShift);
         const int code = x >> kCodeShift;
-        if (code != kMissingCode) {
+        if (code <= 2) {
             const int ak = x & kRankMask;
             int w = 0;
             for (int qi = 0; qi < nq; ++qi) {
                 const int aj = qb[qi];
                 w += (aj < ak) ? 2 : (aj == ak ? 1 : 0);
             }
-            const int ap = ak - w;
-            if (code == 0) s0 += ap; else if (code == 1) s1 += ap; else s2 += ap;
+            add(code, ak - w);
         }
     }
     }
     s0 = wave_sum64(s0); s1 = wave_sum64(s1); s2 = wave_sum64(s2);
-    const SnpInfo inf = a.info[m];
-    const int64_t kp = K - nq;
-    const int64_t D0 = s0 - (int64_t)inf.n0 * (kp + 1);
-    const int64_t D1 = s1 - (int64_t)inf.n1 * (kp + 1);
-    const int64_t D2 = s2 - (int64_t)inf.n2 * (kp + 1);
-    *df_out = snp_df(inf);
+    n0 = wave_sum(n0); n1 = wave_sum(n1); n2 = wave_sum(n2);
+    // group sizes, K' and df over the pair's kept samples (the SNP's own
+    // counts when the trait has every expression value)
+    const int64_t kp = kobs - nq;
+    const int64_t D0 = s0 - (int64_t)n0 * (kp + 1);
+    const int64_t D1 = s1 - (int64_t)n1 * (kp + 1);
+    const int64_t D2 = s2 - (int64_t)n2 * (kp + 1);
+    const int ne = (n0 > 0) + (n1 > 0) + (n2 > 0);
+    const int df = ne > 0 ? ne - 1 : 0;
+    *df_out = df;
     s_out[0] = s0; s_out[1] = s1; s_out[2] = s2;
     __builtin_amdgcn_wave_barrier();
-    return exact_H(D0, D1, D2, inf.n0, inf.n1, inf.n2, kp, ts, snp_df(inf));
+    return exact_H(D0, D1, D2, n0, n1, n2, kp, ts, df);
 }
 
 // Out-of-line entry for the scan kernels' own (rare, or FULL / SUMS) use, so

@@ -263,3 +263,50 @@ def test_heavy_missing_per_snp(kx):
         assert_H(res["H"].cpu().numpy(), o["H"], prec)
         assert_p(res["p"].cpu().numpy(), o["p"], prec)
         _check_hits(kx, x, g, 0.05, prec)
+
+
+# ------------------------------------------------- missing expression values
+# Traits with NaN entries (rank 0): each pair keeps the samples with both an
+# expression value and a genotype (K' per pair, group sizes per pair), with
+# and without missing genotypes; the SNP-stationary (K <= 128) and tiled
+# kernels, every precision and mode.
+NAN_CASES = [(48, 40, 70, 0.0), (102, 37, 65, 0.03), (233, 36, 70, 0.02)]
+
+
+@pytest.mark.parametrize("prec", ["fp16", "int8", "fp64"])
+@pytest.mark.parametrize("K,T,M,pm", NAN_CASES)
+def test_missing_expression(kx, prec, K, T, M, pm):
+    say("nan", prec, K, T, M, pm)
+    x, g = _inputs(17 * K + T, T, K, M, p_missing=pm, nan_frac=0.03)
+    x[2, :] = np.nan                   # no expression value at all: H = 0, p = 1
+    x[3, 1:] = np.nan                  # a single one
+    assert np.isnan(x).any(axis=1).sum() > T // 3
+    r, ts = _ranks(kx, x)
+    gd = _dev(g)
+    o = oracle.scan(x, g, full=True, sums=True)
+    res = kx.test(r, ts, gd, mode="full", precision=prec)
+    torch.cuda.synchronize()
+    assert_H(res["H"].cpu().numpy(), o["H"], "H")
+    assert_p(res["p"].cpu().numpy(), o["p"], "p")
+    res = kx.test(r, ts, gd, mode="sums", precision=prec)
+    torch.cuda.synchronize()
+    assert np.array_equal(res["sums"].cpu().numpy().astype(np.int64), o["sums"])
+    _check_hits(kx, x, g, 0.02, prec)
+
+
+def test_permute_missing_expression(kx):
+    say("permute nan")
+    K, T, M = 48, 30, 50
+    x, g = _inputs(29, T, K, M, p_missing=0.02, nan_frac=0.05)
+    rs = datagen.streams(98)
+    perms = datagen.permutations(rs["perms"], 4, K)
+    r, ts = _ranks(kx, x)
+    p_cs = (0.05, 0.01)
+    res = kx.permute(r, ts, _dev(g), _dev(perms), p_cs=p_cs)
+    torch.cuda.synchronize()
+    counts = res["counts"].cpu().numpy()
+    mp = res["min_p"].cpu().numpy()
+    for i in range(perms.shape[0]):
+        o = oracle.scan(x, g, p_cs=p_cs, perm=perms[i], min_p=True)
+        assert np.array_equal(counts[i], o["counts"]), i
+        assert_p(mp[i], o["min_p"], "perm min p")
