@@ -23,6 +23,9 @@ Workloads (--workload; seeded synthetic data shaped like the paper's
   cohorts_missing  8 cohorts, K in {48, ..., 1000}, 5,000-20,000 traits each,
       one 200,000-SNP panel with 2% missing genotypes; hits at p < 1e-5 per
       cohort
+  missing_expression  the paper-scale workload with NaN expression values in
+      2% of the traits (1-5 each); hits at p < 1e-5 plus the per-trait minimum
+      p, timed beside the same traits without NaN values
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -398,8 +401,61 @@ def cohorts_missing(args, ctx, torch, np, datagen, krux):
     return out
 
 
+def missing_expression(args, ctx, torch, np, datagen, krux):
+    wl = dict(datagen.WORKLOADS[2])
+    T = args.T or wl["T"]
+    M = args.M or wl["M"]
+    K = wl["K"]
+    p_c = 1e-5
+    log("generating workload K=%d T=%d M=%d with missing expression values" % (K, T, M))
+    w = datagen.make_workload(2, T=T, M=M)
+    x_nan = datagen.set_nan_expression(datagen.streams(2)["nan"], w["expr"], 0.02, 5)
+    n_nan = int(np.isnan(x_nan).any(axis=1).sum())
+    log("%d traits with NaN values (%d values)" % (n_nan, int(np.isnan(x_nan).sum())))
+    g = torch.from_numpy(w["geno"]).cuda()
+    runner = Runner(ctx, torch)
+    cap = 1 << 17
+    res_ms = {}
+    for label, xs in (("complete", w["expr"]), ("nan", x_nan)):
+        x = torch.from_numpy(xs).cuda()
+        bufs = {}
+
+        def step():
+            r, ts, _ = ctx.rank(x)
+            res = ctx.test(r, ts, g, p_c=p_c, mode="hits", precision="fp16",
+                           hit_capacity=cap, min_p=not args.no_minp, out=bufs.get("o"))
+            bufs["o"] = res
+            return res
+
+        log("%s: %d warmup + %d timed steps" % (label, args.warmup, args.steps))
+        ms, res, kern_ms, _ = runner.run(step, args.steps, args.warmup)
+        res_ms[label] = (ms, kern_ms, krux.unpack_hits(res)[0])
+        log("%s: %.3f ms/step, main pass %.3f ms, hits %d" % ((label,) + res_ms[label]))
+    ms, kern_ms, n_hits = res_ms["nan"]
+    pairs = float(T) * float(M)
+    out = base_line(args, METRIC, pairs / (ms / 1e3), "pairs/s", ms, "f16", {
+        "workload": "missing_expression", "K": K, "T": T, "M": M, "p_c": p_c,
+        "nan_traits": n_nan, "nan_recipe": "2% of traits, 1-5 NaN values each",
+        "outputs": "sorted hit list (p < 1e-5)" + ("" if args.no_minp else " + per-trait min p")})
+    out["roofline"] = roofline("scan_kernel<F16, KS=7, DIAG, SCREEN>", pairs - n_nan * float(M),
+                               2 * K * 2, kern_ms, PEAK_FP16_TFLOPS, "TFLOP/s")
+    out["n_hits"] = n_hits
+    out["complete_expression"] = {"ms_per_step": res_ms["complete"][0],
+                                  "kernel_ms": res_ms["complete"][1],
+                                  "n_hits": res_ms["complete"][2]}
+    if not args.no_cpu:
+        import oracle
+        rows = np.flatnonzero(np.isnan(x_nan).any(axis=1))
+        xs = x_nan[rows]
+        out["cpu_baseline"] = oracle_baseline(
+            args, len(rows), M, "the traits with NaN values, hits at p<1e-5 + per-trait min p",
+            lambda n: oracle.scan(xs, w["geno"][:n], p_cs=(p_c,), hits=True, min_p=True))
+    return out
+
+
 WORKLOADS = {"paper_scale_hits": paper_scale_hits, "precision_K500": precision_k500,
-             "permutations": permutations, "cohorts_missing": cohorts_missing}
+             "permutations": permutations, "cohorts_missing": cohorts_missing,
+             "missing_expression": missing_expression}
 
 
 def main():

@@ -26,7 +26,7 @@ one child per purpose, so each part is reproducible on its own.
 """
 import numpy as np
 
-_STREAMS = ("expr", "ties", "geno", "plant", "perms", "missing", "cohort")
+_STREAMS = ("expr", "ties", "geno", "plant", "perms", "missing", "cohort", "nan")
 
 
 def streams(seed):
@@ -75,6 +75,18 @@ def set_missing(rng, g, p_missing):
     g = g.copy()
     g[mask] = -1
     return g
+
+
+def set_nan_expression(rng, x, trait_frac, max_per_trait):
+    """Missing expression values: each trait, with probability trait_frac,
+    gets between 1 and max_per_trait NaN entries at distinct samples."""
+    T, K = x.shape
+    x = x.copy()
+    rows = np.flatnonzero(rng.random(T) < trait_frac)
+    for t in rows:
+        n = int(rng.integers(1, max_per_trait + 1))
+        x[t, rng.choice(K, size=min(n, K), replace=False)] = np.nan
+    return x
 
 
 def plant(rng, z, g, n_pairs, min_class=2):
