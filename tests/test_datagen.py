@@ -35,3 +35,19 @@ def test_planted_and_missing_and_perms():
     assert [c["K"] for c in cs] == list(datagen.COHORT_K)
     frac = np.mean(np.concatenate([(c["geno"] == -1).ravel() for c in cs]))
     assert 0.015 < frac < 0.025
+
+
+def test_nan_expression_recipe():
+    x = np.ones((4000, 102), np.float32)
+    y = datagen.set_nan_expression(datagen.streams(5)["nan"], x, 0.02, 5)
+    assert not np.isnan(x).any()                       # input untouched
+    per = np.isnan(y).sum(axis=1)
+    rows = per > 0
+    assert 40 <= rows.sum() <= 130                      # about 2 % of 4000
+    assert per[rows].min() >= 1 and per.max() <= 5
+    assert np.array_equal(y[~np.isnan(y)], x[~np.isnan(y)])
+    # the other streams do not move when the NaN stream is drawn from
+    a = datagen.streams(5)["expr"].random(3)
+    rs = datagen.streams(5)
+    datagen.set_nan_expression(rs["nan"], x, 0.5, 3)
+    assert np.array_equal(a, rs["expr"].random(3))
