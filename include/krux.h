@@ -153,7 +153,39 @@ krux_status krux_permute(krux_ctx* ctx, const int16_t* ranks2, const int64_t* ti
                          const double* p_cs, int32_t n_thr, int64_t* counts,
                          double* min_p, void* stream);
 
-/* One cohort of a batched scan: its own samples (K), traits and genotype
+/* The permuted-data hits themselves (P-value calculation and empirical FDR
+ * correction: the P-value calculation repeated with the same P_c on data
+ * with permuted rank columns), for the full FDR curve.  Same inputs as
+ * krux_permute; p_c in (0, 1].
+ *   hits[hit_capacity]  receives every permuted pair with H > H_c(df) at p_c,
+ *                       sorted by (row, snp), where the trait field holds the
+ *                       row perm * T + trait (perm indexes perms).
+ *   n_hits              device int64: the true count (may exceed
+ *                       hit_capacity; then the kept subset is unspecified). */
+krux_status krux_permute_hits(krux_ctx* ctx, const int16_t* ranks2, const int64_t* tiesum,
+                              int64_t T, int32_t K, const int8_t* geno, int64_t M,
+                              int64_t ld_geno, const int32_t* perms, int32_t P, double p_c,
+                              krux_hit* hits, int64_t hit_capacity, int64_t* n_hits,
+                              void* stream);
+
+/* Empirical FDR at the p-value of every real hit (P-value calculation and
+ * empirical FDR correction: the mean over the P permutations of the number of
+ * permuted associations with p' <= P, over the number of real associations
+ * with p' <= P):
+ *   fdr[i] = #{permuted hits j: p_j <= p_i} / (P * #{real hits j: p_j <= p_i})
+ * computed in double from the two integer counts (one rounding).
+ *   real, n_real   hit list of krux_test (HITS mode) with its device count;
+ *                  min(*n_real, real_capacity) entries are used.
+ *   perm, n_perm   hit list of krux_permute_hits over P permutations at the
+ *                  same p_c, likewise.
+ *   fdr            device, real_capacity doubles; entry i is written for
+ *                  every used real hit i (same order as real).
+ * All pointers are device pointers; n_real and n_perm are never NULL. */
+krux_status krux_fdr_curve(krux_ctx* ctx, const krux_hit* real, const int64_t* n_real,
+                           int64_t real_capacity, const krux_hit* perm, const int64_t* n_perm,
+                           int64_t perm_capacity, int32_t P, double* fdr, void* stream);
+
+/* One cohort of a batched scan:/* One cohort of a batched scan: its own samples (K), traits and genotype
  * matrix over a shared SNP panel of M SNPs. Pointers are device pointers. */
 typedef struct {
     const int16_t* ranks2;  /* T x K */

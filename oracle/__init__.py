@@ -15,6 +15,8 @@ Functions follow the paper's sections:
   scan()       -- every pair: full H/p matrices, group sums, hit lists,
                   per-threshold counts, per-trait minimum p, optional column
                   permutation of the rank matrix (empirical FDR)
+  fdr_curve()  -- empirical FDR at given p-values from real and permuted
+                  p-values (P-value calculation and empirical FDR correction)
 Missing genotypes (code -1) remove the sample from that pair and the ranks
 are recomputed over the remaining samples (handling missing values).
 """
@@ -183,4 +185,21 @@ def scan(expr, geno, p_cs=(), perm=None, full=False, sums=False,
         k = min(n, hit_cap)
         out["n_hits"] = n
         out["hits"] = dict(trait=ht[:k], snp=hs[:k], H=hH[:k], p=hp[:k])
+    return out
+
+
+def fdr_curve(real_p, perm_p, P, at=None):
+    """Empirical FDR (P-value calculation and empirical FDR correction): for a
+    value q, the number of permuted associations with p <= q averaged over
+    the P permutations, divided by the number of real associations with
+    p <= q.  Evaluated at each q of `at` (default: the real p-values), by
+    plain counting; the ratio is formed as count / (P * count) in double."""
+    real_p = np.asarray(real_p, np.float64)
+    perm_p = np.asarray(perm_p, np.float64)
+    at = real_p if at is None else np.asarray(at, np.float64)
+    out = np.empty(len(at))
+    for i, q in enumerate(at):
+        n_perm = int(np.count_nonzero(perm_p <= q))
+        n_real = int(np.count_nonzero(real_p <= q))
+        out[i] = n_perm / (float(P) * float(n_real)) if n_real else float("nan")
     return out

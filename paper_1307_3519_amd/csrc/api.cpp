@@ -448,6 +448,24 @@ double screen_level_for_min_p(double p_c, int64_t M) {
 // Per-row minimum p: rows still at p = 1 after the main pass are re-run with
 // a looser screen (every pair whose p falls below the level is evaluated
 // exactly), first at p_mid, then at p = 1 (every pair with H > 0).
+// The staged hits (appended in any order) sorted by (row, snp) into the
+// caller's buffer; *n_hits receives the true count.
+krux_status sort_stage(krux_ctx* c, const kx::HitRec* stage, const unsigned long long* nh,
+                       int64_t cap, krux_hit* hits, int64_t* n_hits, int64_t rows,
+                       hipStream_t st) {
+    krux_status s = KRUX_OK;
+    size_t tmp_bytes = kx_sort_tmp_bytes(std::max<int64_t>(cap, 1));
+    unsigned long long* keys = (unsigned long long*)ws(c, S_KEYS, (size_t)std::max<int64_t>(cap, 1) * 16, &s);
+    uint32_t* idx = (uint32_t*)ws(c, S_IDX, (size_t)std::max<int64_t>(cap, 1) * 8, &s);
+    void* tmp = ws(c, S_SORT_TMP, tmp_bytes, &s);
+    if (s != KRUX_OK) return s;
+    int tb = 1;
+    while (tb < 64 && ((int64_t)1 << tb) < std::max<int64_t>(rows, 1)) ++tb;
+    HIP_TRY(c, kx_sort_hits(stage, nh, cap, keys, idx, tmp, tmp_bytes, (kx::HitRec*)hits, n_hits,
+                            std::min(64, 32 + tb), st));
+    return KRUX_OK;
+}
+
 krux_status resolve_min_p(krux_ctx* c, kx::ScanArgs base, const Variant& v, const Columns& col,
                           const int16_t* ranks2, const int64_t* tiesum, int64_t T, int K,
                           const int32_t* perms, int64_t V, double p_main, int64_t M,
@@ -601,16 +619,7 @@ krux_status test_impl(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum,
         HIP_TRY(c, kx_launch_bits_to_double(minp, T, min_p, st));
     }
     // deterministic order of the hit list
-    size_t tmp_bytes = kx_sort_tmp_bytes(std::max<int64_t>(cap, 1));
-    unsigned long long* keys = (unsigned long long*)ws(c, S_KEYS, (size_t)std::max<int64_t>(cap, 1) * 16, &s);
-    uint32_t* idx = (uint32_t*)ws(c, S_IDX, (size_t)std::max<int64_t>(cap, 1) * 8, &s);
-    void* tmp = ws(c, S_SORT_TMP, tmp_bytes, &s);
-    if (s != KRUX_OK) return s;
-    int tb = 1;
-    while (tb < 64 && ((int64_t)1 << tb) < std::max<int64_t>(T, 1)) ++tb;
-    HIP_TRY(c, kx_sort_hits(stage, nh, cap, keys, idx, tmp, tmp_bytes, (kx::HitRec*)hits, n_hits,
-                            std::min(64, 32 + tb), st));
-    return KRUX_OK;
+    return sort_stage(c, stage, nh, cap, hits, n_hits, T, st);
 }
 
 }  // namespace
@@ -733,10 +742,15 @@ krux_status krux_test(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum,
                      hits, hit_capacity, n_hits, min_p, H, p, sums, (hipStream_t)stream);
 }
 
-krux_status krux_permute(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum, int64_t T,
+namespace {
+
+// Permuted-data scan: counts per threshold, per-row minimum p and/or the
+// hit list at the first threshold (rows perm * T + trait).
+krux_status permute_impl(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum, int64_t T,
                          int32_t K, const int8_t* geno, int64_t M, int64_t ld_geno,
                          const int32_t* perms, int32_t P, const double* p_cs, int32_t n_thr,
-                         int64_t* counts, double* min_p, void* stream) {
+                         int64_t* counts, double* min_p, krux_hit* hits, int64_t hit_capacity,
+                         int64_t* n_hits, void* stream) {
     if (!c) return fail(nullptr, KRUX_ERR_ARG, "ctx is NULL");
     krux_status s = check_ranks(c, ranks2, tiesum, T, K);
     if (s != KRUX_OK) return s;
@@ -746,7 +760,6 @@ krux_status krux_permute(krux_ctx* c, const int16_t* ranks2, const int64_t* ties
         return fail(c, KRUX_ERR_ARG, "n_thr must be in [1, %d]", kx::kMaxLevels);
     for (int i = 0; i < n_thr; ++i)
         if (!valid_p(p_cs[i])) return fail(c, KRUX_ERR_ARG, "p_cs[%d] = %g", i, p_cs[i]);
-    if (!counts) return fail(c, KRUX_ERR_ARG, "counts is NULL");
     if ((int64_t)P * T > INT32_MAX / 2) return fail(c, KRUX_ERR_UNSUPPORTED, "P * T too large");
     Variant v;
     if ((s = choose_variant(c, K, KRUX_PREC_FP16, &v)) != KRUX_OK) return s;
@@ -766,7 +779,16 @@ krux_status krux_permute(krux_ctx* c, const int16_t* ranks2, const int64_t* ties
     unsigned long long* minp =
         (unsigned long long*)ws(c, S_MINP, (size_t)std::max<int64_t>(V, 1) * 8, &s);
     if (s != KRUX_OK) return s;
-    HIP_TRY(c, kx_launch_fill_u64((unsigned long long*)counts, (int64_t)P * n_thr, 0ull, st));
+    if (counts)
+        HIP_TRY(c, kx_launch_fill_u64((unsigned long long*)counts, (int64_t)P * n_thr, 0ull, st));
+    kx::HitRec* stage = nullptr;
+    unsigned long long* nh = nullptr;
+    if (n_hits) {
+        stage = (kx::HitRec*)ws(c, S_STAGE, (size_t)std::max<int64_t>(hit_capacity, 1) * 24, &s);
+        nh = (unsigned long long*)ws(c, S_NHITS, 256, &s);
+        if (s != KRUX_OK) return s;
+        HIP_TRY(c, kx_launch_fill_u64(nh, 1, 0ull, st));
+    }
     if (min_p) HIP_TRY(c, kx_launch_fill_u64(minp, V, 0x3FF0000000000000ull, st));
     kx::ScanArgs a{};
     a.A = rk.A; a.theta = rk.theta; a.row_v = rk.row_v; a.d_nrows = nullptr; a.n_rows = V;
@@ -774,7 +796,8 @@ krux_status krux_permute(krux_ctx* c, const int16_t* ranks2, const int64_t* ties
     a.G = sn.G; a.gstride = sn.gstride; a.info = sn.info; a.tile_flags = sn.flags;
     a.M = M; a.n_snp_tiles = sn.n_snp_tiles; a.K = K;
     apply_tuning(c, K, KRUX_PREC_FP16, v, V, sn.n_snp_tiles, &a);
-    a.hits = nullptr; a.counts = (unsigned long long*)counts;
+    a.hits = stage; a.hit_cap = n_hits ? hit_capacity : 0; a.n_hits = nh;
+    a.counts = (unsigned long long*)counts;
     a.minp_bits = min_p ? minp : nullptr;
     set_levels(&a, p_cs, n_thr);
     double loosest = *std::max_element(p_cs, p_cs + n_thr);
@@ -789,6 +812,56 @@ krux_status krux_permute(krux_ctx* c, const int16_t* ranks2, const int64_t* ties
             return s;
         HIP_TRY(c, kx_launch_bits_to_double(minp, V, min_p, st));
     }
+    if (n_hits) return sort_stage(c, stage, nh, hit_capacity, hits, n_hits, V, st);
+    return KRUX_OK;
+}
+
+}  // namespace
+
+krux_status krux_permute(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum, int64_t T,
+                         int32_t K, const int8_t* geno, int64_t M, int64_t ld_geno,
+                         const int32_t* perms, int32_t P, const double* p_cs, int32_t n_thr,
+                         int64_t* counts, double* min_p, void* stream) {
+    if (!c) return fail(nullptr, KRUX_ERR_ARG, "ctx is NULL");
+    if (!counts) return fail(c, KRUX_ERR_ARG, "counts is NULL");
+    return permute_impl(c, ranks2, tiesum, T, K, geno, M, ld_geno, perms, P, p_cs, n_thr, counts,
+                        min_p, nullptr, 0, nullptr, stream);
+}
+
+krux_status krux_permute_hits(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum,
+                              int64_t T, int32_t K, const int8_t* geno, int64_t M,
+                              int64_t ld_geno, const int32_t* perms, int32_t P, double p_c,
+                              krux_hit* hits, int64_t hit_capacity, int64_t* n_hits,
+                              void* stream) {
+    if (!c) return fail(nullptr, KRUX_ERR_ARG, "ctx is NULL");
+    if (!n_hits) return fail(c, KRUX_ERR_ARG, "n_hits is NULL");
+    if (hit_capacity < 0) return fail(c, KRUX_ERR_ARG, "hit_capacity < 0");
+    if (hit_capacity > 0 && !hits) return fail(c, KRUX_ERR_ARG, "hits is NULL");
+    if (hit_capacity > (int64_t)UINT32_MAX) return fail(c, KRUX_ERR_ARG, "hit_capacity too large");
+    return permute_impl(c, ranks2, tiesum, T, K, geno, M, ld_geno, perms, P, &p_c, 1, nullptr,
+                        nullptr, hits, hit_capacity, n_hits, stream);
+}
+
+krux_status krux_fdr_curve(krux_ctx* c, const krux_hit* real, const int64_t* n_real,
+                           int64_t real_capacity, const krux_hit* perm, const int64_t* n_perm,
+                           int64_t perm_capacity, int32_t P, double* fdr, void* stream) {
+    if (!c) return fail(nullptr, KRUX_ERR_ARG, "ctx is NULL");
+    if (P < 1) return fail(c, KRUX_ERR_ARG, "P must be >= 1");
+    if (real_capacity < 0 || perm_capacity < 0) return fail(c, KRUX_ERR_ARG, "capacity < 0");
+    if (!n_real || !n_perm) return fail(c, KRUX_ERR_ARG, "n_real / n_perm is NULL");
+    if ((real_capacity > 0 && (!real || !fdr)) || (perm_capacity > 0 && !perm))
+        return fail(c, KRUX_ERR_ARG, "hit list or fdr is NULL");
+    HIP_TRY(c, hipSetDevice(c->device));
+    krux_status s = KRUX_OK;
+    const int64_t big = std::max<int64_t>(std::max(real_capacity, perm_capacity), 1);
+    const size_t tmp_bytes = kx_sort_keys_tmp_bytes(big);
+    unsigned long long* kr = (unsigned long long*)ws(c, S_KEYS, (size_t)std::max<int64_t>(real_capacity, 1) * 16, &s);
+    unsigned long long* kp = (unsigned long long*)ws(c, S_IDX, (size_t)std::max<int64_t>(perm_capacity, 1) * 16, &s);
+    void* tmp = ws(c, S_SORT_TMP, tmp_bytes, &s);
+    if (s != KRUX_OK) return s;
+    HIP_TRY(c, kx_fdr_curve((const kx::HitRec*)real, n_real, real_capacity,
+                            (const kx::HitRec*)perm, n_perm, perm_capacity, P, kr, kp, tmp,
+                            tmp_bytes, fdr, (hipStream_t)stream));
     return KRUX_OK;
 }
 

@@ -51,6 +51,11 @@ size_t kx_sort_tmp_bytes(int64_t cap);
 hipError_t kx_sort_hits(const kx::HitRec* stage, const unsigned long long* n_hits, int64_t cap,
                         unsigned long long* keys, uint32_t* idx, void* tmp, size_t tmp_bytes,
                         kx::HitRec* out, int64_t* n_out, int key_bits, hipStream_t st);
+size_t kx_sort_keys_tmp_bytes(int64_t cap);
+hipError_t kx_fdr_curve(const kx::HitRec* real, const int64_t* n_real, int64_t real_cap,
+                        const kx::HitRec* perm, const int64_t* n_perm, int64_t perm_cap, int P,
+                        unsigned long long* keys_r, unsigned long long* keys_p, void* tmp,
+                        size_t tmp_bytes, double* fdr, hipStream_t st);
 }
 
 // context hooks (api.cpp)

@@ -208,7 +208,7 @@ __device__ inline void tally_pair(const ScanArgs& a, RowTally& r, int64_t v, int
         const unsigned long long idx = atomicAdd(a.n_hits, 1ull);
         if ((int64_t)idx < a.hit_cap) {
             HitRec h;
-            h.trait = (int32_t)(v % a.T);
+            h.trait = (int32_t)v;     // perm * T + trait (the trait without permutations)
             h.snp = (int32_t)(a.snp_base + m);
             h.H = H;
             h.p = pvalue(H, df);

@@ -123,7 +123,7 @@ __device__ inline long long wave_sum64(long long v) {
 // Record one exactly evaluated pair (screen mode).
 __device__ inline void record(const ScanArgs& a, int64_t v, int64_t m, double H, int df) {
     if (df <= 0) return;
-    int64_t trait = v % a.T, perm = v / a.T;
+    const int64_t perm = v / a.T;
     if (a.counts) {
         for (int l = 0; l < a.n_lev; ++l)
             if (H > a.hc[l][df - 1]) atomicAdd(&a.counts[perm * a.n_lev + l], 1ull);
@@ -136,7 +136,7 @@ __device__ inline void record(const ScanArgs& a, int64_t v, int64_t m, double H,
         unsigned long long idx = atomicAdd(a.n_hits, 1ull);
         if ((int64_t)idx < a.hit_cap) {
             HitRec h;
-            h.trait = (int32_t)trait;
+            h.trait = (int32_t)v;     // perm * T + trait (the trait without permutations)
             h.snp = (int32_t)(a.snp_base + m);
             h.H = H;
             h.p = p;

@@ -21,7 +21,8 @@ _PREC = {"fp16": PREC_FP16, "int8": PREC_INT8, "fp64": PREC_FP64}
 _MODE = {"hits": MODE_HITS, "full": MODE_FULL, "sums": MODE_SUMS}
 
 EXPORTS = ("krux_create", "krux_destroy", "krux_last_error", "krux_threshold",
-           "krux_rank", "krux_test", "krux_permute", "krux_test_batched",
+           "krux_rank", "krux_test", "krux_permute", "krux_permute_hits", "krux_fdr_curve",
+           "krux_test_batched",
            "krux_timer_start", "krux_timer_read", "krux_autotune", "krux_load_tuning",
            "krux_tuning_of")
 
@@ -72,6 +73,10 @@ def library():
     lib.krux_permute.restype = ctypes.c_int
     lib.krux_permute.argtypes = [P, P, P, i64, i32, P, i64, i64, P, i32, P, i32, P, P, P]
     lib.krux_test_batched.restype = ctypes.c_int
+    lib.krux_permute_hits.restype = ctypes.c_int
+    lib.krux_permute_hits.argtypes = [P, P, P, i64, i32, P, i64, i64, P, i32, dbl, P, i64, P, P]
+    lib.krux_fdr_curve.restype = ctypes.c_int
+    lib.krux_fdr_curve.argtypes = [P, P, P, i64, P, P, i64, i32, P, P]
     lib.krux_test_batched.argtypes = [P, P, i32, i64, dbl, i32, P]
     lib.krux_timer_start.restype = ctypes.c_int
     lib.krux_timer_start.argtypes = [P]
@@ -266,6 +271,34 @@ class Context:
             geno.stride(0) if M else K, _ptr(perms), P, pcs, len(p_cs), _ptr(counts), _ptr(mp),
             _stream()))
         return dict(counts=counts, min_p=mp)
+
+    def permute_hits(self, ranks2, tiesum, geno, perms, p_c=1e-5, hit_capacity=1 << 20):
+        """Hit list of the permuted data, rows perm * T + trait in the trait
+        field -> dict as test() in hits mode."""
+        T, K = ranks2.shape
+        M = geno.shape[0]
+        P = perms.shape[0]
+        dev = ranks2.device
+        hits = torch.empty(max(hit_capacity, 1) * 24, dtype=torch.uint8, device=dev)
+        nh = torch.zeros(1, dtype=torch.int64, device=dev)
+        self._check(self.lib.krux_permute_hits(
+            self.h, _ptr(ranks2), _ptr(tiesum), T, K, _ptr(geno), M,
+            geno.stride(0) if M else K, _ptr(perms), P, float(p_c), _ptr(hits),
+            int(hit_capacity), _ptr(nh), _stream()))
+        return dict(hits_raw=hits, n_hits_t=nh, min_p=None, hit_capacity=hit_capacity)
+
+    def fdr_curve(self, real, perm, P):
+        """Empirical FDR at the p of every real hit: real from test() (hits
+        mode), perm from permute_hits() over P permutations -> (real_cap,)
+        float64 tensor, valid up to the real hit count."""
+        dev = real["hits_raw"].device
+        fdr = torch.full((max(real["hit_capacity"], 1),), float("nan"), dtype=torch.float64,
+                         device=dev)
+        self._check(self.lib.krux_fdr_curve(
+            self.h, _ptr(real["hits_raw"]), _ptr(real["n_hits_t"]), int(real["hit_capacity"]),
+            _ptr(perm["hits_raw"]), _ptr(perm["n_hits_t"]), int(perm["hit_capacity"]), int(P),
+            _ptr(fdr), _stream()))
+        return fdr
 
     # ------------------------------------------------------------------ cohorts
     def test_batched_buffers(self, cohorts, hit_capacity=1 << 16, min_p=False):

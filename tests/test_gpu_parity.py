@@ -310,3 +310,58 @@ def test_permute_missing_expression(kx):
         o = oracle.scan(x, g, p_cs=p_cs, perm=perms[i], min_p=True)
         assert np.array_equal(counts[i], o["counts"]), i
         assert_p(mp[i], o["min_p"], "perm min p")
+
+
+# ---------------------------------------------------------------- empirical FDR curve
+FDR_CASES = [  # (K, T, M, p_missing, nan_frac, P)
+    (48, 30, 120, 0.0, 0.0, 5),
+    (102, 37, 90, 0.02, 0.02, 4),
+    (233, 20, 70, 0.02, 0.0, 3),
+]
+
+
+@pytest.mark.parametrize("K,T,M,pm,nan,P", FDR_CASES)
+def test_permute_hits_and_fdr_curve(kx, K, T, M, pm, nan, P):
+    from paper_1307_3519_amd.krux import unpack_hits
+    say("fdr", K, T, M, pm, nan, P)
+    x, g = _inputs(31 * K + T, T, K, M, p_missing=pm, nan_frac=nan)
+    perms = datagen.permutations(datagen.streams(K + 7)["perms"], P, K)
+    r, ts = _ranks(kx, x)
+    gd, pd = _dev(g), _dev(perms)
+    p_c = 0.02
+    ph = kx.permute_hits(r, ts, gd, pd, p_c=p_c, hit_capacity=1 << 14)
+    real = kx.test(r, ts, gd, p_c=p_c, mode="hits", precision="fp16", hit_capacity=1 << 14,
+                   min_p=False)
+    fdr = kx.fdr_curve(real, ph, P)
+    torch.cuda.synchronize()
+    n_p, hp = unpack_hits(ph)
+    n_r, hr = unpack_hits(real)
+    # the permuted hits, permutation by permutation (rows perm * T + trait)
+    o_perm_p, tot = [], 0
+    for i in range(P):
+        o = oracle.scan(x, g, p_cs=(p_c,), perm=perms[i], hits=True)
+        sel = (hp["trait"] // T) == i
+        assert np.array_equal(hp["trait"][sel] % T, o["hits"]["trait"]), i
+        assert np.array_equal(hp["snp"][sel], o["hits"]["snp"]), i
+        assert_p(hp["p"][sel], o["hits"]["p"], "permuted hit p")
+        o_perm_p.append(o["hits"]["p"])
+        tot += o["n_hits"]
+    assert n_p == tot and n_p > 0 and n_r > 0
+    f = fdr[:n_r].cpu().numpy()
+    # the curve from the GPU's own p-values, exactly as the definition counts
+    assert np.array_equal(f, oracle.fdr_curve(hr["p"], hp["p"], P))
+    # and from the oracle's hit lists
+    o_real = oracle.scan(x, g, p_cs=(p_c,), hits=True)
+    assert np.array_equal(f, oracle.fdr_curve(o_real["hits"]["p"], np.concatenate(o_perm_p), P))
+    # no permuted hit: FDR 0 at every real hit
+    ph0 = kx.permute_hits(r, ts, gd, pd, p_c=1e-300, hit_capacity=16)
+    f0 = kx.fdr_curve(real, ph0, P)
+    torch.cuda.synchronize()
+    assert unpack_hits(ph0)[0] == 0 and np.all(f0[:n_r].cpu().numpy() == 0.0)
+    # capacity below the count: the true count, a valid subset kept
+    small = kx.permute_hits(r, ts, gd, pd, p_c=p_c, hit_capacity=3)
+    torch.cuda.synchronize()
+    n_s, hs = unpack_hits(small)
+    assert n_s == tot and len(hs["snp"]) == 3
+    full = set(zip(hp["trait"].tolist(), hp["snp"].tolist()))
+    assert set(zip(hs["trait"].tolist(), hs["snp"].tolist())) <= full

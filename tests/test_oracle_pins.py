@@ -366,3 +366,33 @@ def test_scan_permutation_is_column_permutation_of_ranks():
     r, ts, _ = oracle.rank(x)
     rp, tsp, _ = oracle.rank(x[:, pi])
     assert np.array_equal(rp, r[:, pi]) and np.array_equal(ts, tsp)
+
+
+# ---------------------------------------------------------------- empirical FDR
+def test_fdr_curve_worked_example():
+    # hand count (P-value calculation and empirical FDR correction): P = 2
+    # permutations pooled, FDR(q) = (#perm p <= q / 2) / #real p <= q
+    real = [0.001, 0.002, 0.002, 0.01]
+    perm = [0.0005, 0.0015, 0.002, 0.003, 0.02, 0.0001]
+    got = oracle.fdr_curve(real, perm, 2)
+    want = [Fraction(2, 2 * 1), Fraction(4, 2 * 3), Fraction(4, 2 * 3), Fraction(5, 2 * 4)]
+    assert [float(w) for w in want] == list(got)
+
+
+def test_fdr_curve_is_mean_of_per_permutation_ratios():
+    # the mean over permutations of per-permutation counts, each over the real
+    # count, as exact rationals; ties between and within the lists included
+    rng = np.random.default_rng(21)
+    P = 7
+    grid = np.round(rng.uniform(0, 1e-3, 40), 6)          # coarse: many ties
+    real = rng.choice(grid, 60)
+    per_perm = [rng.choice(grid, int(rng.integers(0, 30))) for _ in range(P)]
+    got = oracle.fdr_curve(real, np.concatenate(per_perm), P)
+    for q, g in zip(real, got):
+        n_real = sum(1 for r in real if r <= q)
+        mean = sum(Fraction(sum(1 for x in pp if x <= q), n_real) for pp in per_perm) / P
+        assert g == float(mean)
+    # identical permuted and real data: FDR = 1 at every real p
+    assert np.all(oracle.fdr_curve(real, np.tile(real, P), P) == 1.0)
+    # no permuted hit: 0
+    assert np.all(oracle.fdr_curve(real, [], P) == 0.0)
