@@ -19,7 +19,8 @@ Workloads (--workload; seeded synthetic data shaped like the paper's
       sums of a slice compared bit for bit across the three
   permutations     K=102, 20,000 traits, 100,000 SNPs, 200 permutations of the
       samples; per-permutation hit counts at p < {1e-4, 1e-5, 1e-6} and the
-      per-(permutation, trait) minimum p
+      per-(permutation, trait) minimum p; beside it the full empirical FDR
+      curve at p < 1e-5 (real and permuted hit lists, FDR at every real hit)
   cohorts_missing  8 cohorts, K in {48, ..., 1000}, 5,000-20,000 traits each,
       one 200,000-SNP panel with 2% missing genotypes; hits at p < 1e-5 per
       cohort
@@ -338,6 +339,37 @@ def permutations(args, ctx, torch, np, datagen, krux):
     log("graph replay: %.1f ms/step, counts identical %s" % (gms, same))
     out["graph_replay"] = {"ms_per_step": gms, "value": pairs / (gms / 1e3), "unit": "pairs/s",
                            "identical_counts": same}
+    # the full empirical FDR curve at p < 1e-5: real hits, permuted hits (all
+    # P permutations), FDR at every real hit's p
+    p_f = p_cs[1]
+    fcap = 1 << 23
+
+    def fdr_step():
+        r, ts, _ = ctx.rank(x)
+        real = ctx.test(r, ts, g, p_c=p_f, mode="hits", precision="fp16", hit_capacity=1 << 17,
+                        min_p=False)
+        ph = ctx.permute_hits(r, ts, g, perms, p_c=p_f, hit_capacity=fcap)
+        return real, ph, ctx.fdr_curve(real, ph, P)
+
+    fdr_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        real, ph, fdr = fdr_step()
+    torch.cuda.synchronize()
+    fms = (time.perf_counter() - t0) * 1e3 / steps
+    n_real, hr = krux.unpack_hits(real)
+    n_perm = int(ph["n_hits_t"].item())
+    f = fdr[:n_real].cpu().numpy()
+    order = np.argsort(hr["p"], kind="stable")
+    at = [float(f[order[min(len(order) - 1, int(q * len(order)))]]) for q in (0.1, 0.5, 0.9)] \
+        if n_real else []
+    log("FDR curve: %.1f ms/step, %d real hits, %d permuted hits (%.1f per permutation)"
+        % (fms, n_real, n_perm, n_perm / P))
+    out["fdr_curve"] = {"ms_per_step": fms, "p_c": p_f, "n_real_hits": n_real,
+                        "n_permuted_hits": n_perm,
+                        "fdr_at_real_p_quantiles_0.1_0.5_0.9": at,
+                        "outputs": "real hit list, permuted hit lists, FDR at every real hit"}
     if not args.no_cpu:
         import oracle
         out["cpu_baseline"] = oracle_baseline(
