@@ -243,11 +243,13 @@ __device__ inline void tally_flush(const ScanArgs& a, const RowTally& r, int64_t
 }
 
 // LDS of one wave of scan_nan_traits: the staged rank words (three arrays of
-// nan_words(K) words) followed by the coop_exact buffer.
+// nan_words(K) words), the ranks as int16 (4 nan_words(K) of them), then the
+// coop_exact buffer.
 __host__ __device__ inline int nan_words(int K) { return ((K + 15) & ~15) >> 2; }
 __host__ __device__ inline int nan_wave_lds_bytes(int K) {
-    return 12 * nan_words(K) + 2 * coop_lds_entries(K);
+    return 20 * nan_words(K) + 2 * coop_lds_entries(K);
 }
+constexpr int kNoRank = 0x7FFF;   // above every doubled rank (2K <= 16384)
 
 // Every pair of the flagged traits, exactly (missing expression values,
 // Handling missing values: each pair keeps the samples with both an
@@ -261,8 +263,12 @@ __host__ __device__ inline int nan_wave_lds_bytes(int K) {
 // genotype codes at a time into byte indicators of groups 1 and 2 and takes
 // their dot products with the rank and observation bytes (v_dot4_u32_u8);
 // group 0 follows from the row's totals, K' observed samples whose doubled
-// ranks sum to K' (K' + 1).  SNPs with missing genotypes are re-ranked by
-// the wave (coop_exact), one after the other.  Four waves per SIMD (128
+// ranks sum to K' (K' + 1).  A SNP with up to four removed samples (a
+// missing genotype where the trait has a value) is re-ranked by its lane: a
+// second pass subtracts each removal's effect on the group sums and counts
+// the removed ranks' tie groups for the tie term (Handling tied data).  SNPs
+// with more are re-ranked by the wave (coop_exact), one after the other.
+// Four waves per SIMD (128
 // registers, a few spilled) against two at the compiler's choice: 8.3 ->
 // 7.2 ms per step with 402 such traits of 20 000 against 500 000 SNPs.
 template <int MODE>
@@ -276,7 +282,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     uint32_t* slo = (uint32_t*)((char*)s_buf + (size_t)wave * nan_wave_lds_bytes(K));
     uint32_t* shi = slo + KW;
     uint32_t* sob = shi + KW;
-    int16_t* sb = (int16_t*)(sob + KW);           // coop_exact buffer
+    int16_t* srk = (int16_t*)(sob + KW);          // the ranks, 4 KW of them (zero past K)
+    int16_t* sb = srk + 4 * KW;                   // coop_exact buffer
     const bool wide = 2 * K > 255;                // ranks above one byte
     const int64_t nb = (a.M + kWave - 1) / kWave;
     const int64_t rows = (int64_t)*n_list * P;
@@ -310,6 +317,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
             shi[i] = hi;
             sob[i] = ob;
         }
+        for (int k = lane; k < 4 * KW; k += kWave) srk[k] = k < K ? rk[pm ? pm[k] : k] : 0;
         kobs = wave_sum(kobs);
         __builtin_amdgcn_wave_barrier();
         const int64_t k1 = kobs + 1;
@@ -324,11 +332,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
             const int64_t m = blk * kWave + lane;
             const bool active = m < a.M;
             const int nmiss = active ? (int)a.info[m].nmiss : 0;
-            if (active && nmiss == 0) {
-                const int8_t* gr = a.G + m * (int64_t)a.gstride;
-                uint32_t s1 = 0, s2 = 0, n1 = 0, n2 = 0, h1 = 0, h2 = 0;
+            const int8_t* gr = a.G + (active ? m : 0) * (int64_t)a.gstride;
+            uint32_t s1 = 0, s2 = 0, n1 = 0, n2 = 0, h1 = 0, h2 = 0;
+            // removed samples: a missing genotype where the trait has a
+            // value.  The lane keeps the ranks of up to four (kNoRank: none);
+            // a SNP with more is re-ranked by the wave.
+            int nq = 0;
+            int q0 = kNoRank, q1 = kNoRank, q2 = kNoRank, q3 = kNoRank;
+            // pass 1: group sums and counts over the observed samples, and
+            // (only in waves that have a SNP with a missing genotype) the
+            // ranks of the removed samples
+            auto pass1 = [&](auto with_miss) {
                 // the packed row stride is a multiple of 32 bytes: 16-byte
-                // loads stay inside the row (codes past K meet zero bytes)
+                // loads stay inside the row (codes past K meet zero ranks)
                 for (int i0 = 0; i0 < KW; i0 += 4) {
                     const uint4 g4 = *(const uint4*)(gr + 4 * i0);
                     const uint4 l4 = *(const uint4*)(slo + i0);
@@ -339,7 +355,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
                     uint32_t i1[4], i2[4];
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
-                        // codes are 0..3: bit 0 alone marks group 1, bit 1 alone group 2
+                        // codes are 0..3: bit 0 alone marks group 1, bit 1
+                        // alone group 2, both the missing code
                         const uint32_t w = gw[j], t = w >> 1;
                         i1[j] = (w & 0x01010101u) & ~t;
                         i2[j] = (t & 0x01010101u) & ~w;
@@ -347,6 +364,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
                         s2 = __builtin_amdgcn_udot4(i2[j], lw[j], s2, false);
                         n1 = __builtin_amdgcn_udot4(i1[j], ow[j], n1, false);
                         n2 = __builtin_amdgcn_udot4(i2[j], ow[j], n2, false);
+                        if (decltype(with_miss)::value && nmiss) {
+                            uint32_t m3 = (w & t) & 0x01010101u;
+                            while (m3) {
+                                const int k = 4 * (i0 + j) + (__builtin_ctz(m3) >> 3);
+                                m3 &= m3 - 1u;
+                                const int aq = srk[k];
+                                if (aq != 0) {
+                                    q0 = nq == 0 ? aq : q0;
+                                    q1 = nq == 1 ? aq : q1;
+                                    q2 = nq == 2 ? aq : q2;
+                                    q3 = nq == 3 ? aq : q3;
+                                    ++nq;
+                                }
+                            }
+                        }
                     }
                     if (wide) {
                         const uint4 h4 = *(const uint4*)(shi + i0);
@@ -358,18 +390,69 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
                         }
                     }
                 }
-                const int64_t S1 = (int64_t)s1 + ((int64_t)h1 << 8);
-                const int64_t S2 = (int64_t)s2 + ((int64_t)h2 << 8);
-                const int N1 = (int)n1, N2 = (int)n2, N0 = kobs - N1 - N2;
-                const int64_t S0 = (int64_t)kobs * k1 - S1 - S2;
+            };
+            if (__ballot(nmiss > 0)) {
+                if (active) pass1(std::true_type{});
+            } else if (active) {
+                pass1(std::false_type{});
+            }
+            const bool lane_ok = active && nq <= 4;
+            // Removing sample j lowers every kept doubled rank above a_j by 2
+            // and every tied one by 1, so group i loses
+            // sum_{k in group i} ([a_k > a_j] + [a_k >= a_j]); e_j is the
+            // size of a_j's tie group before any removal.
+            int nqw = lane_ok ? nq : 0;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) nqw = max(nqw, __shfl_xor(nqw, o, 64));
+            int64_t c1 = 0, c2 = 0;
+            int e0 = 0, e1 = 0, e2 = 0, e3 = 0;
+            if (nqw > 0 && lane_ok && nq > 0) {
+                for (int i0 = 0; i0 < KW; i0 += 4) {
+                    const uint4 g4 = *(const uint4*)(gr + 4 * i0);
+                    const uint32_t gw[4] = {g4.x, g4.y, g4.z, g4.w};
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) {
+                            const int ak = srk[4 * (i0 + j) + b];
+                            const uint32_t code = (gw[j] >> (8 * b)) & 3u;
+                            auto one = [&](int q, int& e) {
+                                const int f = (ak > q) + (ak >= q);
+                                c1 += code == 1u ? f : 0;
+                                c2 += code == 2u ? f : 0;
+                                e += ak == q;
+                            };
+                            one(q0, e0);
+                            if (nqw > 1) one(q1, e1);
+                            if (nqw > 2) one(q2, e2);
+                            if (nqw > 3) one(q3, e3);
+                        }
+                    }
+                }
+            }
+            if (lane_ok) {
+                const int kp = kobs - nq;
+                const int64_t kp1 = kp + 1;
+                const int64_t S1 = (int64_t)s1 + ((int64_t)h1 << 8) - c1;
+                const int64_t S2 = (int64_t)s2 + ((int64_t)h2 << 8) - c2;
+                const int N1 = (int)n1, N2 = (int)n2, N0 = kp - N1 - N2;
+                const int64_t S0 = (int64_t)kp * kp1 - S1 - S2;
+                // tie term: a removal from a tie group of current size t
+                // takes 3 t (t - 1) off (t^3 - t)
+                int64_t ts = tsum;
+                auto drop = [&](int64_t t) { ts -= 3 * t * (t - 1); };
+                if (nq > 0) drop(e0);
+                if (nq > 1) drop(e1 - (q1 == q0));
+                if (nq > 2) drop(e2 - (q2 == q0) - (q2 == q1));
+                if (nq > 3) drop(e3 - (q3 == q0) - (q3 == q1) - (q3 == q2));
                 const int ne = (N0 > 0) + (N1 > 0) + (N2 > 0);
                 const int df = ne > 0 ? ne - 1 : 0;
-                const double H = exact_H(S0 - N0 * k1, S1 - N1 * k1, S2 - N2 * k1, N0, N1, N2,
-                                         kobs, tsum, df);
+                const double H = exact_H(S0 - N0 * kp1, S1 - N1 * kp1, S2 - N2 * kp1, N0, N1, N2,
+                                         kp, ts, df);
                 if (MODE == SCREEN) tally_pair(a, tl, v, m, H, df);
                 else emit_full<MODE>(a, v, m, H, df, S0, S1, S2);
             }
-            unsigned long long todo = __ballot(nmiss > 0);
+            unsigned long long todo = __ballot(active && !lane_ok);
             while (todo) {
                 const int j = __builtin_ctzll(todo);
                 todo &= todo - 1ull;
