@@ -445,9 +445,6 @@ double screen_level_for_min_p(double p_c, int64_t M) {
     return std::max(p_c, std::min(1.0, 64.0 / (double)std::max<int64_t>(M, 1)));
 }
 
-// Per-row minimum p: rows still at p = 1 after the main pass are re-run with
-// a looser screen (every pair whose p falls below the level is evaluated
-// exactly), first at p_mid, then at p = 1 (every pair with H > 0).
 // The staged hits (appended in any order) sorted by (row, snp) into the
 // caller's buffer; *n_hits receives the true count.
 krux_status sort_stage(krux_ctx* c, const kx::HitRec* stage, const unsigned long long* nh,
@@ -466,6 +463,9 @@ krux_status sort_stage(krux_ctx* c, const kx::HitRec* stage, const unsigned long
     return KRUX_OK;
 }
 
+// Per-row minimum p: rows still at p = 1 after the main pass are re-run with
+// a looser screen (every pair whose p falls below the level is evaluated
+// exactly), first at p_mid, then at p = 1 (every pair with H > 0).
 krux_status resolve_min_p(krux_ctx* c, kx::ScanArgs base, const Variant& v, const Columns& col,
                           const int16_t* ranks2, const int64_t* tiesum, int64_t T, int K,
                           const int32_t* perms, int64_t V, double p_main, int64_t M,
