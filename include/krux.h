@@ -138,6 +138,22 @@ krux_status krux_test(krux_ctx* ctx, const int16_t* ranks2, const int64_t* tiesu
                       double* min_p, double* H, double* p, int32_t* sums,
                       void* stream);
 
+/* HITS-mode scan with the SNPs grouped by their pattern of missing genotypes
+ * (Handling missing values: one sub-problem per unique pattern, with the
+ * pattern's samples removed from the genotype and expression matrices).
+ * Every pattern shared by at least min_group SNPs (>= 1) becomes a complete
+ * sub-problem over its remaining samples; the other SNPs are scanned as by
+ * krux_test.  Same arguments, outputs and results as krux_test in HITS mode
+ * (hits sorted by (trait, snp), true count in *n_hits, min_p per trait);
+ * faster when many SNPs share their missing samples (a failed sample).
+ * Synchronises `stream` twice (to group the patterns on the host) and makes
+ * small synchronous copies, so it cannot be captured into a graph. */
+krux_status krux_test_grouped(krux_ctx* ctx, const int16_t* ranks2, const int64_t* tiesum,
+                              int64_t T, int32_t K, const int8_t* geno, int64_t M,
+                              int64_t ld_geno, int64_t snp_base, double p_c, int32_t precision,
+                              int64_t min_group, krux_hit* hits, int64_t hit_capacity,
+                              int64_t* n_hits, double* min_p, void* stream);
+
 /* Permuted-data repeats for the empirical FDR (P-value calculation and
  * empirical FDR correction): for each permutation pi (perms, P x K int32,
  * each a permutation of 0..K-1) the rank matrix columns are permuted, the

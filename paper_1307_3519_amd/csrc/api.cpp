@@ -9,6 +9,7 @@
 #include <cstring>
 #include <string>
 #include <map>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -25,6 +26,8 @@ enum Slot {
     S_SORT_TMP, S_F64_R, S_F64_I, S_F64_S, S_COUNT_PREV, S_CAND, S_NCAND, S_MCAND, S_NMCAND,
     S_TUNE_HITS, S_TUNE_N,
     S_AH, S_AH2, S_BF, S_BF3, S_NAN_FLAG, S_NAN_LIST, S_NAN_N,
+    S_G_KEYS, S_G_QMASK, S_G_SNPS, S_G_SAMPLES, S_G_EXPR, S_G_R, S_G_TS, S_G_GENO, S_G_STAGE,
+    S_G_CNT, S_G_MINP, S_G_PHITS, S_G_PN, S_G_PMINP,
     S_N_SLOTS
 };
 
@@ -862,6 +865,153 @@ krux_status krux_fdr_curve(krux_ctx* c, const krux_hit* real, const int64_t* n_r
     HIP_TRY(c, kx_fdr_curve((const kx::HitRec*)real, n_real, real_capacity,
                             (const kx::HitRec*)perm, n_perm, perm_capacity, P, kr, kp, tmp,
                             tmp_bytes, fdr, (hipStream_t)stream));
+    return KRUX_OK;
+}
+
+// Hits of one scan with SNPs grouped by missing-genotype pattern (Handling
+// missing values): each group of at least min_group SNPs with the same
+// missing samples Q becomes a complete sub-problem over the other K - |Q|
+// samples (ranks recomputed over them by ranking the gathered ranks); the
+// remaining SNPs form one more sub-problem over all K samples.  The
+// sub-problems' hits are mapped back to SNP indices and sorted together, and
+// their per-trait minima merged.  Results equal krux_test's.
+krux_status krux_test_grouped(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum,
+                              int64_t T, int32_t K, const int8_t* geno, int64_t M,
+                              int64_t ld_geno, int64_t snp_base, double p_c, int32_t precision,
+                              int64_t min_group, krux_hit* hits, int64_t hit_capacity,
+                              int64_t* n_hits, double* min_p, void* stream) {
+    if (!c) return fail(nullptr, KRUX_ERR_ARG, "ctx is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    krux_status s = check_ranks(c, ranks2, tiesum, T, K);
+    if (s != KRUX_OK) return s;
+    if ((s = check_geno(c, geno, M, ld_geno, K)) != KRUX_OK) return s;
+    if (!valid_p(p_c)) return fail(c, KRUX_ERR_ARG, "p_c = %g not in (0, 1]", p_c);
+    if (precision < KRUX_PREC_FP16 || precision > KRUX_PREC_FP64)
+        return fail(c, KRUX_ERR_ARG, "precision %d", precision);
+    if (!n_hits) return fail(c, KRUX_ERR_ARG, "n_hits is NULL");
+    if (hit_capacity < 0 || (hit_capacity > 0 && !hits))
+        return fail(c, KRUX_ERR_ARG, "hits / hit_capacity");
+    if (hit_capacity > (int64_t)UINT32_MAX) return fail(c, KRUX_ERR_ARG, "hit_capacity too large");
+    if (min_group < 1) return fail(c, KRUX_ERR_ARG, "min_group < 1");
+    auto plain = [&]() {
+        return test_impl(c, ranks2, tiesum, T, K, geno, M, ld_geno, snp_base, p_c, KRUX_MODE_HITS,
+                         precision, hits, hit_capacity, n_hits, min_p, nullptr, nullptr, nullptr,
+                         st);
+    };
+    if (M == 0 || T == 0) return plain();
+    HIP_TRY(c, hipSetDevice(c->device));
+    const int grid = c->n_cu * 8;
+
+    // 1. pattern keys, grouped on the host (one synchronisation)
+    uint64_t* keys = (uint64_t*)ws(c, S_G_KEYS, (size_t)M * 8, &s);
+    if (s != KRUX_OK) return s;
+    HIP_TRY(c, kx_launch_miss_keys(geno, M, ld_geno, K, keys, grid, st));
+    std::vector<uint64_t> hk((size_t)M);
+    HIP_TRY(c, hipMemcpyAsync(hk.data(), keys, (size_t)M * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    std::unordered_map<uint64_t, std::vector<int32_t>> by_key;
+    for (int64_t m = 0; m < M; ++m)
+        if (hk[m]) by_key[hk[m]].push_back((int32_t)m);
+    std::vector<std::vector<int32_t>> groups;
+    std::vector<uint8_t> in_group((size_t)M, 0);
+    for (auto& kv : by_key)
+        if ((int64_t)kv.second.size() >= min_group) {
+            for (int32_t m : kv.second) in_group[m] = 1;
+            groups.push_back(std::move(kv.second));
+        }
+    if (groups.empty()) return plain();
+    std::sort(groups.begin(), groups.end());          // deterministic order
+    std::vector<int32_t> rest;
+    for (int64_t m = 0; m < M; ++m)
+        if (!in_group[m]) rest.push_back((int32_t)m);
+
+    // 2. each group's kept samples from its first SNP; every member is
+    //    checked against that pattern on the device (a key collision sends
+    //    the whole call to the ungrouped path)
+    const size_t G = groups.size();
+    std::vector<std::vector<int32_t>> kept(G);
+    std::vector<uint8_t> qmask_h(G * (size_t)K);
+    std::vector<int8_t> row((size_t)K);
+    for (size_t gi = 0; gi < G; ++gi) {
+        HIP_TRY(c, hipMemcpy(row.data(), geno + (int64_t)groups[gi][0] * ld_geno, (size_t)K,
+                             hipMemcpyDeviceToHost));
+        for (int k = 0; k < K; ++k) {
+            const bool miss = row[k] < 0 || row[k] > 2;
+            qmask_h[gi * K + k] = miss;
+            if (!miss) kept[gi].push_back(k);
+        }
+    }
+    std::vector<int32_t> snp_all, smp_all;
+    std::vector<int64_t> snp_off, smp_off;
+    for (size_t gi = 0; gi < G; ++gi) {
+        snp_off.push_back((int64_t)snp_all.size());
+        snp_all.insert(snp_all.end(), groups[gi].begin(), groups[gi].end());
+        smp_off.push_back((int64_t)smp_all.size());
+        smp_all.insert(smp_all.end(), kept[gi].begin(), kept[gi].end());
+    }
+    snp_off.push_back((int64_t)snp_all.size());
+    snp_all.insert(snp_all.end(), rest.begin(), rest.end());
+    int32_t* d_snps = (int32_t*)ws(c, S_G_SNPS, snp_all.size() * 4, &s);
+    int32_t* d_smp = (int32_t*)ws(c, S_G_SAMPLES, std::max<size_t>(smp_all.size(), 1) * 4, &s);
+    uint8_t* d_q = (uint8_t*)ws(c, S_G_QMASK, qmask_h.size(), &s);
+    unsigned long long* cnt = (unsigned long long*)ws(c, S_G_CNT, 256, &s);
+    if (s != KRUX_OK) return s;
+    HIP_TRY(c, hipMemcpy(d_snps, snp_all.data(), snp_all.size() * 4, hipMemcpyHostToDevice));
+    if (!smp_all.empty())
+        HIP_TRY(c, hipMemcpy(d_smp, smp_all.data(), smp_all.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(d_q, qmask_h.data(), qmask_h.size(), hipMemcpyHostToDevice));
+    HIP_TRY(c, kx_launch_fill_u64(cnt, 3, 0ull, st));     // bad, stored, total
+    for (size_t gi = 0; gi < G; ++gi)
+        HIP_TRY(c, kx_launch_check_pattern(geno, ld_geno, K, d_snps + snp_off[gi],
+                                           (int64_t)groups[gi].size(), d_q + gi * K, cnt, grid,
+                                           st));
+    unsigned long long bad = 0;
+    HIP_TRY(c, hipMemcpyAsync(&bad, cnt, 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    if (bad) return plain();
+
+    // 3. the sub-problems
+    const int64_t cap = hit_capacity;
+    kx::HitRec* stage = (kx::HitRec*)ws(c, S_G_STAGE, (size_t)std::max<int64_t>(cap, 1) * 24, &s);
+    kx::HitRec* phits = (kx::HitRec*)ws(c, S_G_PHITS, (size_t)std::max<int64_t>(cap, 1) * 24, &s);
+    int64_t* pn = (int64_t*)ws(c, S_G_PN, 256, &s);
+    double* acc = min_p ? (double*)ws(c, S_G_MINP, (size_t)T * 8, &s) : nullptr;
+    double* pmin = min_p ? (double*)ws(c, S_G_PMINP, (size_t)T * 8, &s) : nullptr;
+    int8_t* gsub = (int8_t*)ws(c, S_G_GENO, (size_t)M * K, &s);
+    float* xsub = (float*)ws(c, S_G_EXPR, (size_t)T * K * 4, &s);
+    int16_t* rsub = (int16_t*)ws(c, S_G_R, (size_t)T * K * 2, &s);
+    int64_t* tsub = (int64_t*)ws(c, S_G_TS, (size_t)T * 8, &s);
+    if (s != KRUX_OK) return s;
+    if (min_p) HIP_TRY(c, kx_launch_fill_u64((unsigned long long*)acc, T, 0x3FF0000000000000ull, st));
+    for (size_t part = 0; part <= G; ++part) {
+        const bool grp = part < G;
+        const int64_t n = grp ? (int64_t)groups[part].size() : (int64_t)rest.size();
+        if (n == 0) continue;
+        const int32_t* snps = d_snps + snp_off[part];
+        const int Kp = grp ? (int)kept[part].size() : K;
+        const int16_t* r2 = ranks2;
+        const int64_t* ts = tiesum;
+        const int32_t* S = nullptr;
+        if (grp) {
+            if (Kp == 0) continue;                 // no sample left: H = 0, p = 1, no hit
+            S = d_smp + smp_off[part];
+            HIP_TRY(c, kx_launch_gather_rank_cols(ranks2, T, K, S, Kp, xsub, grid, st));
+            HIP_TRY(c, kx_launch_rank(xsub, T, Kp, Kp, rsub, tsub, nullptr, 1 << 30, st));
+            r2 = rsub;
+            ts = tsub;
+        }
+        HIP_TRY(c, kx_launch_gather_geno(geno, ld_geno, snps, n, S, Kp, gsub, grid, st));
+        if ((s = test_impl(c, r2, ts, T, Kp, gsub, n, Kp, 0, p_c, KRUX_MODE_HITS, precision,
+                           (krux_hit*)phits, cap, pn, pmin, nullptr, nullptr, nullptr, st)) !=
+            KRUX_OK)
+            return s;
+        HIP_TRY(c, kx_launch_append_hits(phits, pn, cap, snps, snp_base, stage, cnt + 1, cnt + 2,
+                                         grid, st));
+        if (min_p) HIP_TRY(c, kx_launch_min_merge(pmin, acc, T, grid, st));
+    }
+    if ((s = sort_stage(c, stage, cnt + 1, cap, hits, n_hits, T, st)) != KRUX_OK) return s;
+    HIP_TRY(c, kx_launch_set_counts(n_hits, cnt + 2, cnt + 1, cap, st));
+    if (min_p) HIP_TRY(c, hipMemcpyAsync(min_p, acc, (size_t)T * 8, hipMemcpyDeviceToDevice, st));
     return KRUX_OK;
 }
 

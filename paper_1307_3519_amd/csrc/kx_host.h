@@ -51,6 +51,23 @@ size_t kx_sort_tmp_bytes(int64_t cap);
 hipError_t kx_sort_hits(const kx::HitRec* stage, const unsigned long long* n_hits, int64_t cap,
                         unsigned long long* keys, uint32_t* idx, void* tmp, size_t tmp_bytes,
                         kx::HitRec* out, int64_t* n_out, int key_bits, hipStream_t st);
+hipError_t kx_launch_miss_keys(const int8_t* geno, int64_t M, int64_t ld, int K, uint64_t* key,
+                               int grid, hipStream_t st);
+hipError_t kx_launch_check_pattern(const int8_t* geno, int64_t ld, int K, const int32_t* snps,
+                                   int64_t n, const uint8_t* qmask, unsigned long long* bad,
+                                   int grid, hipStream_t st);
+hipError_t kx_launch_gather_rank_cols(const int16_t* ranks2, int64_t T, int K, const int32_t* S,
+                                      int Kp, float* out, int grid, hipStream_t st);
+hipError_t kx_launch_gather_geno(const int8_t* geno, int64_t ld, const int32_t* rows, int64_t n,
+                                 const int32_t* S, int Kp, int8_t* out, int grid, hipStream_t st);
+hipError_t kx_launch_append_hits(const kx::HitRec* part, const int64_t* part_n, int64_t cap,
+                                 const int32_t* snp_map, int64_t snp_base, kx::HitRec* stage,
+                                 unsigned long long* stored, unsigned long long* total, int grid,
+                                 hipStream_t st);
+hipError_t kx_launch_min_merge(const double* part, double* acc, int64_t n, int grid,
+                               hipStream_t st);
+hipError_t kx_launch_set_counts(int64_t* n_out, const unsigned long long* total,
+                                unsigned long long* stored, int64_t cap, hipStream_t st);
 size_t kx_sort_keys_tmp_bytes(int64_t cap);
 hipError_t kx_fdr_curve(const kx::HitRec* real, const int64_t* n_real, int64_t real_cap,
                         const kx::HitRec* perm, const int64_t* n_perm, int64_t perm_cap, int P,

@@ -77,6 +77,17 @@ def set_missing(rng, g, p_missing):
     return g
 
 
+def set_missing_samples(rng, g, sample_sets, fracs):
+    """Sample-structured missing genotypes (a failed sample): for each set of
+    samples and its fraction, each SNP, with that probability, has every
+    sample of the set missing (-1).  Later sets overwrite earlier ones."""
+    g = g.copy()
+    for samples, frac in zip(sample_sets, fracs):
+        rows = rng.random(g.shape[0]) < frac
+        g[np.ix_(rows, np.asarray(samples, dtype=np.int64))] = -1
+    return g
+
+
 def set_nan_expression(rng, x, trait_frac, max_per_trait):
     """Missing expression values: each trait, with probability trait_frac,
     gets between 1 and max_per_trait NaN entries at distinct samples."""

@@ -22,6 +22,7 @@ _MODE = {"hits": MODE_HITS, "full": MODE_FULL, "sums": MODE_SUMS}
 
 EXPORTS = ("krux_create", "krux_destroy", "krux_last_error", "krux_threshold",
            "krux_rank", "krux_test", "krux_permute", "krux_permute_hits", "krux_fdr_curve",
+           "krux_test_grouped",
            "krux_test_batched",
            "krux_timer_start", "krux_timer_read", "krux_autotune", "krux_load_tuning",
            "krux_tuning_of")
@@ -73,6 +74,9 @@ def library():
     lib.krux_permute.restype = ctypes.c_int
     lib.krux_permute.argtypes = [P, P, P, i64, i32, P, i64, i64, P, i32, P, i32, P, P, P]
     lib.krux_test_batched.restype = ctypes.c_int
+    lib.krux_test_grouped.restype = ctypes.c_int
+    lib.krux_test_grouped.argtypes = [P, P, P, i64, i32, P, i64, i64, i64, dbl, i32, i64, P, i64,
+                                      P, P, P]
     lib.krux_permute_hits.restype = ctypes.c_int
     lib.krux_permute_hits.argtypes = [P, P, P, i64, i32, P, i64, i64, P, i32, dbl, P, i64, P, P]
     lib.krux_fdr_curve.restype = ctypes.c_int
@@ -247,6 +251,23 @@ class Context:
         if m == MODE_FULL:
             return dict(H=H, p=p)
         return dict(sums=sums)
+
+    def test_grouped(self, ranks2, tiesum, geno, p_c=1e-5, precision="fp16", min_group=256,
+                     hit_capacity=1 << 16, min_p=True, snp_base=0):
+        """As test() in hits mode, with SNPs grouped by missing-genotype pattern."""
+        T, K = ranks2.shape
+        M = geno.shape[0]
+        assert geno.dtype == torch.int8 and geno.dim() == 2 and geno.shape[1] == K
+        assert M == 0 or geno.stride(1) == 1
+        dev = ranks2.device
+        hits = torch.empty(max(hit_capacity, 1) * 24, dtype=torch.uint8, device=dev)
+        nh = torch.zeros(1, dtype=torch.int64, device=dev)
+        mp = torch.empty(T, dtype=torch.float64, device=dev) if min_p else None
+        self._check(self.lib.krux_test_grouped(
+            self.h, _ptr(ranks2), _ptr(tiesum), T, K, _ptr(geno), M,
+            geno.stride(0) if M else K, int(snp_base), float(p_c), _PREC[precision],
+            int(min_group), _ptr(hits), int(hit_capacity), _ptr(nh), _ptr(mp), _stream()))
+        return dict(hits_raw=hits, n_hits_t=nh, min_p=mp, hit_capacity=hit_capacity)
 
     # ------------------------------------------------------------------ permute
     def permute(self, ranks2, tiesum, geno, perms, p_cs=(1e-4, 1e-5, 1e-6), min_p=True,

@@ -51,3 +51,16 @@ def test_nan_expression_recipe():
     rs = datagen.streams(5)
     datagen.set_nan_expression(rs["nan"], x, 0.5, 3)
     assert np.array_equal(a, rs["expr"].random(3))
+
+
+def test_sample_structured_missing():
+    g = np.zeros((2000, 50), np.int8)
+    out = datagen.set_missing_samples(datagen.streams(6)["missing"], g, [[1, 7, 49], [3]],
+                                      [0.5, 0.25])
+    assert not (g < 0).any()
+    miss = out < 0
+    a = miss[:, [1, 7, 49]].all(axis=1)
+    assert np.array_equal(a, miss[:, [1, 7, 49]].any(axis=1))     # all or none
+    assert 850 <= a.sum() <= 1150
+    assert 380 <= miss[:, 3].sum() <= 620
+    assert miss.sum() == 3 * a.sum() + miss[:, 3].sum()

@@ -385,3 +385,51 @@ def test_missing_expression_heavy_ties(kx):
     torch.cuda.synchronize()
     assert np.array_equal(res["sums"].cpu().numpy().astype(np.int64), o["sums"])
     _check_hits(kx, x, g, 0.05, "fp16")
+
+
+# ---------------------------------------------------------------- missing-pattern groups
+GROUP_CASES = [  # (K, T, M, precision)
+    (102, 40, 600, "fp16"),
+    (48, 30, 400, "int8"),
+    (233, 25, 300, "fp16"),
+    (102, 20, 300, "fp64"),
+]
+
+
+@pytest.mark.parametrize("K,T,M,prec", GROUP_CASES)
+def test_grouped_patterns(kx, K, T, M, prec):
+    from paper_1307_3519_amd.krux import unpack_hits
+    say("grouped", K, T, M, prec)
+    x, g = _inputs(41 * K + T, T, K, M, nan_frac=0.02)
+    rs = datagen.streams(K + T)
+    g = datagen.set_missing_samples(rs["missing"], g, [[3, 17, K - 1], [8]], [0.6, 0.2])
+    g = datagen.set_missing(rs["cohort"], g, 0.003)       # sporadic: patterns of their own
+    r, ts = _ranks(kx, x)
+    gd = _dev(g)
+    p_c = 0.02
+    res = kx.test_grouped(r, ts, gd, p_c=p_c, precision=prec, min_group=16,
+                          hit_capacity=1 << 15, snp_base=5)
+    ref = kx.test(r, ts, gd, p_c=p_c, mode="hits", precision=prec, hit_capacity=1 << 15,
+                  min_p=True, snp_base=5)
+    torch.cuda.synchronize()
+    o = oracle.scan(x, g, p_cs=(p_c,), hits=True, min_p=True)
+    n, h = unpack_hits(res)
+    assert n == o["n_hits"] and n > 0
+    assert np.array_equal(h["trait"], o["hits"]["trait"])
+    assert np.array_equal(h["snp"] - 5, o["hits"]["snp"])
+    assert_H(h["H"], o["hits"]["H"], "grouped H")
+    assert_p(h["p"], o["hits"]["p"], "grouped p")
+    assert_p(res["min_p"].cpu().numpy(), o["min_p"], "grouped min p")
+    # the same bits as the ungrouped scan
+    n2, h2 = unpack_hits(ref)
+    assert n2 == n
+    for f in ("trait", "snp", "H", "p"):
+        assert np.array_equal(h[f], h2[f]), f
+    assert np.array_equal(res["min_p"].cpu().numpy(), ref["min_p"].cpu().numpy())
+    # capacity below the count: the true count and a valid subset
+    small = kx.test_grouped(r, ts, gd, p_c=p_c, precision=prec, min_group=16, hit_capacity=4)
+    torch.cuda.synchronize()
+    n_s, hs = unpack_hits(small)
+    assert n_s == n and len(hs["snp"]) == 4
+    assert set(zip(hs["trait"].tolist(), hs["snp"].tolist())) <= \
+        set(zip(h["trait"].tolist(), (h["snp"] - 5).tolist()))
