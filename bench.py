@@ -24,6 +24,9 @@ Workloads (--workload; seeded synthetic data shaped like the paper's
   cohorts_missing  8 cohorts, K in {48, ..., 1000}, 5,000-20,000 traits each,
       one 200,000-SNP panel with 2% missing genotypes; hits at p < 1e-5 per
       cohort
+  sample_missing   the paper-scale workload with sample-structured missing
+      genotypes (samples 5 and 40 missing in 90% of the SNPs, sample 77 in
+      30%); the pattern-grouped scan timed beside the per-pair path
   missing_expression  the paper-scale workload with NaN expression values in
       2% of the traits (1-5 each); hits at p < 1e-5 plus the per-trait minimum
       p, timed beside the same traits without NaN values
@@ -485,9 +488,63 @@ def missing_expression(args, ctx, torch, np, datagen, krux):
     return out
 
 
+def sample_missing(args, ctx, torch, np, datagen, krux):
+    wl = dict(datagen.WORKLOADS[2])
+    T = args.T or wl["T"]
+    M = args.M or wl["M"]
+    K = wl["K"]
+    p_c = 1e-5
+    sets, fracs = [[5, 40], [77]], [0.9, 0.3]
+    log("generating workload K=%d T=%d M=%d, failed samples %s at %s" % (K, T, M, sets, fracs))
+    w = datagen.make_workload(2, T=T, M=M)
+    g_np = datagen.set_missing_samples(datagen.streams(2)["missing"], w["geno"], sets, fracs)
+    x = torch.from_numpy(w["expr"]).cuda()
+    g = torch.from_numpy(g_np).cuda()
+    runner = Runner(ctx, torch)
+    cap = 1 << 17
+    minp = not args.no_minp
+    steps = max(1, min(args.steps, 10))
+    warm = max(1, min(args.warmup, 3))
+
+    def per_pair():
+        r, ts, _ = ctx.rank(x)
+        return ctx.test(r, ts, g, p_c=p_c, mode="hits", precision="fp16", hit_capacity=cap,
+                        min_p=minp)
+
+    def grouped():
+        r, ts, _ = ctx.rank(x)
+        return ctx.test_grouped(r, ts, g, p_c=p_c, precision="fp16", min_group=256,
+                                hit_capacity=cap, min_p=minp)
+
+    log("per-pair path: %d warmup + %d timed steps" % (warm, steps))
+    ms_pp, res_pp, _, _ = runner.run(per_pair, steps, warm)
+    log("grouped path: %d warmup + %d timed steps" % (warm, steps))
+    ms_g, res_g, _, _ = runner.run(grouped, steps, warm)
+    a, b = krux.unpack_hits(res_pp), krux.unpack_hits(res_g)
+    same = same_hits(a, b) and (not minp or bool(torch.equal(res_pp["min_p"], res_g["min_p"])))
+    log("per-pair %.2f ms/step, grouped %.2f ms/step, hits %d / %d, identical %s"
+        % (ms_pp, ms_g, a[0], b[0], same))
+    pairs = float(T) * float(M)
+    out = base_line(args, METRIC, pairs / (ms_g / 1e3), "pairs/s", ms_g, "f16", {
+        "workload": "sample_missing", "K": K, "T": T, "M": M, "p_c": p_c,
+        "failed_samples": sets, "fraction_of_snps": fracs, "min_group": 256,
+        "outputs": "sorted hit list (p < 1e-5)" + (" + per-trait min p" if minp else "")})
+    out["steps"], out["warmup"] = steps, warm
+    out["per_pair_path"] = {"ms_per_step": ms_pp, "value": pairs / (ms_pp / 1e3),
+                            "unit": "pairs/s"}
+    out["identical_results"] = same
+    out["n_hits"] = b[0]
+    if not args.no_cpu:
+        import oracle
+        out["cpu_baseline"] = oracle_baseline(
+            args, T, M, "hits at p<1e-5" + (" + per-trait min p" if minp else ""),
+            lambda n: oracle.scan(w["expr"], g_np[:n], p_cs=(p_c,), hits=True, min_p=minp))
+    return out
+
+
 WORKLOADS = {"paper_scale_hits": paper_scale_hits, "precision_K500": precision_k500,
              "permutations": permutations, "cohorts_missing": cohorts_missing,
-             "missing_expression": missing_expression}
+             "missing_expression": missing_expression, "sample_missing": sample_missing}
 
 
 def main():

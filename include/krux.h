@@ -146,8 +146,8 @@ krux_status krux_test(krux_ctx* ctx, const int16_t* ranks2, const int64_t* tiesu
  * krux_test.  Same arguments, outputs and results as krux_test in HITS mode
  * (hits sorted by (trait, snp), true count in *n_hits, min_p per trait);
  * faster when many SNPs share their missing samples (a failed sample).
- * Synchronises `stream` twice (to group the patterns on the host) and makes
- * small synchronous copies, so it cannot be captured into a graph. */
+ * Synchronises `stream` a few times (the host reads the patterns' counts
+ * and masks), so it cannot be captured into a graph. */
 krux_status krux_test_grouped(krux_ctx* ctx, const int16_t* ranks2, const int64_t* tiesum,
                               int64_t T, int32_t K, const int8_t* geno, int64_t M,
                               int64_t ld_geno, int64_t snp_base, double p_c, int32_t precision,

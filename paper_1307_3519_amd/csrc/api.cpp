@@ -9,7 +9,6 @@
 #include <cstring>
 #include <string>
 #include <map>
-#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -902,73 +901,79 @@ krux_status krux_test_grouped(krux_ctx* c, const int16_t* ranks2, const int64_t*
     HIP_TRY(c, hipSetDevice(c->device));
     const int grid = c->n_cu * 8;
 
-    // 1. pattern keys, grouped on the host (one synchronisation)
-    uint64_t* keys = (uint64_t*)ws(c, S_G_KEYS, (size_t)M * 8, &s);
+    // 1. pattern keys; their runs in sorted order give the patterns shared
+    //    by at least min_group SNPs (G of them, keys ascending)
+    const size_t tmpb = kx_group_tmp_bytes(M);
+    uint64_t* keys = (uint64_t*)ws(c, S_G_KEYS, (size_t)M * 28 + 256, &s);
+    void* gtmp = ws(c, S_G_EXPR, std::max(tmpb, (size_t)T * K * 4), &s);
     if (s != KRUX_OK) return s;
+    uint64_t* sorted = keys + M;
+    uint64_t* uniq = keys + 2 * M;
+    uint32_t* runc = (uint32_t*)(keys + 3 * M);
+    uint32_t* nrun = runc + M;
     HIP_TRY(c, kx_launch_miss_keys(geno, M, ld_geno, K, keys, grid, st));
-    std::vector<uint64_t> hk((size_t)M);
-    HIP_TRY(c, hipMemcpyAsync(hk.data(), keys, (size_t)M * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, kx_group_runs(keys, M, sorted, uniq, runc, nrun, gtmp, tmpb, st));
+    uint32_t n_runs = 0;
+    HIP_TRY(c, hipMemcpyAsync(&n_runs, nrun, 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipStreamSynchronize(st));
-    std::unordered_map<uint64_t, std::vector<int32_t>> by_key;
-    for (int64_t m = 0; m < M; ++m)
-        if (hk[m]) by_key[hk[m]].push_back((int32_t)m);
-    std::vector<std::vector<int32_t>> groups;
-    std::vector<uint8_t> in_group((size_t)M, 0);
-    for (auto& kv : by_key)
-        if ((int64_t)kv.second.size() >= min_group) {
-            for (int32_t m : kv.second) in_group[m] = 1;
-            groups.push_back(std::move(kv.second));
+    std::vector<uint64_t> uk(n_runs);
+    std::vector<uint32_t> uc(n_runs);
+    if (n_runs) {
+        HIP_TRY(c, hipMemcpyAsync(uk.data(), uniq, (size_t)n_runs * 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipMemcpyAsync(uc.data(), runc, (size_t)n_runs * 4, hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipStreamSynchronize(st));
+    }
+    std::vector<uint64_t> big;
+    std::vector<int64_t> off(1, 0);
+    for (uint32_t r = 0; r < n_runs; ++r)
+        if (uk[r] != 0 && (int64_t)uc[r] >= min_group) {
+            big.push_back(uk[r]);
+            off.push_back(off.back() + uc[r]);
         }
-    if (groups.empty()) return plain();
-    std::sort(groups.begin(), groups.end());          // deterministic order
-    std::vector<int32_t> rest;
-    for (int64_t m = 0; m < M; ++m)
-        if (!in_group[m]) rest.push_back((int32_t)m);
+    const int G = (int)big.size();
+    if (G == 0) return plain();
+    off.push_back(M);                                  // the rest: [off[G], M)
 
-    // 2. each group's kept samples from its first SNP; every member is
-    //    checked against that pattern on the device (a key collision sends
-    //    the whole call to the ungrouped path)
-    const size_t G = groups.size();
-    std::vector<std::vector<int32_t>> kept(G);
-    std::vector<uint8_t> qmask_h(G * (size_t)K);
-    std::vector<int8_t> row((size_t)K);
-    for (size_t gi = 0; gi < G; ++gi) {
-        HIP_TRY(c, hipMemcpy(row.data(), geno + (int64_t)groups[gi][0] * ld_geno, (size_t)K,
-                             hipMemcpyDeviceToHost));
-        for (int k = 0; k < K; ++k) {
-            const bool miss = row[k] < 0 || row[k] > 2;
-            qmask_h[gi * K + k] = miss;
-            if (!miss) kept[gi].push_back(k);
-        }
-    }
-    std::vector<int32_t> snp_all, smp_all;
-    std::vector<int64_t> snp_off, smp_off;
-    for (size_t gi = 0; gi < G; ++gi) {
-        snp_off.push_back((int64_t)snp_all.size());
-        snp_all.insert(snp_all.end(), groups[gi].begin(), groups[gi].end());
-        smp_off.push_back((int64_t)smp_all.size());
-        smp_all.insert(smp_all.end(), kept[gi].begin(), kept[gi].end());
-    }
-    snp_off.push_back((int64_t)snp_all.size());
-    snp_all.insert(snp_all.end(), rest.begin(), rest.end());
-    int32_t* d_snps = (int32_t*)ws(c, S_G_SNPS, snp_all.size() * 4, &s);
-    int32_t* d_smp = (int32_t*)ws(c, S_G_SAMPLES, std::max<size_t>(smp_all.size(), 1) * 4, &s);
-    uint8_t* d_q = (uint8_t*)ws(c, S_G_QMASK, qmask_h.size(), &s);
-    unsigned long long* cnt = (unsigned long long*)ws(c, S_G_CNT, 256, &s);
+    // 2. every SNP into its part; each group's pattern from one member,
+    //    every member checked against it (a key collision sends the whole
+    //    call to the ungrouped path)
+    int32_t* d_snps = (int32_t*)ws(c, S_G_SNPS, (size_t)M * 4 + 256, &s);
+    int64_t* d_off = (int64_t*)ws(c, S_G_SAMPLES, (size_t)(G + 2) * 8 + (size_t)G * K * 4 + 256, &s);
+    int32_t* d_smp = (int32_t*)(d_off + G + 2);
+    uint64_t* d_big = (uint64_t*)ws(c, S_G_QMASK, (size_t)G * 8 + (size_t)G * K + 256, &s);
+    uint8_t* d_q = (uint8_t*)(d_big + G);
+    unsigned long long* cnt = (unsigned long long*)ws(c, S_G_CNT, (size_t)(G + 8) * 8, &s);
     if (s != KRUX_OK) return s;
-    HIP_TRY(c, hipMemcpy(d_snps, snp_all.data(), snp_all.size() * 4, hipMemcpyHostToDevice));
-    if (!smp_all.empty())
-        HIP_TRY(c, hipMemcpy(d_smp, smp_all.data(), smp_all.size() * 4, hipMemcpyHostToDevice));
-    HIP_TRY(c, hipMemcpy(d_q, qmask_h.data(), qmask_h.size(), hipMemcpyHostToDevice));
-    HIP_TRY(c, kx_launch_fill_u64(cnt, 3, 0ull, st));     // bad, stored, total
-    for (size_t gi = 0; gi < G; ++gi)
-        HIP_TRY(c, kx_launch_check_pattern(geno, ld_geno, K, d_snps + snp_off[gi],
-                                           (int64_t)groups[gi].size(), d_q + gi * K, cnt, grid,
-                                           st));
+    unsigned long long* fill = cnt + 3;                // cnt: bad, stored, total
+    HIP_TRY(c, hipMemcpyAsync(d_big, big.data(), (size_t)G * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(c, hipMemcpyAsync(d_off, off.data(), (size_t)(G + 2) * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(c, kx_launch_fill_u64(cnt, G + 4, 0ull, st));
+    HIP_TRY(c, kx_launch_assign_parts(keys, M, d_big, G, d_off, fill, d_snps, grid, st));
+    HIP_TRY(c, kx_launch_pattern_mask(geno, ld_geno, K, d_snps, d_off, G, d_q, grid, st));
+    for (int gi = 0; gi < G; ++gi)
+        HIP_TRY(c, kx_launch_check_pattern(geno, ld_geno, K, d_snps + off[gi],
+                                           off[gi + 1] - off[gi], d_q + (int64_t)gi * K, cnt,
+                                           grid, st));
+    std::vector<uint8_t> qmask_h((size_t)G * K);
     unsigned long long bad = 0;
+    HIP_TRY(c, hipMemcpyAsync(qmask_h.data(), d_q, qmask_h.size(), hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipMemcpyAsync(&bad, cnt, 8, hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipStreamSynchronize(st));
     if (bad) return plain();
+    std::vector<int32_t> smp_all;
+    std::vector<int64_t> smp_off;
+    std::vector<int> kp_of;
+    for (int gi = 0; gi < G; ++gi) {
+        smp_off.push_back((int64_t)smp_all.size());
+        for (int k = 0; k < K; ++k)
+            if (!qmask_h[(size_t)gi * K + k]) smp_all.push_back(k);
+        kp_of.push_back((int)(smp_all.size() - smp_off.back()));
+    }
+    if (!smp_all.empty()) {
+        HIP_TRY(c, hipMemcpyAsync(d_smp, smp_all.data(), smp_all.size() * 4,
+                                  hipMemcpyHostToDevice, st));
+        HIP_TRY(c, hipStreamSynchronize(st));         // smp_all is pageable host memory
+    }
 
     // 3. the sub-problems
     const int64_t cap = hit_capacity;
@@ -978,17 +983,17 @@ krux_status krux_test_grouped(krux_ctx* c, const int16_t* ranks2, const int64_t*
     double* acc = min_p ? (double*)ws(c, S_G_MINP, (size_t)T * 8, &s) : nullptr;
     double* pmin = min_p ? (double*)ws(c, S_G_PMINP, (size_t)T * 8, &s) : nullptr;
     int8_t* gsub = (int8_t*)ws(c, S_G_GENO, (size_t)M * K, &s);
-    float* xsub = (float*)ws(c, S_G_EXPR, (size_t)T * K * 4, &s);
+    float* xsub = (float*)gtmp;
     int16_t* rsub = (int16_t*)ws(c, S_G_R, (size_t)T * K * 2, &s);
     int64_t* tsub = (int64_t*)ws(c, S_G_TS, (size_t)T * 8, &s);
     if (s != KRUX_OK) return s;
     if (min_p) HIP_TRY(c, kx_launch_fill_u64((unsigned long long*)acc, T, 0x3FF0000000000000ull, st));
-    for (size_t part = 0; part <= G; ++part) {
+    for (int part = 0; part <= G; ++part) {
         const bool grp = part < G;
-        const int64_t n = grp ? (int64_t)groups[part].size() : (int64_t)rest.size();
+        const int64_t n = off[part + 1] - off[part];
         if (n == 0) continue;
-        const int32_t* snps = d_snps + snp_off[part];
-        const int Kp = grp ? (int)kept[part].size() : K;
+        const int32_t* snps = d_snps + off[part];
+        const int Kp = grp ? kp_of[part] : K;
         const int16_t* r2 = ranks2;
         const int64_t* ts = tiesum;
         const int32_t* S = nullptr;

@@ -3,6 +3,8 @@
 // matrices).  The kernels key each SNP by its pattern, check a group's
 // members against the pattern, gather the sub-problem's columns and rows,
 // and merge the sub-problems' hit lists and per-trait minima.
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_run_length_encode.hpp>
 #include "kx_common.h"
 
 namespace kx {
@@ -31,6 +33,61 @@ __global__ __launch_bounds__(256) void miss_keys(const int8_t* __restrict__ geno
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) h += __shfl_xor(h, o, 64);
         if (lane == 0) key[m] = h;
+    }
+}
+
+// Part of every SNP: the index of its key among the G sorted group keys, G
+// (the ungrouped rest) when absent; each SNP is placed in its part's slice
+// of list (order within a part is arbitrary).  Lanes of a wave with the same
+// part take their places with one atomic.
+__global__ void assign_parts(const uint64_t* __restrict__ key, int64_t M,
+                             const uint64_t* __restrict__ big, int G,
+                             const int64_t* __restrict__ off, unsigned long long* fill,
+                             int32_t* __restrict__ list) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t m0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); m0 < M;
+         m0 += stride) {
+        const int64_t m = m0 + lane;
+        const bool valid = m < M;
+        int g = -1;
+        if (valid) {
+            const uint64_t k = key[m];
+            int lo = 0, hi = G;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (big[mid] < k) lo = mid + 1;
+                else hi = mid;
+            }
+            g = (k != 0 && lo < G && big[lo] == k) ? lo : G;
+        }
+        unsigned long long todo = __ballot(valid);
+        while (todo) {
+            const int leader = __builtin_ctzll(todo);
+            const int gl = __shfl(g, leader, 64);
+            const unsigned long long same = __ballot(valid && g == gl);
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(&fill[gl], (unsigned long long)__popcll(same));
+            base = __shfl(base, leader, 64);
+            if (valid && g == gl)
+                list[off[gl] + (int64_t)(base + __popcll(same & below))] = (int32_t)m;
+            todo &= ~same;
+        }
+    }
+}
+
+// qmask[g][k] = 1 when sample k is missing at the first SNP of group g's
+// slice of list (any member: all are checked against it afterwards).
+__global__ void pattern_mask(const int8_t* __restrict__ geno, int64_t ld, int K,
+                             const int32_t* __restrict__ list, const int64_t* __restrict__ off,
+                             int G, uint8_t* __restrict__ qmask) {
+    const int64_t n = (int64_t)G * K;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t g = i / K;
+        const int k = (int)(i - g * K);
+        qmask[i] = is_missing(geno[(int64_t)list[off[g]] * ld + k]) ? 1 : 0;
     }
 }
 
@@ -117,6 +174,44 @@ __global__ void set_counts(int64_t* n_out, const unsigned long long* total,
 extern "C" hipError_t kx_launch_miss_keys(const int8_t* geno, int64_t M, int64_t ld, int K,
                                           uint64_t* key, int grid, hipStream_t st) {
     hipLaunchKernelGGL(kx::miss_keys, dim3(grid), dim3(256), 0, st, geno, M, ld, K, key);
+    return hipGetLastError();
+}
+
+// Sorted copy of the keys and its runs: uniq[r], counts[r] for r < *n_runs.
+extern "C" size_t kx_group_tmp_bytes(int64_t M) {
+    size_t a = 0, b = 0;
+    (void)rocprim::radix_sort_keys((void*)nullptr, a, (uint64_t*)nullptr, (uint64_t*)nullptr,
+                                   (size_t)M, 0, 64);
+    (void)rocprim::run_length_encode((void*)nullptr, b, (uint64_t*)nullptr, (unsigned int)M,
+                                     (uint64_t*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr);
+    return a > b ? a : b;
+}
+
+extern "C" hipError_t kx_group_runs(const uint64_t* key, int64_t M, uint64_t* sorted,
+                                    uint64_t* uniq, uint32_t* counts, uint32_t* n_runs, void* tmp,
+                                    size_t tmp_bytes, hipStream_t st) {
+    size_t bytes = tmp_bytes;
+    hipError_t e = rocprim::radix_sort_keys(tmp, bytes, key, sorted, (size_t)M, 0, 64, st);
+    if (e != hipSuccess) return e;
+    bytes = tmp_bytes;
+    return rocprim::run_length_encode(tmp, bytes, sorted, (unsigned int)M, uniq, counts, n_runs,
+                                      st);
+}
+
+extern "C" hipError_t kx_launch_assign_parts(const uint64_t* key, int64_t M, const uint64_t* big,
+                                             int G, const int64_t* off,
+                                             unsigned long long* fill, int32_t* list, int grid,
+                                             hipStream_t st) {
+    hipLaunchKernelGGL(kx::assign_parts, dim3(grid), dim3(256), 0, st, key, M, big, G, off, fill,
+                       list);
+    return hipGetLastError();
+}
+
+extern "C" hipError_t kx_launch_pattern_mask(const int8_t* geno, int64_t ld, int K,
+                                             const int32_t* list, const int64_t* off, int G,
+                                             uint8_t* qmask, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(kx::pattern_mask, dim3(grid), dim3(256), 0, st, geno, ld, K, list, off, G,
+                       qmask);
     return hipGetLastError();
 }
 
