@@ -55,6 +55,13 @@ def test_null_context_is_rejected():
                        None, 0, None, None, None, None, None, None)
     assert st == 1
     assert lib.krux_create(None, 0) == 1
+    # the permuted-hit, FDR-curve and grouped entry points
+    assert lib.krux_permute_hits(None, None, None, 0, 1, None, 0, 1, None, 1, 0.1, None, 0,
+                                 None, None) == 1
+    assert lib.krux_fdr_curve(None, None, None, 0, None, None, 0, 1, None, None) == 1
+    assert lib.krux_test_grouped(None, None, None, 0, 1, None, 0, 1, 0, 0.1, 0, 16, None, 0,
+                                 None, None, None) == 1
+    assert b"ctx" in lib.krux_last_error(None)
 
 
 def test_struct_layouts():

@@ -433,3 +433,28 @@ def test_grouped_patterns(kx, K, T, M, prec):
     assert n_s == n and len(hs["snp"]) == 4
     assert set(zip(hs["trait"].tolist(), hs["snp"].tolist())) <= \
         set(zip(h["trait"].tolist(), (h["snp"] - 5).tolist()))
+
+
+def test_new_entry_points_reject_bad_arguments(kx):
+    from paper_1307_3519_amd import krux
+    say("argument errors")
+    x, g = _inputs(5, 8, 20, 30)
+    r, ts = _ranks(kx, x)
+    gd = _dev(g)
+    perms = _dev(datagen.permutations(datagen.streams(5)["perms"], 2, 20))
+    with pytest.raises(krux.KruxError):
+        kx.test_grouped(r, ts, gd, min_group=0)
+    with pytest.raises(krux.KruxError):
+        kx.test_grouped(r, ts, gd, p_c=0.0)
+    with pytest.raises(krux.KruxError):
+        kx.permute_hits(r, ts, gd, perms, p_c=1.5)
+    real = kx.test(r, ts, gd, p_c=0.5, mode="hits", hit_capacity=64)
+    ph = kx.permute_hits(r, ts, gd, perms, p_c=0.5, hit_capacity=64)
+    with pytest.raises(krux.KruxError):
+        kx.fdr_curve(real, ph, 0)
+    torch.cuda.synchronize()
+    # the context still works after the rejected calls
+    f = kx.fdr_curve(real, ph, 2)
+    torch.cuda.synchronize()
+    n = int(real["n_hits_t"].item())
+    assert n > 0 and np.all(np.isfinite(f[:n].cpu().numpy()))
