@@ -942,13 +942,14 @@ krux_status krux_test_grouped(krux_ctx* c, const int16_t* ranks2, const int64_t*
     int32_t* d_smp = (int32_t*)(d_off + G + 2);
     uint64_t* d_big = (uint64_t*)ws(c, S_G_QMASK, (size_t)G * 8 + (size_t)G * K + 256, &s);
     uint8_t* d_q = (uint8_t*)(d_big + G);
-    unsigned long long* cnt = (unsigned long long*)ws(c, S_G_CNT, (size_t)(G + 8) * 8, &s);
+    unsigned long long* cnt = (unsigned long long*)ws(c, S_G_CNT, 256, &s);
     if (s != KRUX_OK) return s;
-    unsigned long long* fill = cnt + 3;                // cnt: bad, stored, total
     HIP_TRY(c, hipMemcpyAsync(d_big, big.data(), (size_t)G * 8, hipMemcpyHostToDevice, st));
     HIP_TRY(c, hipMemcpyAsync(d_off, off.data(), (size_t)(G + 2) * 8, hipMemcpyHostToDevice, st));
-    HIP_TRY(c, kx_launch_fill_u64(cnt, G + 4, 0ull, st));
-    HIP_TRY(c, kx_launch_assign_parts(keys, M, d_big, G, d_off, fill, d_snps, grid, st));
+    HIP_TRY(c, kx_launch_fill_u64(cnt, 3, 0ull, st));  // bad, stored, total
+    int32_t* pid = (int32_t*)sorted;                   // the sorted keys are no longer needed
+    HIP_TRY(c, kx_group_parts(keys, M, d_big, G, pid, pid + M, (int32_t*)uniq, d_snps, gtmp, tmpb,
+                              grid, st));
     HIP_TRY(c, kx_launch_pattern_mask(geno, ld_geno, K, d_snps, d_off, G, d_q, grid, st));
     for (int gi = 0; gi < G; ++gi)
         HIP_TRY(c, kx_launch_check_pattern(geno, ld_geno, K, d_snps + off[gi],

@@ -3,6 +3,7 @@
 // matrices).  The kernels key each SNP by its pattern, check a group's
 // members against the pattern, gather the sub-problem's columns and rows,
 // and merge the sub-problems' hit lists and per-trait minima.
+#include <algorithm>
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_run_length_encode.hpp>
 #include "kx_common.h"
@@ -37,43 +38,22 @@ __global__ __launch_bounds__(256) void miss_keys(const int8_t* __restrict__ geno
 }
 
 // Part of every SNP: the index of its key among the G sorted group keys, G
-// (the ungrouped rest) when absent; each SNP is placed in its part's slice
-// of list (order within a part is arbitrary).  Lanes of a wave with the same
-// part take their places with one atomic.
-__global__ void assign_parts(const uint64_t* __restrict__ key, int64_t M,
-                             const uint64_t* __restrict__ big, int G,
-                             const int64_t* __restrict__ off, unsigned long long* fill,
-                             int32_t* __restrict__ list) {
-    const int lane = threadIdx.x & 63;
-    const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t m0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); m0 < M;
-         m0 += stride) {
-        const int64_t m = m0 + lane;
-        const bool valid = m < M;
-        int g = -1;
-        if (valid) {
-            const uint64_t k = key[m];
-            int lo = 0, hi = G;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (big[mid] < k) lo = mid + 1;
-                else hi = mid;
-            }
-            g = (k != 0 && lo < G && big[lo] == k) ? lo : G;
+// (the ungrouped rest) when absent.  A stable sort of (part, SNP) then lists
+// each part's SNPs in ascending order, the parts one after the other.
+__global__ void part_ids(const uint64_t* __restrict__ key, int64_t M,
+                         const uint64_t* __restrict__ big, int G, int32_t* __restrict__ pid,
+                         int32_t* __restrict__ idx) {
+    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < M;
+         m += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = key[m];
+        int lo = 0, hi = G;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (big[mid] < k) lo = mid + 1;
+            else hi = mid;
         }
-        unsigned long long todo = __ballot(valid);
-        while (todo) {
-            const int leader = __builtin_ctzll(todo);
-            const int gl = __shfl(g, leader, 64);
-            const unsigned long long same = __ballot(valid && g == gl);
-            unsigned long long base = 0;
-            if (lane == leader) base = atomicAdd(&fill[gl], (unsigned long long)__popcll(same));
-            base = __shfl(base, leader, 64);
-            if (valid && g == gl)
-                list[off[gl] + (int64_t)(base + __popcll(same & below))] = (int32_t)m;
-            todo &= ~same;
-        }
+        pid[m] = (k != 0 && lo < G && big[lo] == k) ? lo : G;
+        idx[m] = (int32_t)m;
     }
 }
 
@@ -184,7 +164,11 @@ extern "C" size_t kx_group_tmp_bytes(int64_t M) {
                                    (size_t)M, 0, 64);
     (void)rocprim::run_length_encode((void*)nullptr, b, (uint64_t*)nullptr, (unsigned int)M,
                                      (uint64_t*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr);
-    return a > b ? a : b;
+    size_t c = 0;
+    (void)rocprim::radix_sort_pairs((void*)nullptr, c, (const uint32_t*)nullptr,
+                                    (uint32_t*)nullptr, (const int32_t*)nullptr,
+                                    (int32_t*)nullptr, (size_t)M, 0, 31);
+    return std::max(a, std::max(b, c));
 }
 
 extern "C" hipError_t kx_group_runs(const uint64_t* key, int64_t M, uint64_t* sorted,
@@ -198,13 +182,19 @@ extern "C" hipError_t kx_group_runs(const uint64_t* key, int64_t M, uint64_t* so
                                       st);
 }
 
-extern "C" hipError_t kx_launch_assign_parts(const uint64_t* key, int64_t M, const uint64_t* big,
-                                             int G, const int64_t* off,
-                                             unsigned long long* fill, int32_t* list, int grid,
-                                             hipStream_t st) {
-    hipLaunchKernelGGL(kx::assign_parts, dim3(grid), dim3(256), 0, st, key, M, big, G, off, fill,
-                       list);
-    return hipGetLastError();
+// pid, pid_sorted, idx: M int32 each; list receives the SNPs by part.
+extern "C" hipError_t kx_group_parts(const uint64_t* key, int64_t M, const uint64_t* big, int G,
+                                     int32_t* pid, int32_t* pid_sorted, int32_t* idx,
+                                     int32_t* list, void* tmp, size_t tmp_bytes, int grid,
+                                     hipStream_t st) {
+    hipLaunchKernelGGL(kx::part_ids, dim3(grid), dim3(256), 0, st, key, M, big, G, pid, idx);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int bits = 1;
+    while (bits < 31 && (1 << bits) <= G) ++bits;
+    size_t bytes = tmp_bytes;
+    return rocprim::radix_sort_pairs(tmp, bytes, (const uint32_t*)pid, (uint32_t*)pid_sorted,
+                                     idx, list, (size_t)M, 0, bits, st);
 }
 
 extern "C" hipError_t kx_launch_pattern_mask(const int8_t* geno, int64_t ld, int K,

@@ -57,9 +57,9 @@ size_t kx_group_tmp_bytes(int64_t M);
 hipError_t kx_group_runs(const uint64_t* key, int64_t M, uint64_t* sorted, uint64_t* uniq,
                          uint32_t* counts, uint32_t* n_runs, void* tmp, size_t tmp_bytes,
                          hipStream_t st);
-hipError_t kx_launch_assign_parts(const uint64_t* key, int64_t M, const uint64_t* big, int G,
-                                  const int64_t* off, unsigned long long* fill, int32_t* list,
-                                  int grid, hipStream_t st);
+hipError_t kx_group_parts(const uint64_t* key, int64_t M, const uint64_t* big, int G,
+                          int32_t* pid, int32_t* pid_sorted, int32_t* idx, int32_t* list,
+                          void* tmp, size_t tmp_bytes, int grid, hipStream_t st);
 hipError_t kx_launch_pattern_mask(const int8_t* geno, int64_t ld, int K, const int32_t* list,
                                   const int64_t* off, int G, uint8_t* qmask, int grid,
                                   hipStream_t st);
