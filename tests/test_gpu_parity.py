@@ -458,3 +458,26 @@ def test_new_entry_points_reject_bad_arguments(kx):
     torch.cuda.synchronize()
     n = int(real["n_hits_t"].item())
     assert n > 0 and np.all(np.isfinite(f[:n].cpu().numpy()))
+
+
+def test_grouped_degenerate_cases(kx):
+    # no pattern reaches min_group, complete genotypes, a pattern that removes
+    # every sample but one, and an empty SNP panel: all equal krux_test
+    from paper_1307_3519_amd.krux import unpack_hits
+    say("grouped degenerate")
+    K, T, M = 30, 12, 120
+    x, g = _inputs(9, T, K, M)
+    g_one = g.copy()
+    g_one[:60, 1:] = -1                    # 60 SNPs keep only sample 0
+    for gg, mg in ((g, 4), (datagen.set_missing(datagen.streams(3)["missing"], g, 0.05), 1000),
+                   (g_one, 8), (g[:0], 1)):
+        r, ts = _ranks(kx, x)
+        gd = _dev(gg)
+        res = kx.test_grouped(r, ts, gd, p_c=0.05, min_group=mg, hit_capacity=4096)
+        ref = kx.test(r, ts, gd, p_c=0.05, mode="hits", hit_capacity=4096, min_p=True)
+        torch.cuda.synchronize()
+        a, b = unpack_hits(res), unpack_hits(ref)
+        assert a[0] == b[0]
+        for f in ("trait", "snp", "H", "p"):
+            assert np.array_equal(a[1][f], b[1][f]), f
+        assert np.array_equal(res["min_p"].cpu().numpy(), ref["min_p"].cpu().numpy())
