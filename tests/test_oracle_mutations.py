@@ -36,6 +36,8 @@ MUTATIONS = {
                          "if (oracle_pvalue(bitsd(mid), df) > p_c) lo = mid; else hi = mid;"),
     "perm_inverted": ("for (int k = 0; k < K; k++) xp[k] = x[perm[k]];",
                       "for (int k = 0; k < K; k++) xp[perm[k]] = x[k];"),
+    "nan_counted_in_group": ("if (gi < 0 || gi > 2 || a2[k] == 0) continue;",
+                             "if (gi < 0 || gi > 2) continue;"),
     "genotype_index_shift": ("o->n[gi] += 1;\n        o->s2[gi] += a2[k];",
                              "o->n[gi] += 1;\n        o->s2[(gi + 1) % 3] += a2[k];"),
 }
@@ -52,6 +54,7 @@ BATTERY = [
     pins.test_degenerate_cases,
     pins.test_invariants,
     pins.test_missing_genotype_equals_kept_samples,
+    pins.test_missing_expression_equals_kept_samples,
     pins.test_rational_to_double_matches_fraction,
     pins.test_scan_permutation_is_column_permutation_of_ranks,
 ]
@@ -77,4 +80,42 @@ def test_planted_mistake_is_caught(name, tmp_path):
                 caught.append(t.__name__)
     finally:
         oracle.use_library(None)
+    assert caught, "mutation %s passed every pin" % name
+
+
+# The FDR curve is plain Python in the oracle package: planted mistakes are
+# substituted for it directly and must each fail one of its pins.
+def _fdr_mutant(name):
+    import numpy as np
+
+    def f(real_p, perm_p, P, at=None):
+        real_p = np.asarray(real_p, np.float64)
+        perm_p = np.asarray(perm_p, np.float64)
+        at = real_p if at is None else np.asarray(at, np.float64)
+        out = np.empty(len(at))
+        for i, q in enumerate(at):
+            n_perm = int(np.count_nonzero(perm_p < q if name == "perm_strict" else perm_p <= q))
+            n_real = int(np.count_nonzero(real_p < q if name == "real_strict" else real_p <= q))
+            if name == "real_total":
+                n_real = len(real_p)
+            scale = 1.0 if name == "no_mean_over_perms" else float(P)
+            out[i] = n_perm / (scale * float(n_real)) if n_real else float("nan")
+        return out
+    return f
+
+
+FDR_BATTERY = [pins.test_fdr_curve_worked_example,
+               pins.test_fdr_curve_is_mean_of_per_permutation_ratios]
+
+
+@pytest.mark.parametrize("name", ["perm_strict", "real_strict", "real_total",
+                                  "no_mean_over_perms"])
+def test_planted_fdr_mistake_is_caught(name, monkeypatch):
+    monkeypatch.setattr(oracle, "fdr_curve", _fdr_mutant(name))
+    caught = []
+    for t in FDR_BATTERY:
+        try:
+            t()
+        except (AssertionError, ValueError, ZeroDivisionError):
+            caught.append(t.__name__)
     assert caught, "mutation %s passed every pin" % name
