@@ -1,0 +1,102 @@
+"""Pins for the multi-allelic oracle (oracle/multi.py): facts fixed by the
+mathematics, independent of its code.
+
+  scipy        scipy.stats.kruskal with 4-6 groups; scipy.stats.chi2.sf
+  C oracle     two alleles (classes 0..2): the same H as the C oracle
+  brute force  the exact permutation-null mean E[H] = df for 4 groups
+  threshold    the largest double with p >= p_c; the C oracle's for df 1, 2
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+import scipy.stats as st
+
+import oracle
+from oracle import multi
+from paper_1307_3519_amd import datagen
+
+
+def test_chi2_tail_matches_scipy():
+    for df in range(1, 9):
+        for H in (0.0, 1e-6, 0.3, 1.0, 2.5, 7.0, 15.0, 40.0, 90.0, 200.0):
+            want = st.chi2.sf(H, df)
+            got = multi.chi2_tail(H, df)
+            assert got == pytest.approx(want, rel=1e-12, abs=1e-300), (df, H)
+
+
+def test_threshold_is_largest_double_with_p_at_least_pc():
+    for df in (1, 2, 3, 4, 5, 7):
+        for pc in (0.5, 1e-3, 1e-5, 1e-8):
+            h = multi.threshold(pc, df)
+            assert multi.chi2_tail(h, df) >= pc
+            assert multi.chi2_tail(math.nextafter(h, math.inf), df) < pc
+    for df in (1, 2):
+        for pc in (0.3, 1e-4, 1e-6):
+            assert multi.threshold(pc, df) == pytest.approx(oracle.threshold(pc, df), rel=1e-15)
+
+
+def test_two_alleles_equal_the_c_oracle():
+    rs = datagen.streams(23)
+    K = 45
+    x = datagen.inject_ties(rs["ties"], datagen.to_expression(
+        datagen.log_normal_z(rs["expr"], 25, K)), 0.1)
+    g, _ = datagen.genotypes(rs["geno"], 25, K)
+    g = datagen.set_missing(rs["missing"], g, 0.05)
+    x[rs["missing"].random(x.shape) < 0.03] = np.nan
+    for t in range(25):
+        o = oracle.one_pair(x[t], g[t])
+        m = multi.one_pair(x[t], g[t], 3)
+        assert m["H"] == o["H"] and m["df"] == o["df"] and m["tiesum"] == o["tiesum"]
+        assert list(m["s2"]) == list(o["s2"])
+        assert m["p"] == pytest.approx(o["p"], rel=1e-14, abs=1e-300)
+
+
+@pytest.mark.parametrize("G", [4, 5, 6])
+def test_vs_scipy_kruskal(G):
+    rng = np.random.default_rng(G)
+    K = 60
+    for _ in range(20):
+        x = np.round(rng.lognormal(size=K), 1).astype(np.float32)     # ties
+        g = rng.integers(0, G, size=K)
+        g[rng.random(K) < 0.05] = G + 2                               # missing codes
+        x[rng.random(K) < 0.03] = np.nan
+        keep = (~np.isnan(x)) & (g < G)
+        groups = [x[keep & (g == c)].astype(np.float64) for c in range(G)]
+        groups = [q for q in groups if len(q)]
+        o = multi.one_pair(x, g, G)
+        assert o["df"] == len(groups) - 1
+        r = st.kruskal(*groups)
+        assert o["H"] == pytest.approx(r.statistic, rel=1e-10)
+        assert o["p"] == pytest.approx(r.pvalue, rel=1e-9, abs=1e-300)
+
+
+def test_permutation_null_mean_is_df():
+    # 7 distinct values in 4 groups of sizes (2, 2, 2, 1): over all 630
+    # assignments of samples to groups, the mean of H is exactly df = 3
+    x = np.array([0.3, 1.1, 2.0, 2.7, 3.5, 4.2, 5.9], np.float32)
+    labels = [0, 0, 1, 1, 2, 2, 3]
+    Hs = set()
+    total, count = 0.0, 0
+    for perm in set(itertools.permutations(labels)):
+        o = multi.one_pair(x, np.array(perm), 4)
+        total += o["H"]
+        count += 1
+        Hs.add(o["H"])
+    assert count == 630 and len(Hs) > 10
+    assert total / count == pytest.approx(3.0, rel=1e-12)
+
+
+def test_perfect_separation_closed_form():
+    # G groups of n samples each, ordered: H = 3(K-1)/(K^3-K) * sum D_c^2/n
+    # with D_c = n (2 c n + n + 1) - n (K + 1) in doubled ranks
+    for G, n in ((4, 3), (5, 2), (6, 4)):
+        K = G * n
+        x = np.arange(K, dtype=np.float32)
+        g = np.repeat(np.arange(G), n)
+        o = multi.one_pair(x, g, G)
+        D = [n * (2 * c * n + n + 1) - n * (K + 1) for c in range(G)]
+        want = 3 * (K - 1) * sum(d * d / n for d in D) / (K ** 3 - K)
+        assert o["H"] == pytest.approx(want, rel=1e-14)
+        assert o["df"] == G - 1
