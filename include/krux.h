@@ -154,6 +154,26 @@ krux_status krux_test_grouped(krux_ctx* ctx, const int16_t* ranks2, const int64_
                               int64_t min_group, krux_hit* hits, int64_t hit_capacity,
                               int64_t* n_hits, double* min_p, void* stream);
 
+/* Multi-allelic markers (Input data: genotype values 0..l; Calculation of
+ * the Kruskal-Wallis test statistic, eq. (2), over l + 1 groups; P-value
+ * calculation for df up to l).  Genotype codes 0..n_classes-1 are classes,
+ * any other code is missing (the sample is removed from the pair and the
+ * ranks recomputed, as in krux_test); a 0 rank is a missing expression value.
+ * df = non-empty classes - 1, p = the chi-square tail at df.  H is computed
+ * in double from exact integer group sums (relative error a few ulp, not the
+ * once-rounded rational of krux_test).  No GEMM: one GPU lane per pair.
+ *   n_classes  2..8 (l + 1); K <= 4096.
+ *   mode       KRUX_MODE_HITS: hits (sorted by (trait, snp)) with
+ *              H > H_c(df), the largest double whose chi-square tail at df is
+ *              >= p_c; *n_hits the true count.  KRUX_MODE_FULL: H and p
+ *              (device, T x M doubles).
+ * Other arguments as krux_test; unused outputs may be NULL. */
+krux_status krux_test_multi(krux_ctx* ctx, const int16_t* ranks2, const int64_t* tiesum,
+                            int64_t T, int32_t K, const int8_t* geno, int64_t M, int64_t ld_geno,
+                            int32_t n_classes, int64_t snp_base, double p_c, int32_t mode,
+                            krux_hit* hits, int64_t hit_capacity, int64_t* n_hits, double* H,
+                            double* p, void* stream);
+
 /* Permuted-data repeats for the empirical FDR (P-value calculation and
  * empirical FDR correction): for each permutation pi (perms, P x K int32,
  * each a permutation of 0..K-1) the rank matrix columns are permuted, the

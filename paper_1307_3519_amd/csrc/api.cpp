@@ -1021,6 +1021,105 @@ krux_status krux_test_grouped(krux_ctx* c, const int16_t* ranks2, const int64_t*
     return KRUX_OK;
 }
 
+namespace {
+
+// Upper chi-square tail for any df on the host (the closed forms of
+// Q(df/2, H/2), as in the multi-allelic kernel), and its threshold on H.
+double host_chi2_upper(double H, int df) {
+    if (df <= 0) return 1.0;
+    const double x = 0.5 * H;
+    if (df % 2 == 0) {
+        double term = 1.0, total = 1.0;
+        for (int k = 1; k < df / 2; ++k) {
+            term *= x / k;
+            total += term;
+        }
+        return std::exp(-x) * total;
+    }
+    double total = std::erfc(std::sqrt(x));
+    if (df > 1) {
+        double term = std::sqrt(x) / 0.88622692545275801365;   // Gamma(3/2)
+        double sum = term;
+        for (int k = 2; k <= (df - 1) / 2; ++k) {
+            term *= x / (k - 0.5);
+            sum += term;
+        }
+        total += std::exp(-x) * sum;
+    }
+    return total;
+}
+
+double threshold_any_df(double p_c, int df) {
+    uint64_t lo, hi;
+    double d0 = 0.0, d1 = 8192.0;
+    std::memcpy(&lo, &d0, 8);
+    std::memcpy(&hi, &d1, 8);
+    while (hi - lo > 1) {
+        uint64_t mid = lo + (hi - lo) / 2;
+        double h;
+        std::memcpy(&h, &mid, 8);
+        if (host_chi2_upper(h, df) >= p_c) lo = mid; else hi = mid;
+    }
+    double r;
+    std::memcpy(&r, &lo, 8);
+    return r;
+}
+
+}  // namespace
+
+// Multi-allelic markers: classes 0..n_classes-1, exact per pair on the GPU
+// without the GEMM (HITS or FULL).
+krux_status krux_test_multi(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum, int64_t T,
+                            int32_t K, const int8_t* geno, int64_t M, int64_t ld_geno,
+                            int32_t n_classes, int64_t snp_base, double p_c, int32_t mode,
+                            krux_hit* hits, int64_t hit_capacity, int64_t* n_hits, double* H,
+                            double* p, void* stream) {
+    if (!c) return fail(nullptr, KRUX_ERR_ARG, "ctx is NULL");
+    krux_status s = check_ranks(c, ranks2, tiesum, T, K);
+    if (s != KRUX_OK) return s;
+    if ((s = check_geno(c, geno, M, ld_geno, K)) != KRUX_OK) return s;
+    if (K > 4096) return fail(c, KRUX_ERR_UNSUPPORTED, "K = %d above 4096", K);
+    if (n_classes < 2 || n_classes > kx::kMaxClasses)
+        return fail(c, KRUX_ERR_ARG, "n_classes = %d not in [2, %d]", n_classes, kx::kMaxClasses);
+    if (mode != KRUX_MODE_HITS && mode != KRUX_MODE_FULL)
+        return fail(c, KRUX_ERR_ARG, "mode %d (HITS or FULL)", mode);
+    hipStream_t st = (hipStream_t)stream;
+    kx::MultiArgs a{};
+    a.ranks2 = ranks2; a.tiesum = tiesum; a.T = T; a.K = K; a.geno = geno; a.ld = ld_geno;
+    a.M = M; a.snp_base = snp_base;
+    if (mode == KRUX_MODE_HITS) {
+        if (!valid_p(p_c)) return fail(c, KRUX_ERR_ARG, "p_c = %g not in (0, 1]", p_c);
+        if (!n_hits) return fail(c, KRUX_ERR_ARG, "n_hits is NULL");
+        if (hit_capacity < 0 || (hit_capacity > 0 && !hits))
+            return fail(c, KRUX_ERR_ARG, "hits / hit_capacity");
+        if (hit_capacity > (int64_t)UINT32_MAX)
+            return fail(c, KRUX_ERR_ARG, "hit_capacity too large");
+        for (int df = 1; df < n_classes; ++df) a.hc[df] = threshold_any_df(p_c, df);
+    } else if (T * M > 0 && (!H || !p)) {
+        return fail(c, KRUX_ERR_ARG, "H / p is NULL");
+    }
+    HIP_TRY(c, hipSetDevice(c->device));
+    kx::HitRec* stage = nullptr;
+    unsigned long long* nh = nullptr;
+    if (mode == KRUX_MODE_HITS) {
+        stage = (kx::HitRec*)ws(c, S_STAGE, (size_t)std::max<int64_t>(hit_capacity, 1) * 24, &s);
+        nh = (unsigned long long*)ws(c, S_NHITS, 256, &s);
+        if (s != KRUX_OK) return s;
+        HIP_TRY(c, kx_launch_fill_u64(nh, 1, 0ull, st));
+        a.hits = stage; a.hit_cap = hit_capacity; a.n_hits = nh;
+    } else {
+        a.H_out = H; a.p_out = p;
+    }
+    if (T > 0 && M > 0) {
+        const int64_t items = T * ((M + 63) / 64);
+        const int grid = (int)std::min<int64_t>((items + 3) / 4, (int64_t)c->n_cu * 8);
+        HIP_TRY(c, kx_launch_multi(&a, n_classes, mode == KRUX_MODE_FULL ? kx::FULL : kx::SCREEN,
+                                   grid, st));
+    }
+    if (mode == KRUX_MODE_HITS) return sort_stage(c, stage, nh, hit_capacity, hits, n_hits, T, st);
+    return KRUX_OK;
+}
+
 krux_status krux_test_batched(krux_ctx* c, const krux_cohort* co, int32_t n, int64_t M,
                               double p_c, int32_t precision, void* stream) {
     if (!c) return fail(nullptr, KRUX_ERR_ARG, "ctx is NULL");

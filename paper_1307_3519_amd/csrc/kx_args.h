@@ -83,6 +83,25 @@ struct ScanArgs {
     unsigned long long* n_mcand;
 };
 
+// Multi-allelic scan (classes 0..n_classes-1, at most kMaxClasses).
+constexpr int kMaxClasses = 8;
+struct MultiArgs {
+    const int16_t* ranks2;   // T x K doubled midranks, 0 = missing value
+    const int64_t* tiesum;   // T
+    int64_t T;
+    int K;
+    const int8_t* geno;      // M x K codes, row stride ld
+    int64_t ld;
+    int64_t M;
+    double hc[kMaxClasses];  // hc[df]: threshold on H at df (hits)
+    HitRec* hits;
+    int64_t hit_cap;
+    unsigned long long* n_hits;
+    int64_t snp_base;
+    double* H_out;           // full mode: T x M
+    double* p_out;
+};
+
 // Extra operands of the tiled large-K kernels.
 struct TiledArgs {
     const void* Bf;      // [snp tiles][ks][NC][64] fragments

@@ -12,6 +12,7 @@ namespace kx {
 struct PrepArgs;
 struct ScanArgs;
 struct TiledArgs;
+struct MultiArgs;
 }
 
 extern "C" {
@@ -78,6 +79,8 @@ hipError_t kx_launch_min_merge(const double* part, double* acc, int64_t n, int g
                                hipStream_t st);
 hipError_t kx_launch_set_counts(int64_t* n_out, const unsigned long long* total,
                                 unsigned long long* stored, int64_t cap, hipStream_t st);
+hipError_t kx_launch_multi(const kx::MultiArgs* a, int n_classes, int mode, int grid,
+                           hipStream_t st);
 size_t kx_sort_keys_tmp_bytes(int64_t cap);
 hipError_t kx_fdr_curve(const kx::HitRec* real, const int64_t* n_real, int64_t real_cap,
                         const kx::HitRec* perm, const int64_t* n_perm, int64_t perm_cap, int P,

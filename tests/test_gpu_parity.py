@@ -481,3 +481,40 @@ def test_grouped_degenerate_cases(kx):
         for f in ("trait", "snp", "H", "p"):
             assert np.array_equal(a[1][f], b[1][f]), f
         assert np.array_equal(res["min_p"].cpu().numpy(), ref["min_p"].cpu().numpy())
+
+
+# ---------------------------------------------------------------- multi-allelic markers
+MULTI_CASES = [  # (K, T, M, n_classes)
+    (40, 8, 70, 4),
+    (37, 6, 65, 6),
+    (150, 5, 30, 5),
+    (30, 5, 40, 8),
+]
+
+
+@pytest.mark.parametrize("K,T,M,G", MULTI_CASES)
+def test_multi_allelic(kx, K, T, M, G):
+    from oracle import multi
+    from paper_1307_3519_amd.krux import unpack_hits
+    say("multi", K, T, M, G)
+    rng = np.random.default_rng(K * 100 + G)
+    x = np.round(rng.lognormal(size=(T, K)), 1).astype(np.float32)      # ties
+    x[rng.random(x.shape) < 0.03] = np.nan
+    x[0, :] = np.nan
+    q = rng.dirichlet(np.ones(G), size=M)
+    g = np.array([rng.choice(G, size=K, p=q[m]) for m in range(M)], dtype=np.int8)
+    g[rng.random(g.shape) < 0.03] = -1
+    g[rng.random(g.shape) < 0.01] = G + 1                                # also missing
+    g[1, :] = 0                                                          # one class only
+    r, ts = _ranks(kx, x)
+    gd = _dev(g)
+    p_c = 0.05
+    o = multi.scan(x, g, G, p_c=p_c)
+    full = kx.test_multi(r, ts, gd, G, mode="full")
+    res = kx.test_multi(r, ts, gd, G, p_c=p_c, mode="hits", hit_capacity=4096, snp_base=3)
+    torch.cuda.synchronize()
+    assert_H(full["H"].cpu().numpy(), o["H"], "multi H")
+    assert_p(full["p"].cpu().numpy(), o["p"], "multi p")
+    n, h = unpack_hits(res)
+    assert n == len(o["hits"]) and n > 0
+    assert list(zip(h["trait"].tolist(), (h["snp"] - 3).tolist())) == o["hits"]
