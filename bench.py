@@ -27,6 +27,9 @@ Workloads (--workload; seeded synthetic data shaped like the paper's
   sample_missing   the paper-scale workload with sample-structured missing
       genotypes (samples 5 and 40 missing in 90% of the SNPs, sample 77 in
       30%); the pattern-grouped scan timed beside the per-pair path
+  multi_allelic    K=102, 20,000 traits, 50,000 markers with 4 genotype classes
+      (class frequencies Dirichlet(1) per marker); hits at p < 1e-5 through
+      the lane-per-pair multi-allelic kernel
   missing_expression  the paper-scale workload with NaN expression values in
       2% of the traits (1-5 each); hits at p < 1e-5 plus the per-trait minimum
       p, timed beside the same traits without NaN values
@@ -542,9 +545,64 @@ def sample_missing(args, ctx, torch, np, datagen, krux):
     return out
 
 
+def multi_allelic(args, ctx, torch, np, datagen, krux):
+    K, G = 102, 4
+    T = args.T or 20000
+    M = args.M or 50000
+    p_c = 1e-5
+    log("generating workload K=%d T=%d M=%d, %d genotype classes" % (K, T, M, G))
+    w = datagen.make_workload(2, T=T, M=1)
+    rng = np.random.default_rng(7)
+    q = rng.dirichlet(np.ones(G), size=M)
+    u = rng.random((M, K))
+    g_np = (u[:, :, None] > np.cumsum(q, axis=1)[:, None, :]).sum(axis=2).astype(np.int8)
+    x = torch.from_numpy(w["expr"]).cuda()
+    g = torch.from_numpy(g_np).cuda()
+    runner = Runner(ctx, torch)
+    steps = max(1, min(args.steps, 5))
+
+    def step():
+        r, ts, _ = ctx.rank(x)
+        return ctx.test_multi(r, ts, g, G, p_c=p_c, mode="hits", hit_capacity=1 << 17)
+
+    log("multi-allelic: 1 warmup + %d timed steps" % steps)
+    ms, res, _, _ = runner.run(step, steps, 1)
+    n_hits = krux.unpack_hits(res)[0]
+    pairs = float(T) * float(M)
+    log("multi-allelic: %.2f ms/step, %.3e pairs/s, hits %d" % (ms, pairs / (ms / 1e3), n_hits))
+    out = base_line(args, "SNP-trait pairs/sec, multi-allelic markers", pairs / (ms / 1e3),
+                    "pairs/s", ms, "int32/f64", {
+                        "workload": "multi_allelic", "K": K, "T": T, "M": M, "classes": G,
+                        "p_c": p_c, "outputs": "sorted hit list"})
+    out["steps"], out["warmup"] = steps, 1
+    out["n_hits"] = n_hits
+    # VALU-bound lane kernel: about 3 G + 3 integer operations per sample and pair
+    ops = pairs * K * (3 * G + 3)
+    kern_ms = ms
+    out["roofline"] = {"bound": "alu", "kernel": "scan_multi<4, SCREEN>",
+                       "achieved": ops / (kern_ms / 1e3) / 1e12,
+                       "peak": 256 * 4 * 16 * 2.4e9 / 1e12, "unit": "Tops/s (int32 lane ops)",
+                       "frac": ops / (kern_ms / 1e3) / (256 * 4 * 16 * 2.4e9),
+                       "traffic": None, "note": "step time used for the kernel time"}
+    if not args.no_cpu:
+        from oracle import multi
+        t0 = time.perf_counter()
+        n_snp, Tn = 0, min(T, 20)
+        while time.perf_counter() - t0 < args.cpu_seconds and n_snp < M:
+            multi.scan(w["expr"][:Tn], g_np[n_snp:n_snp + 5], G, p_c=p_c)
+            n_snp += 5
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": Tn * n_snp / dt, "unit": "pairs/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": "%d traits x the first %d SNPs (multi-allelic Python "
+                                         "oracle, exact rationals), %.1f s" % (Tn, n_snp, dt)}
+    return out
+
+
 WORKLOADS = {"paper_scale_hits": paper_scale_hits, "precision_K500": precision_k500,
              "permutations": permutations, "cohorts_missing": cohorts_missing,
-             "missing_expression": missing_expression, "sample_missing": sample_missing}
+             "missing_expression": missing_expression, "sample_missing": sample_missing,
+             "multi_allelic": multi_allelic}
 
 
 def main():
