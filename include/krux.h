@@ -162,7 +162,7 @@ krux_status krux_test_grouped(krux_ctx* ctx, const int16_t* ranks2, const int64_
  * df = non-empty classes - 1, p = the chi-square tail at df.  H is computed
  * in double from exact integer group sums (relative error a few ulp, not the
  * once-rounded rational of krux_test).  No GEMM: one GPU lane per pair.
- *   n_classes  2..8 (l + 1); K <= 4096.
+ *   n_classes  2..8 (l + 1); K <= 2048.
  *   mode       KRUX_MODE_HITS: hits (sorted by (trait, snp)) with
  *              H > H_c(df), the largest double whose chi-square tail at df is
  *              >= p_c; *n_hits the true count.  KRUX_MODE_FULL: H and p

@@ -1078,15 +1078,15 @@ krux_status krux_test_multi(krux_ctx* c, const int16_t* ranks2, const int64_t* t
     krux_status s = check_ranks(c, ranks2, tiesum, T, K);
     if (s != KRUX_OK) return s;
     if ((s = check_geno(c, geno, M, ld_geno, K)) != KRUX_OK) return s;
-    if (K > 4096) return fail(c, KRUX_ERR_UNSUPPORTED, "K = %d above 4096", K);
+    if (K > 2048) return fail(c, KRUX_ERR_UNSUPPORTED, "K = %d above 2048", K);
     if (n_classes < 2 || n_classes > kx::kMaxClasses)
         return fail(c, KRUX_ERR_ARG, "n_classes = %d not in [2, %d]", n_classes, kx::kMaxClasses);
     if (mode != KRUX_MODE_HITS && mode != KRUX_MODE_FULL)
         return fail(c, KRUX_ERR_ARG, "mode %d (HITS or FULL)", mode);
     hipStream_t st = (hipStream_t)stream;
     kx::MultiArgs a{};
-    a.ranks2 = ranks2; a.tiesum = tiesum; a.T = T; a.K = K; a.geno = geno; a.ld = ld_geno;
-    a.M = M; a.snp_base = snp_base;
+    a.ranks2 = ranks2; a.tiesum = tiesum; a.T = T; a.K = K; a.M = M; a.snp_base = snp_base;
+    a.pstride = (K + 15) & ~15;
     if (mode == KRUX_MODE_HITS) {
         if (!valid_p(p_c)) return fail(c, KRUX_ERR_ARG, "p_c = %g not in (0, 1]", p_c);
         if (!n_hits) return fail(c, KRUX_ERR_ARG, "n_hits is NULL");
@@ -1111,6 +1111,11 @@ krux_status krux_test_multi(krux_ctx* c, const int16_t* ranks2, const int64_t* t
         a.H_out = H; a.p_out = p;
     }
     if (T > 0 && M > 0) {
+        uint8_t* packed = (uint8_t*)ws(c, S_G_GENO, (size_t)M * a.pstride, &s);
+        if (s != KRUX_OK) return s;
+        HIP_TRY(c, kx_launch_multi_pack(geno, ld_geno, M, K, n_classes, a.pstride, packed,
+                                        c->n_cu * 8, st));
+        a.packed = packed;
         const int64_t items = T * ((M + 63) / 64);
         const int grid = (int)std::min<int64_t>((items + 3) / 4, (int64_t)c->n_cu * 8);
         HIP_TRY(c, kx_launch_multi(&a, n_classes, mode == KRUX_MODE_FULL ? kx::FULL : kx::SCREEN,

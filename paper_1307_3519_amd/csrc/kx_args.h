@@ -90,8 +90,8 @@ struct MultiArgs {
     const int64_t* tiesum;   // T
     int64_t T;
     int K;
-    const int8_t* geno;      // M x K codes, row stride ld
-    int64_t ld;
+    const uint8_t* packed;   // M rows of pstride bytes: class 0..G-1, else 0xFF
+    int pstride;             // a multiple of 16, >= K
     int64_t M;
     double hc[kMaxClasses];  // hc[df]: threshold on H at df (hits)
     HitRec* hits;

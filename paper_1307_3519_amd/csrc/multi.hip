@@ -38,16 +38,40 @@ __device__ inline double chi2_upper(double H, int df) {
     return total;
 }
 
-__device__ inline bool multi_missing(int code, int G) { return code < 0 || code >= G; }
+// Genotype rows copied to a 16-byte-aligned stride, classes 0..G-1 kept and
+// every other code (and the padding past K) set to 0xFF.
+__global__ void multi_pack(const int8_t* __restrict__ geno, int64_t ld, int64_t M, int K, int G,
+                           int stride, uint8_t* __restrict__ out) {
+    const int64_t n = M * stride;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t m = i / stride;
+        const int k = (int)(i - m * stride);
+        const int code = k < K ? geno[m * ld + k] : -1;
+        out[i] = (code >= 0 && code < G) ? (uint8_t)code : (uint8_t)0xFF;
+    }
+}
+
+// bytes of w equal to the byte value in v (v replicated) -> 1, else 0
+__device__ inline uint32_t eq_bytes(uint32_t w, uint32_t v) {
+    const uint32_t x = w ^ v;
+    return (~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u) >> 7;
+}
 
 template <int G, int MODE>
 __global__ __launch_bounds__(256) void scan_multi(MultiArgs a) {
-    extern __shared__ __attribute__((aligned(16))) int16_t s_rk[];
+    extern __shared__ __attribute__((aligned(16))) uint32_t s_words[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int K = a.K;
-    const int K16 = (K + 15) & ~15;
-    int16_t* srk = s_rk + wave * K16;
+    const int KW = ((K + 15) & ~15) >> 2;          // words of four samples, a multiple of 4
+    // per wave: low rank bytes, high rank bytes, observed flags (KW words
+    // each), then the ranks as int16 (4 KW)
+    uint32_t* slo = s_words + (size_t)wave * 5 * KW;
+    uint32_t* shi = slo + KW;
+    uint32_t* sob = shi + KW;
+    int16_t* srk = (int16_t*)(sob + KW);
+    const bool wide = 2 * K > 255;
     const int64_t nb = (a.M + kWave - 1) / kWave;
     const int64_t items = a.T * nb;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
@@ -55,38 +79,65 @@ __global__ __launch_bounds__(256) void scan_multi(MultiArgs a) {
         const int64_t trait = it / nb;
         const int64_t blk = it - trait * nb;
         int kobs = 0;
-        for (int k = lane; k < K16; k += kWave) {
-            const int16_t ak = k < K ? a.ranks2[trait * K + k] : (int16_t)0;
-            srk[k] = ak;
-            kobs += ak != 0;
+        for (int i = lane; i < KW; i += kWave) {
+            uint32_t lo = 0, hi = 0, ob = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int k = 4 * i + b;
+                const int ak = k < K ? (int)a.ranks2[trait * K + k] : 0;
+                lo |= (uint32_t)(ak & 0xFF) << (8 * b);
+                hi |= (uint32_t)(ak >> 8) << (8 * b);
+                ob |= (uint32_t)(ak != 0) << (8 * b);
+                kobs += ak != 0;
+                srk[k] = (int16_t)ak;
+            }
+            slo[i] = lo;
+            shi[i] = hi;
+            sob[i] = ob;
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) kobs += __shfl_xor(kobs, o, 64);
         __builtin_amdgcn_wave_barrier();
         const int64_t m = blk * kWave + lane;
         if (m < a.M) {
-            const int8_t* row = a.geno + m * a.ld;
-            int64_t s[G];
-            int n[G];
+            const uint8_t* row = a.packed + m * (int64_t)a.pstride;
+            uint32_t sl[G], sh[G], n[G];
 #pragma unroll
-            for (int c = 0; c < G; ++c) { s[c] = 0; n[c] = 0; }
-            int nq = 0;
-            for (int k = 0; k < K; ++k) {
-                const int code = row[k];
-                const int ak = srk[k];
+            for (int c = 0; c < G; ++c) { sl[c] = 0; sh[c] = 0; n[c] = 0; }
+            uint32_t nq = 0;
+            for (int i0 = 0; i0 < KW; i0 += 4) {
+                const uint4 g4 = *(const uint4*)(row + 4 * i0);
+                const uint4 l4 = *(const uint4*)(slo + i0);
+                const uint4 o4 = *(const uint4*)(sob + i0);
+                const uint4 h4 = wide ? *(const uint4*)(shi + i0) : make_uint4(0, 0, 0, 0);
+                const uint32_t gw[4] = {g4.x, g4.y, g4.z, g4.w};
+                const uint32_t lw[4] = {l4.x, l4.y, l4.z, l4.w};
+                const uint32_t ow[4] = {o4.x, o4.y, o4.z, o4.w};
+                const uint32_t hw[4] = {h4.x, h4.y, h4.z, h4.w};
 #pragma unroll
-                for (int c = 0; c < G; ++c)
-                    if (code == c) { s[c] += ak; n[c] += ak != 0; }
-                nq += multi_missing(code, G) && ak != 0;
+                for (int j = 0; j < 4; ++j) {
+#pragma unroll
+                    for (int c = 0; c < G; ++c) {
+                        const uint32_t ind = eq_bytes(gw[j], 0x01010101u * (uint32_t)c);
+                        sl[c] = __builtin_amdgcn_udot4(ind, lw[j], sl[c], false);
+                        n[c] = __builtin_amdgcn_udot4(ind, ow[j], n[c], false);
+                        if (wide) sh[c] = __builtin_amdgcn_udot4(ind, hw[j], sh[c], false);
+                    }
+                    nq = __builtin_amdgcn_udot4(eq_bytes(gw[j], 0xFFFFFFFFu), ow[j], nq, false);
+                }
             }
-            // removed samples, in sample order: each lowers every kept
-            // doubled rank above its own by 2 and every tied one by 1, and
-            // its tie group (current size t) loses 3 t (t - 1) of the tie term
+            int64_t s[G];
+#pragma unroll
+            for (int c = 0; c < G; ++c) s[c] = (int64_t)sl[c] + ((int64_t)sh[c] << 8);
+            // removed samples (K' counts only the kept ones), in sample
+            // order: each lowers every kept doubled rank above its own by 2
+            // and every tied one by 1, and its tie group (current size t)
+            // loses 3 t (t - 1) of the tie term.  Samples past K read rank 0.
             int64_t ts = a.tiesum[trait];
             if (nq > 0) {
                 for (int j = 0; j < K; ++j) {
                     const int aj = srk[j];
-                    if (!(multi_missing(row[j], G) && aj != 0)) continue;
+                    if (!(row[j] == 0xFF && aj != 0)) continue;
                     int e = 0, before = 0;
                     for (int k = 0; k < K; ++k) {
                         const int code = row[k];
@@ -96,13 +147,13 @@ __global__ __launch_bounds__(256) void scan_multi(MultiArgs a) {
                         for (int c = 0; c < G; ++c)
                             if (code == c) s[c] -= f;
                         e += ak == aj;
-                        before += k < j && ak == aj && multi_missing(code, G);
+                        before += k < j && ak == aj && code == 0xFF;
                     }
                     const int64_t t = e - before;
                     ts -= 3 * t * (t - 1);
                 }
             }
-            const int64_t kp = kobs - nq;
+            const int64_t kp = kobs - (int64_t)nq;
             int ne = 0;
 #pragma unroll
             for (int c = 0; c < G; ++c) ne += n[c] > 0;
@@ -142,7 +193,7 @@ __global__ __launch_bounds__(256) void scan_multi(MultiArgs a) {
 
 template <int G>
 hipError_t launch_multi_g(const MultiArgs& a, int mode, int grid, hipStream_t st) {
-    const size_t lds = (size_t)4 * ((a.K + 15) & ~15) * sizeof(int16_t);
+    const size_t lds = (size_t)4 * 5 * (((a.K + 15) & ~15) >> 2) * sizeof(uint32_t);
     if (mode == FULL)
         hipLaunchKernelGGL((scan_multi<G, FULL>), dim3(grid), dim3(256), lds, st, a);
     else
@@ -151,6 +202,15 @@ hipError_t launch_multi_g(const MultiArgs& a, int mode, int grid, hipStream_t st
 }
 
 }  // namespace kx
+
+extern "C" hipError_t kx_launch_multi_pack(const int8_t* geno, int64_t ld, int64_t M, int K,
+                                           int G, int stride, uint8_t* out, int grid,
+                                           hipStream_t st) {
+    if (M * stride <= 0) return hipSuccess;
+    hipLaunchKernelGGL(kx::multi_pack, dim3(grid), dim3(256), 0, st, geno, ld, M, K, G, stride,
+                       out);
+    return hipGetLastError();
+}
 
 extern "C" hipError_t kx_launch_multi(const kx::MultiArgs* a, int n_classes, int mode, int grid,
                                       hipStream_t st) {
