@@ -100,3 +100,44 @@ def test_perfect_separation_closed_form():
         want = 3 * (K - 1) * sum(d * d / n for d in D) / (K ** 3 - K)
         assert o["H"] == pytest.approx(want, rel=1e-14)
         assert o["df"] == G - 1
+
+
+# Planted mistakes in the multi-allelic oracle must each fail one of the pins
+# above (the source is edited in memory and loaded as a separate module).
+MULTI_MUTATIONS = {
+    "drop_tie_term": ("E = kp ** 3 - kp - tiesum", "E = kp ** 3 - kp"),
+    "wrong_centre": ("(s2[c] - n[c] * (kp + 1)) ** 2", "(s2[c] - n[c] * kp) ** 2"),
+    "df_off_by_one": ("df = nonempty - 1 if nonempty > 0 else 0", "df = nonempty if nonempty > 0 else 0"),
+    "odd_tail_no_erfc": ("total = math.erfc(math.sqrt(x))", "total = 0.0"),
+    "even_tail_sum_short": ("for k in range(1, df // 2):", "for k in range(1, df // 2 - 1):"),
+    "missing_code_kept": ("0 <= int(g[k]) < n_classes", "int(g[k]) < n_classes"),
+}
+
+MULTI_BATTERY = ["test_chi2_tail_matches_scipy", "test_threshold_is_largest_double_with_p_at_least_pc",
+                 "test_two_alleles_equal_the_c_oracle", "test_vs_scipy_kruskal",
+                 "test_permutation_null_mean_is_df", "test_perfect_separation_closed_form"]
+
+
+@pytest.mark.parametrize("name", sorted(MULTI_MUTATIONS))
+def test_planted_multi_mistake_is_caught(name, monkeypatch):
+    import types
+    old, new = MULTI_MUTATIONS[name]
+    src = open(multi.__file__).read()
+    assert src.count(old) == 1, name
+    mod = types.ModuleType("multi_mutant")
+    exec(compile(src.replace(old, new), "multi_mutant", "exec"), mod.__dict__)
+    monkeypatch.setattr(__import__("oracle").multi, "chi2_tail", mod.chi2_tail)
+    monkeypatch.setattr(__import__("oracle").multi, "threshold", mod.threshold)
+    monkeypatch.setattr(__import__("oracle").multi, "one_pair", mod.one_pair)
+    caught = []
+    for t in MULTI_BATTERY:
+        fn = globals()[t]
+        try:
+            if t == "test_vs_scipy_kruskal":
+                for G in (4, 5, 6):
+                    fn(G)
+            else:
+                fn()
+        except (AssertionError, ValueError, ZeroDivisionError, OverflowError, IndexError):
+            caught.append(t)
+    assert caught, "mutation %s passed every pin" % name
