@@ -448,6 +448,11 @@ def test_new_entry_points_reject_bad_arguments(kx):
         kx.test_grouped(r, ts, gd, p_c=0.0)
     with pytest.raises(krux.KruxError):
         kx.permute_hits(r, ts, gd, perms, p_c=1.5)
+    for G in (1, 9):
+        with pytest.raises(krux.KruxError):
+            kx.test_multi(r, ts, gd, G)
+    with pytest.raises(krux.KruxError):
+        kx.test_multi(r, ts, gd, 4, mode="sums")
     real = kx.test(r, ts, gd, p_c=0.5, mode="hits", hit_capacity=64)
     ph = kx.permute_hits(r, ts, gd, perms, p_c=0.5, hit_capacity=64)
     with pytest.raises(krux.KruxError):
