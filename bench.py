@@ -576,10 +576,10 @@ def multi_allelic(args, ctx, torch, np, datagen, krux):
                         "p_c": p_c, "outputs": "sorted hit list"})
     out["steps"], out["warmup"] = steps, 1
     out["n_hits"] = n_hits
-    # VALU-bound lane kernel: per four samples and class, a byte-equality
-    # test (about 7 operations) and two dot4 products, plus 8 operations for
-    # the missing code (an operation count, not a measured one)
-    ops = pairs * (K / 4.0) * (9 * G + 8)
+    # VALU-bound lane kernel: per four samples and class 1..G-1, a
+    # byte-equality test (about 7 operations) and two dot4 products, plus 10
+    # operations for the missing code (an operation count, not a measured one)
+    ops = pairs * (K / 4.0) * (9 * (G - 1) + 10)
     kern_ms = ms
     out["roofline"] = {"bound": "alu", "kernel": "scan_multi<4, SCREEN>",  # and multi_pack
                        "achieved": ops / (kern_ms / 1e3) / 1e12,

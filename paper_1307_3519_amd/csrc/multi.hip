@@ -101,10 +101,11 @@ __global__ __launch_bounds__(256) void scan_multi(MultiArgs a) {
         const int64_t m = blk * kWave + lane;
         if (m < a.M) {
             const uint8_t* row = a.packed + m * (int64_t)a.pstride;
+            // classes 1..G-1 by indicator; class 0 from the totals below
             uint32_t sl[G], sh[G], n[G];
 #pragma unroll
             for (int c = 0; c < G; ++c) { sl[c] = 0; sh[c] = 0; n[c] = 0; }
-            uint32_t nq = 0;
+            uint32_t nq = 0, ql = 0, qh = 0;     // removed samples: count, rank bytes
             for (int i0 = 0; i0 < KW; i0 += 4) {
                 const uint4 g4 = *(const uint4*)(row + 4 * i0);
                 const uint4 l4 = *(const uint4*)(slo + i0);
@@ -117,18 +118,29 @@ __global__ __launch_bounds__(256) void scan_multi(MultiArgs a) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
 #pragma unroll
-                    for (int c = 0; c < G; ++c) {
+                    for (int c = 1; c < G; ++c) {
                         const uint32_t ind = eq_bytes(gw[j], 0x01010101u * (uint32_t)c);
                         sl[c] = __builtin_amdgcn_udot4(ind, lw[j], sl[c], false);
                         n[c] = __builtin_amdgcn_udot4(ind, ow[j], n[c], false);
                         if (wide) sh[c] = __builtin_amdgcn_udot4(ind, hw[j], sh[c], false);
                     }
-                    nq = __builtin_amdgcn_udot4(eq_bytes(gw[j], 0xFFFFFFFFu), ow[j], nq, false);
+                    const uint32_t indq = eq_bytes(gw[j], 0xFFFFFFFFu);
+                    nq = __builtin_amdgcn_udot4(indq, ow[j], nq, false);
+                    ql = __builtin_amdgcn_udot4(indq, lw[j], ql, false);
+                    if (wide) qh = __builtin_amdgcn_udot4(indq, hw[j], qh, false);
                 }
             }
+            // observed samples: doubled ranks summing to kobs (kobs + 1);
+            // class 0 holds the observed ones neither removed nor in 1..G-1
             int64_t s[G];
+            s[0] = (int64_t)kobs * (kobs + 1) - ((int64_t)ql + ((int64_t)qh << 8));
+            n[0] = (uint32_t)kobs - nq;
 #pragma unroll
-            for (int c = 0; c < G; ++c) s[c] = (int64_t)sl[c] + ((int64_t)sh[c] << 8);
+            for (int c = 1; c < G; ++c) {
+                s[c] = (int64_t)sl[c] + ((int64_t)sh[c] << 8);
+                s[0] -= s[c];
+                n[0] -= n[c];
+            }
             // removed samples (K' counts only the kept ones), in sample
             // order: each lowers every kept doubled rank above its own by 2
             // and every tied one by 1, and its tie group (current size t)
