@@ -576,10 +576,10 @@ def multi_allelic(args, ctx, torch, np, datagen, krux):
                         "p_c": p_c, "outputs": "sorted hit list"})
     out["steps"], out["warmup"] = steps, 1
     out["n_hits"] = n_hits
-    # VALU-bound lane kernel: per four samples and class 1..G-1, a
-    # byte-equality test (about 7 operations) and two dot4 products, plus 10
-    # operations for the missing code (an operation count, not a measured one)
-    ops = pairs * (K / 4.0) * (9 * (G - 1) + 10)
+    # VALU-bound lane kernel: per four samples, about 8 operations for the
+    # code bits and the missing code, then per class 1..G-1 two ANDs and two
+    # dot4 products (an operation count, not a measured one)
+    ops = pairs * (K / 4.0) * (4 * (G - 1) + 8)
     kern_ms = ms
     out["roofline"] = {"bound": "alu", "kernel": "scan_multi<4, SCREEN>",  # and multi_pack
                        "achieved": ops / (kern_ms / 1e3) / 1e12,

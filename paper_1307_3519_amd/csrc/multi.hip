@@ -52,12 +52,6 @@ __global__ void multi_pack(const int8_t* __restrict__ geno, int64_t ld, int64_t 
     }
 }
 
-// bytes of w equal to the byte value in v (v replicated) -> 1, else 0
-__device__ inline uint32_t eq_bytes(uint32_t w, uint32_t v) {
-    const uint32_t x = w ^ v;
-    return (~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u) >> 7;
-}
-
 template <int G, int MODE>
 __global__ __launch_bounds__(256) void scan_multi(MultiArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint32_t s_words[];
@@ -117,14 +111,24 @@ __global__ __launch_bounds__(256) void scan_multi(MultiArgs a) {
                 const uint32_t hw[4] = {h4.x, h4.y, h4.z, h4.w};
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
+                    // codes are 0..7 or 0xFF: a class's indicator bytes are
+                    // the AND of its three low bits, each taken as is or
+                    // inverted (0xFF matches only code 7, which also needs
+                    // the top bit clear)
+                    const uint32_t w = gw[j];
+                    const uint32_t b0 = w & 0x01010101u, b1 = (w >> 1) & 0x01010101u;
+                    const uint32_t b2 = (w >> 2) & 0x01010101u, top = (w >> 7) & 0x01010101u;
 #pragma unroll
                     for (int c = 1; c < G; ++c) {
-                        const uint32_t ind = eq_bytes(gw[j], 0x01010101u * (uint32_t)c);
+                        uint32_t ind = (c & 1) ? b0 : (b0 ^ 0x01010101u);
+                        ind &= (c & 2) ? b1 : (b1 ^ 0x01010101u);
+                        ind &= (c & 4) ? b2 : (b2 ^ 0x01010101u);
+                        if (c == 7) ind &= ~top;
                         sl[c] = __builtin_amdgcn_udot4(ind, lw[j], sl[c], false);
                         n[c] = __builtin_amdgcn_udot4(ind, ow[j], n[c], false);
                         if (wide) sh[c] = __builtin_amdgcn_udot4(ind, hw[j], sh[c], false);
                     }
-                    const uint32_t indq = eq_bytes(gw[j], 0xFFFFFFFFu);
+                    const uint32_t indq = top;                 // the missing code
                     nq = __builtin_amdgcn_udot4(indq, ow[j], nq, false);
                     ql = __builtin_amdgcn_udot4(indq, lw[j], ql, false);
                     if (wide) qh = __builtin_amdgcn_udot4(indq, hw[j], qh, false);
