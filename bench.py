@@ -28,8 +28,8 @@ Workloads (--workload; seeded synthetic data shaped like the paper's
       genotypes (samples 5 and 40 missing in 90% of the SNPs, sample 77 in
       30%); the pattern-grouped scan timed beside the per-pair path
   multi_allelic    K=102, 20,000 traits, 50,000 markers with 4 genotype classes
-      (class frequencies Dirichlet(1) per marker); hits at p < 1e-5 through
-      the lane-per-pair multi-allelic kernel
+      (class frequencies Dirichlet(1) per marker); hits at p < 1e-5 plus the
+      per-trait minimum p through the lane-per-pair multi-allelic kernel
   missing_expression  the paper-scale workload with NaN expression values in
       2% of the traits (1-5 each); hits at p < 1e-5 plus the per-trait minimum
       p, timed beside the same traits without NaN values
@@ -563,7 +563,8 @@ def multi_allelic(args, ctx, torch, np, datagen, krux):
 
     def step():
         r, ts, _ = ctx.rank(x)
-        return ctx.test_multi(r, ts, g, G, p_c=p_c, mode="hits", hit_capacity=1 << 17)
+        return ctx.test_multi(r, ts, g, G, p_c=p_c, mode="hits", hit_capacity=1 << 17,
+                              min_p=not args.no_minp)
 
     log("multi-allelic: 1 warmup + %d timed steps" % steps)
     ms, res, _, _ = runner.run(step, steps, 1)
@@ -573,12 +574,14 @@ def multi_allelic(args, ctx, torch, np, datagen, krux):
     out = base_line(args, "SNP-trait pairs/sec, multi-allelic markers", pairs / (ms / 1e3),
                     "pairs/s", ms, "int32/f64", {
                         "workload": "multi_allelic", "K": K, "T": T, "M": M, "classes": G,
-                        "p_c": p_c, "outputs": "sorted hit list"})
+                        "p_c": p_c, "outputs": "sorted hit list" +
+                        ("" if args.no_minp else " + per-trait min p")})
     out["steps"], out["warmup"] = steps, 1
     out["n_hits"] = n_hits
     # VALU-bound lane kernel: per four samples, about 8 operations for the
     # code bits and the missing code, then per class 1..G-1 two ANDs and two
-    # dot4 products (an operation count, not a measured one)
+    # dot4 products (an operation count, not a measured one; the p-value of
+    # every pair for the minimum p is not counted)
     ops = pairs * (K / 4.0) * (4 * (G - 1) + 8)
     kern_ms = ms
     out["roofline"] = {"bound": "alu", "kernel": "scan_multi<4, SCREEN>",  # and multi_pack

@@ -165,14 +165,15 @@ krux_status krux_test_grouped(krux_ctx* ctx, const int16_t* ranks2, const int64_
  *   n_classes  2..8 (l + 1); K <= 2048.
  *   mode       KRUX_MODE_HITS: hits (sorted by (trait, snp)) with
  *              H > H_c(df), the largest double whose chi-square tail at df is
- *              >= p_c; *n_hits the true count.  KRUX_MODE_FULL: H and p
- *              (device, T x M doubles).
+ *              >= p_c; *n_hits the true count; min_p (device, T doubles, may
+ *              be NULL) the minimum p over the SNPs per trait.
+ *              KRUX_MODE_FULL: H and p (device, T x M doubles).
  * Other arguments as krux_test; unused outputs may be NULL. */
 krux_status krux_test_multi(krux_ctx* ctx, const int16_t* ranks2, const int64_t* tiesum,
                             int64_t T, int32_t K, const int8_t* geno, int64_t M, int64_t ld_geno,
                             int32_t n_classes, int64_t snp_base, double p_c, int32_t mode,
-                            krux_hit* hits, int64_t hit_capacity, int64_t* n_hits, double* H,
-                            double* p, void* stream);
+                            krux_hit* hits, int64_t hit_capacity, int64_t* n_hits,
+                            double* min_p, double* H, double* p, void* stream);
 
 /* Permuted-data repeats for the empirical FDR (P-value calculation and
  * empirical FDR correction): for each permutation pi (perms, P x K int32,

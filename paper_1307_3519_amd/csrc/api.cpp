@@ -1072,8 +1072,8 @@ double threshold_any_df(double p_c, int df) {
 krux_status krux_test_multi(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum, int64_t T,
                             int32_t K, const int8_t* geno, int64_t M, int64_t ld_geno,
                             int32_t n_classes, int64_t snp_base, double p_c, int32_t mode,
-                            krux_hit* hits, int64_t hit_capacity, int64_t* n_hits, double* H,
-                            double* p, void* stream) {
+                            krux_hit* hits, int64_t hit_capacity, int64_t* n_hits,
+                            double* min_p, double* H, double* p, void* stream) {
     if (!c) return fail(nullptr, KRUX_ERR_ARG, "ctx is NULL");
     krux_status s = check_ranks(c, ranks2, tiesum, T, K);
     if (s != KRUX_OK) return s;
@@ -1107,6 +1107,11 @@ krux_status krux_test_multi(krux_ctx* c, const int16_t* ranks2, const int64_t* t
         if (s != KRUX_OK) return s;
         HIP_TRY(c, kx_launch_fill_u64(nh, 1, 0ull, st));
         a.hits = stage; a.hit_cap = hit_capacity; a.n_hits = nh;
+        if (min_p && T > 0) {
+            a.minp_bits = (unsigned long long*)ws(c, S_MINP, (size_t)T * 8, &s);
+            if (s != KRUX_OK) return s;
+            HIP_TRY(c, kx_launch_fill_u64(a.minp_bits, T, 0x3FF0000000000000ull, st));
+        }
     } else {
         a.H_out = H; a.p_out = p;
     }
@@ -1121,7 +1126,10 @@ krux_status krux_test_multi(krux_ctx* c, const int16_t* ranks2, const int64_t* t
         HIP_TRY(c, kx_launch_multi(&a, n_classes, mode == KRUX_MODE_FULL ? kx::FULL : kx::SCREEN,
                                    grid, st));
     }
-    if (mode == KRUX_MODE_HITS) return sort_stage(c, stage, nh, hit_capacity, hits, n_hits, T, st);
+    if (mode == KRUX_MODE_HITS) {
+        if (a.minp_bits) HIP_TRY(c, kx_launch_bits_to_double(a.minp_bits, T, min_p, st));
+        return sort_stage(c, stage, nh, hit_capacity, hits, n_hits, T, st);
+    }
     return KRUX_OK;
 }
 

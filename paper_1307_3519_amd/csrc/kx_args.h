@@ -100,6 +100,7 @@ struct MultiArgs {
     int64_t snp_base;
     double* H_out;           // full mode: T x M
     double* p_out;
+    unsigned long long* minp_bits;  // hits mode: [T] bits of the per-trait min p, or null
 };
 
 // Extra operands of the tiled large-K kernels.

@@ -69,6 +69,7 @@ __global__ __launch_bounds__(256) void scan_multi(MultiArgs a) {
     const int64_t nb = (a.M + kWave - 1) / kWave;
     const int64_t items = a.T * nb;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    double pmin = 2.0;                               // the lane's smallest p of the item
     for (int64_t it = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; it < items; it += waves) {
         const int64_t trait = it / nb;
         const int64_t blk = it - trait * nb;
@@ -191,7 +192,9 @@ __global__ __launch_bounds__(256) void scan_multi(MultiArgs a) {
             if (MODE == FULL) {
                 a.H_out[trait * a.M + m] = H;
                 a.p_out[trait * a.M + m] = chi2_upper(H, df);
-            } else if (df > 0 && H > a.hc[df]) {
+            } else {
+                if (a.minp_bits) pmin = fmin(pmin, chi2_upper(H, df));
+                if (df > 0 && H > a.hc[df]) {
                 const unsigned long long idx = atomicAdd(a.n_hits, 1ull);
                 if ((int64_t)idx < a.hit_cap) {
                     HitRec h;
@@ -201,7 +204,16 @@ __global__ __launch_bounds__(256) void scan_multi(MultiArgs a) {
                     h.p = chi2_upper(H, df);
                     a.hits[idx] = h;
                 }
+                }
             }
+        }
+        if (MODE != FULL && a.minp_bits) {
+            // every lane of the wave holds the same trait: one update per wave
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) pmin = fmin(pmin, __shfl_xor(pmin, o, 64));
+            if (lane == 0 && pmin <= 1.0)
+                atomicMin(&a.minp_bits[trait], (unsigned long long)__double_as_longlong(pmin));
+            pmin = 2.0;
         }
         __builtin_amdgcn_wave_barrier();
     }

@@ -76,7 +76,7 @@ def library():
     lib.krux_test_batched.restype = ctypes.c_int
     lib.krux_test_multi.restype = ctypes.c_int
     lib.krux_test_multi.argtypes = [P, P, P, i64, i32, P, i64, i64, i32, i64, dbl, i32, P, i64,
-                                    P, P, P, P]
+                                    P, P, P, P, P]
     lib.krux_test_grouped.restype = ctypes.c_int
     lib.krux_test_grouped.argtypes = [P, P, P, i64, i32, P, i64, i64, i64, dbl, i32, i64, P, i64,
                                       P, P, P]
@@ -273,7 +273,7 @@ class Context:
         return dict(hits_raw=hits, n_hits_t=nh, min_p=mp, hit_capacity=hit_capacity)
 
     def test_multi(self, ranks2, tiesum, geno, n_classes, p_c=1e-5, mode="hits",
-                   hit_capacity=1 << 16, snp_base=0):
+                   hit_capacity=1 << 16, snp_base=0, min_p=True):
         """Multi-allelic markers (codes 0..n_classes-1): hits mode -> dict as
         test(); full mode -> dict(H, p) (T, M) float64."""
         T, K = ranks2.shape
@@ -282,20 +282,22 @@ class Context:
         assert M == 0 or geno.stride(1) == 1
         dev = ranks2.device
         m = _MODE[mode]
-        hits = nh = H = p = None
+        hits = nh = H = p = mp = None
         if m == MODE_HITS:
             hits = torch.empty(max(hit_capacity, 1) * 24, dtype=torch.uint8, device=dev)
             nh = torch.zeros(1, dtype=torch.int64, device=dev)
+            if min_p:
+                mp = torch.empty(T, dtype=torch.float64, device=dev)
         else:
             H = torch.empty((T, M), dtype=torch.float64, device=dev)
             p = torch.empty((T, M), dtype=torch.float64, device=dev)
         self._check(self.lib.krux_test_multi(
             self.h, _ptr(ranks2), _ptr(tiesum), T, K, _ptr(geno), M,
             geno.stride(0) if M else K, int(n_classes), int(snp_base), float(p_c), m,
-            _ptr(hits), int(hit_capacity) if m == MODE_HITS else 0, _ptr(nh), _ptr(H), _ptr(p),
-            _stream()))
+            _ptr(hits), int(hit_capacity) if m == MODE_HITS else 0, _ptr(nh), _ptr(mp), _ptr(H),
+            _ptr(p), _stream()))
         if m == MODE_HITS:
-            return dict(hits_raw=hits, n_hits_t=nh, min_p=None, hit_capacity=hit_capacity)
+            return dict(hits_raw=hits, n_hits_t=nh, min_p=mp, hit_capacity=hit_capacity)
         return dict(H=H, p=p)
 
     # ------------------------------------------------------------------ permute

@@ -523,3 +523,4 @@ def test_multi_allelic(kx, K, T, M, G):
     n, h = unpack_hits(res)
     assert n == len(o["hits"]) and n > 0
     assert list(zip(h["trait"].tolist(), (h["snp"] - 3).tolist())) == o["hits"]
+    assert_p(res["min_p"].cpu().numpy(), o["p"].min(axis=1), "multi min p")
