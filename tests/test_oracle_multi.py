@@ -102,6 +102,78 @@ def test_perfect_separation_closed_form():
         assert o["df"] == G - 1
 
 
+def _scan_case(seed, T=6, M=40, K=36, G=5):
+    rng = np.random.default_rng(seed)
+    x = np.round(rng.lognormal(size=(T, K)), 1).astype(np.float32)      # ties
+    x[rng.random(x.shape) < 0.03] = np.nan
+    q = rng.dirichlet(np.ones(G), size=M)
+    g = np.array([rng.choice(G, size=K, p=q[m]) for m in range(M)], dtype=np.int8)
+    g[rng.random(g.shape) < 0.04] = -1
+    # strong effects on a few pairs so that both sides of the threshold occur
+    for t in range(T):
+        m = int(rng.integers(0, M))
+        x[t] = np.where(np.isnan(x[t]), x[t], x[t] + 0.8 * g[m].clip(0)).astype(np.float32)
+    return x, g
+
+
+def test_scan_hits_follow_scipy_tail_below_pc():
+    # Hit rule (P-value calculation, strict reading): a pair is a hit iff its
+    # degrees of freedom are at least 1 and its chi-square p-value is below
+    # P_c.  Checked pair by pair against scipy: H from kruskal over the kept
+    # samples, df from the number of classes present, p from chi2.sf; pairs
+    # whose p lies within 1e-9 (relative) of P_c are left out, where the two
+    # tails may round differently.
+    G, p_c = 5, 0.01
+    x, g = _scan_case(3, G=G)
+    o = multi.scan(x, g, G, p_c=p_c)
+    hits = set(o["hits"])
+    assert o["hits"] == sorted(o["hits"])
+    n_hit = n_miss = 0
+    for t in range(x.shape[0]):
+        for m in range(g.shape[0]):
+            keep = (~np.isnan(x[t])) & (g[m] >= 0) & (g[m] < G)
+            groups = [x[t][keep & (g[m] == c)].astype(np.float64) for c in range(G)]
+            groups = [q for q in groups if len(q)]
+            df = len(groups) - 1
+            if df < 1 or len(np.unique(np.concatenate(groups))) < 2:
+                assert (t, m) not in hits
+                continue
+            pv = st.chi2.sf(st.kruskal(*groups).statistic, df)
+            if abs(pv - p_c) <= 1e-9 * p_c:
+                continue
+            want = pv < p_c
+            assert ((t, m) in hits) == want, (t, m, pv, df)
+            n_hit += want
+            n_miss += not want
+    assert n_hit >= 3 and n_miss >= 3
+
+
+def test_scan_pair_at_exactly_pc_is_not_a_hit():
+    # A pair whose p-value equals P_c is not a hit (strict p < P_c); with
+    # P_c one ulp above its p it is.  The pair is chosen where the tail
+    # falls from one double of H to the next, so that P_c = p(H) pins the
+    # threshold to H itself.
+    G = 5
+    x, g = _scan_case(4, T=4, M=25, G=G)
+    o = multi.scan(x, g, G)
+    chosen = None
+    for t in range(x.shape[0]):
+        for m in range(g.shape[0]):
+            H = o["H"][t, m]
+            one = multi.one_pair(x[t], g[m], G)
+            if one["df"] >= 2 and H > 1.0:
+                pc = multi.chi2_tail(H, one["df"])
+                if multi.chi2_tail(math.nextafter(H, math.inf), one["df"]) < pc and pc > 1e-12:
+                    chosen = (t, m, pc)
+                    break
+        if chosen:
+            break
+    assert chosen is not None
+    t, m, pc = chosen
+    assert (t, m) not in multi.scan(x, g, G, p_c=pc)["hits"]
+    assert (t, m) in multi.scan(x, g, G, p_c=math.nextafter(pc, 1.0))["hits"]
+
+
 # Planted mistakes in the multi-allelic oracle must each fail one of the pins
 # above (the source is edited in memory and loaded as a separate module).
 MULTI_MUTATIONS = {
@@ -111,11 +183,16 @@ MULTI_MUTATIONS = {
     "odd_tail_no_erfc": ("total = math.erfc(math.sqrt(x))", "total = 0.0"),
     "even_tail_sum_short": ("for k in range(1, df // 2):", "for k in range(1, df // 2 - 1):"),
     "missing_code_kept": ("0 <= int(g[k]) < n_classes", "int(g[k]) < n_classes"),
+    "scan_hit_at_threshold": ('o["H"] > threshold(p_c, o["df"])', 'o["H"] >= threshold(p_c, o["df"])'),
+    "scan_df_plus_one": ('threshold(p_c, o["df"])', 'threshold(p_c, o["df"] + 1)'),
+    "scan_df_minus_one": ('threshold(p_c, o["df"])', 'threshold(p_c, max(o["df"] - 1, 1))'),
 }
 
 MULTI_BATTERY = ["test_chi2_tail_matches_scipy", "test_threshold_is_largest_double_with_p_at_least_pc",
                  "test_two_alleles_equal_the_c_oracle", "test_vs_scipy_kruskal",
-                 "test_permutation_null_mean_is_df", "test_perfect_separation_closed_form"]
+                 "test_permutation_null_mean_is_df", "test_perfect_separation_closed_form",
+                 "test_scan_hits_follow_scipy_tail_below_pc",
+                 "test_scan_pair_at_exactly_pc_is_not_a_hit"]
 
 
 @pytest.mark.parametrize("name", sorted(MULTI_MUTATIONS))
@@ -129,6 +206,7 @@ def test_planted_multi_mistake_is_caught(name, monkeypatch):
     monkeypatch.setattr(__import__("oracle").multi, "chi2_tail", mod.chi2_tail)
     monkeypatch.setattr(__import__("oracle").multi, "threshold", mod.threshold)
     monkeypatch.setattr(__import__("oracle").multi, "one_pair", mod.one_pair)
+    monkeypatch.setattr(__import__("oracle").multi, "scan", mod.scan)
     caught = []
     for t in MULTI_BATTERY:
         fn = globals()[t]
