@@ -20,6 +20,19 @@
  *     memory.  The context owns its scratch memory (allocated at first use,
  *     grown as needed, freed by krux_destroy).  Calls on one context must not
  *     overlap in time (one context per host thread).
+ *   - Graph capture: krux_rank, krux_test (fp16 and int8), krux_permute,
+ *     krux_permute_hits, krux_fdr_curve, krux_test_multi and
+ *     krux_test_batched enqueue kernels only (no host synchronisation, no
+ *     memset nodes), so the caller may capture a call into a HIP graph and
+ *     replay it.  A call made while its stream is being captured must not
+ *     need more scratch than an earlier call on the same context already
+ *     allocated: otherwise it returns KRUX_ERR_UNSUPPORTED (run the same call
+ *     once without capture first).  Once a call has been captured, a later
+ *     call that needs a larger scratch buffer gets a new one and the old one
+ *     is kept until krux_destroy, so captured graphs stay valid.  Replays of
+ *     a graph and other calls on the same context must not overlap in time.
+ *     krux_test_grouped, krux_autotune and the fp64 comparator synchronise
+ *     and are refused under capture.
  *   - Doubled midranks: a = 2 x (average rank), i.e.
  *     a_k = 2 #{j: x_j < x_k} + #{j: x_j == x_k} + 1, an integer in [2, 2K];
  *     0 marks a missing (NaN) expression value.
@@ -82,7 +95,8 @@ enum {
 #define KRUX_MAX_K_FP16 2049
 
 /* Create a context on HIP device `device`.  Returns KRUX_OK and *out, or an
- * error (then *out is NULL). */
+ * error (then *out is NULL).  Tuned launch configurations are loaded into a
+ * context afterwards with krux_load_tuning (or found by krux_autotune). */
 krux_status krux_create(krux_ctx** out, int device);
 
 /* Free a context and all its scratch memory.  Synchronises its device. */
@@ -182,8 +196,9 @@ krux_status krux_test_multi(krux_ctx* ctx, const int16_t* ranks2, const int64_t*
  *   p_cs    (host) n_thr p-value thresholds, each in (0, 1].
  *   counts  P x n_thr int64: number of hits at each threshold.
  *   min_p   P x T doubles or NULL: per permutation and trait, min p over SNPs.
- * The whole batch is one graph of launches, replayed when the call is
- * repeated with the same arguments. */
+ * Every permutation of the batch is scanned by the same kernel launches (rows
+ * perm * T + trait of one operand).  The call enqueues kernels only, so the
+ * caller may capture it into a graph and replay it (see the conventions). */
 krux_status krux_permute(krux_ctx* ctx, const int16_t* ranks2, const int64_t* tiesum,
                          int64_t T, int32_t K, const int8_t* geno, int64_t M,
                          int64_t ld_geno, const int32_t* perms, int32_t P,
@@ -222,8 +237,8 @@ krux_status krux_fdr_curve(krux_ctx* ctx, const krux_hit* real, const int64_t* n
                            int64_t real_capacity, const krux_hit* perm, const int64_t* n_perm,
                            int64_t perm_capacity, int32_t P, double* fdr, void* stream);
 
-/* One cohort of a batched scan:/* One cohort of a batched scan: its own samples (K), traits and genotype
- * matrix over a shared SNP panel of M SNPs. Pointers are device pointers. */
+/* One cohort of a batched scan: its own samples (K), traits and genotype
+ * matrix over a shared SNP panel of M SNPs.  Pointers are device pointers. */
 typedef struct {
     const int16_t* ranks2;  /* T x K */
     const int64_t* tiesum;  /* T */
@@ -242,6 +257,19 @@ typedef struct {
 krux_status krux_test_batched(krux_ctx* ctx, const krux_cohort* cohorts,
                               int32_t n_cohorts, int64_t M, double p_c,
                               int32_t precision, void* stream);
+
+/* Limits on the two screened-pair buffers of the context (entries; 0 = the
+ * built-in sizes, which grow with the expected number of screened pairs):
+ * `candidates` bounds the buffer of pairs of complete SNPs that pass the fp32
+ * screen (16 B each; built in: at least 2^22), `missing_pairs` the buffer of
+ * pairs of SNPs with missing genotypes that pass the missing-genotype bound
+ * (16 B each; built in: at least 2^16).  Pairs beyond a full buffer are
+ * evaluated inside the scan kernels instead (slower, identical results), so
+ * a limit bounds scratch memory, and a tiny limit exercises those paths.
+ * Applies to later krux_test / krux_permute / krux_permute_hits /
+ * krux_test_grouped / krux_test_batched calls on this context. */
+krux_status krux_set_pair_buffer_limits(krux_ctx* ctx, int64_t candidates,
+                                        int64_t missing_pairs);
 
 /* Instrumentation of the fused scan kernels (the rank-sum GEMM with its
  * epilogue): after krux_timer_start, each main pass of krux_test /

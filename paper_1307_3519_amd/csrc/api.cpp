@@ -60,6 +60,15 @@ struct krux_ctx {
     bool timing = false;    // krux_timer_start .. krux_timer_read
     std::vector<hipEvent_t> ev;   // start/stop pairs of timed launches
     size_t ev_used = 0;
+    // limits on the two screened-pair buffers (krux_set_pair_buffer_limits; 0: none)
+    int64_t cand_limit = 0, mcand_limit = 0;
+    // graph capture: `capturing` holds while a call enqueues into a stream that
+    // is being captured (no buffer may grow then); once anything has been
+    // captured, a growing buffer keeps its old allocation in `retired` (freed by
+    // krux_destroy) because a graph may still read it
+    bool capturing = false;
+    bool captured = false;
+    std::vector<void*> retired;
 };
 
 namespace {
@@ -84,14 +93,27 @@ krux_status fail(krux_ctx* c, krux_status s, const char* fmt, ...) {
             return fail(c, KRUX_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));   \
     } while (0)
 
-// Grow-only scratch buffer of the context.
+// Grow-only scratch buffer of the context.  Growing is refused while the
+// call's stream is being captured (an allocation cannot be captured, and the
+// graph would hold the old pointer); after a capture the old allocation is
+// kept, not freed, so that captured graphs stay valid.
 void* ws(krux_ctx* c, int slot, size_t bytes, krux_status* st) {
     Buf& b = c->bufs[slot];
     if (bytes == 0) bytes = 256;
     if (b.n >= bytes) return b.p;
+    if (c->capturing) {
+        *st = fail(c, KRUX_ERR_UNSUPPORTED,
+                   "a scratch buffer must grow to %zu bytes while the stream is being captured: "
+                   "run the same call once without capture first", bytes);
+        return nullptr;
+    }
     if (b.p) {
-        (void)hipDeviceSynchronize();
-        (void)hipFree(b.p);
+        if (c->captured) {
+            c->retired.push_back(b.p);
+        } else {
+            (void)hipDeviceSynchronize();
+            (void)hipFree(b.p);
+        }
         b.p = nullptr;
         b.n = 0;
     }
@@ -106,6 +128,25 @@ void* ws(krux_ctx* c, int slot, size_t bytes, krux_status* st) {
 }
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Start of an entry point that enqueues on `st`: notes whether the stream is
+// being captured into a graph.  Calls that synchronise pass may_capture =
+// false and are refused under capture.
+krux_status begin_call(krux_ctx* c, hipStream_t st, bool may_capture = true) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipStreamIsCapturing(st, &cs));
+    c->capturing = cs == hipStreamCaptureStatusActive;
+    if (c->capturing && !may_capture)
+        return fail(c, KRUX_ERR_UNSUPPORTED, "this call synchronises its stream and cannot be captured");
+    if (c->capturing) c->captured = true;
+    return KRUX_OK;
+}
+
+// Entries of a screened-pair buffer after the context's limit.
+int64_t pair_limit(int64_t want, int64_t limit) {
+    return limit > 0 ? std::min(want, limit) : want;
+}
 
 // Capacity of the screened-pair buffer (16 B per entry).  When a scan finds
 // more candidates than this, the extra ones are evaluated inside the scan.
@@ -410,7 +451,9 @@ krux_status run_screen(krux_ctx* c, kx::ScanArgs a, const Variant& v, const Colu
     // the pairs, at most 2^27 entries (2 GB of the 288 GB); the rest are
     // evaluated in the scan kernel itself, which is several times slower (at
     // the 64/M screen level of a min-p run, a few percent of the pairs pass)
-    a.mcand_cap = std::min<int64_t>(std::max<int64_t>(n_rows_max * a.M / 16, 1 << 16), 1LL << 27);
+    a.mcand_cap = pair_limit(
+        std::min<int64_t>(std::max<int64_t>(n_rows_max * a.M / 16, 1 << 16), 1LL << 27),
+        c->mcand_limit);
     a.mcand = (int4*)ws(c, S_MCAND, (size_t)a.mcand_cap * sizeof(int4), &s);
     a.n_mcand = a.n_cand + 1;      // both counters were cleared by the preceding prep kernel
     if (s != KRUX_OK) return s;
@@ -555,6 +598,8 @@ krux_status test_impl(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum,
     } else {
         if (T * M > 0 && !sums) return fail(c, KRUX_ERR_ARG, "sums is NULL");
     }
+    if (precision == KRUX_PREC_FP64 && c->capturing)
+        return fail(c, KRUX_ERR_UNSUPPORTED, "the fp64 comparator cannot be captured");
     if (precision == KRUX_PREC_FP64)
         return kx_fp64_test(c, ranks2, tiesum, T, K, geno, M, ld_geno, snp_base, p_c, mode, hits,
                             hit_capacity, n_hits, min_p, H, p, sums, st);
@@ -611,7 +656,7 @@ krux_status test_impl(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum,
     // the few rows without one get the looser passes of resolve_min_p.
     const double p_screen = min_p ? screen_level_for_min_p(p_c, M) : p_c;
     set_screen(&a, p_screen);
-    a.cand_cap = candidate_capacity(T, M, p_screen);
+    a.cand_cap = pair_limit(candidate_capacity(T, M, p_screen), c->cand_limit);
     if ((s = run_screen(c, a, v, col, rk.A_hi, st, T, true)) != KRUX_OK) return s;
     if ((s = run_nan_traits(c, a, ns, 1, kx::SCREEN, st)) != KRUX_OK) return s;
     if (min_p && T > 0) {
@@ -695,6 +740,14 @@ krux_status krux_timer_read(krux_ctx* c, double* total_ms, int64_t* launches) {
     return KRUX_OK;
 }
 
+krux_status krux_set_pair_buffer_limits(krux_ctx* c, int64_t candidates, int64_t missing_pairs) {
+    if (!c) return fail(nullptr, KRUX_ERR_ARG, "ctx is NULL");
+    if (candidates < 0 || missing_pairs < 0) return fail(c, KRUX_ERR_ARG, "negative limit");
+    c->cand_limit = candidates;
+    c->mcand_limit = missing_pairs;
+    return KRUX_OK;
+}
+
 void krux_destroy(krux_ctx* c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
@@ -703,6 +756,7 @@ void krux_destroy(krux_ctx* c) {
     kx_fp64_release(c);
     for (auto& b : c->bufs)
         if (b.p) (void)hipFree(b.p);
+    for (void* p : c->retired) (void)hipFree(p);
     delete c;
 }
 
@@ -728,7 +782,8 @@ krux_status krux_rank(krux_ctx* c, const float* expr, int64_t T, int32_t K, int6
     if (ld_expr < K) return fail(c, KRUX_ERR_SHAPE, "ld_expr < K");
     if (T > 0 && (!expr || !ranks2 || !tiesum)) return fail(c, KRUX_ERR_ARG, "NULL array");
     if (T == 0) return KRUX_OK;
-    HIP_TRY(c, hipSetDevice(c->device));
+    krux_status s = begin_call(c, (hipStream_t)stream);
+    if (s != KRUX_OK) return s;
     HIP_TRY(c, kx_launch_rank(expr, T, K, ld_expr, ranks2, tiesum, nvalid, 1 << 30,
                               (hipStream_t)stream));
     return KRUX_OK;
@@ -740,6 +795,8 @@ krux_status krux_test(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum,
                       int64_t hit_capacity, int64_t* n_hits, double* min_p, double* H, double* p,
                       int32_t* sums, void* stream) {
     if (!c) return fail(nullptr, KRUX_ERR_ARG, "ctx is NULL");
+    krux_status s = begin_call(c, (hipStream_t)stream);
+    if (s != KRUX_OK) return s;
     return test_impl(c, ranks2, tiesum, T, K, geno, M, ld_geno, snp_base, p_c, mode, precision,
                      hits, hit_capacity, n_hits, min_p, H, p, sums, (hipStream_t)stream);
 }
@@ -757,6 +814,7 @@ krux_status permute_impl(krux_ctx* c, const int16_t* ranks2, const int64_t* ties
     krux_status s = check_ranks(c, ranks2, tiesum, T, K);
     if (s != KRUX_OK) return s;
     if ((s = check_geno(c, geno, M, ld_geno, K)) != KRUX_OK) return s;
+    if ((s = begin_call(c, (hipStream_t)stream)) != KRUX_OK) return s;
     if (P < 1 || !perms) return fail(c, KRUX_ERR_ARG, "need P >= 1 permutations");
     if (n_thr < 1 || n_thr > kx::kMaxLevels || !p_cs)
         return fail(c, KRUX_ERR_ARG, "n_thr must be in [1, %d]", kx::kMaxLevels);
@@ -805,7 +863,7 @@ krux_status permute_impl(krux_ctx* c, const int16_t* ranks2, const int64_t* ties
     double loosest = *std::max_element(p_cs, p_cs + n_thr);
     if (min_p) loosest = screen_level_for_min_p(loosest, M);
     set_screen(&a, loosest);
-    a.cand_cap = candidate_capacity(V, M, loosest);
+    a.cand_cap = pair_limit(candidate_capacity(V, M, loosest), c->cand_limit);
     if ((s = run_screen(c, a, v, col, rk.A_hi, st, V, true)) != KRUX_OK) return s;
     if ((s = run_nan_traits(c, a, ns, P, kx::SCREEN, st)) != KRUX_OK) return s;
     if (min_p && V > 0) {
@@ -853,8 +911,8 @@ krux_status krux_fdr_curve(krux_ctx* c, const krux_hit* real, const int64_t* n_r
     if (!n_real || !n_perm) return fail(c, KRUX_ERR_ARG, "n_real / n_perm is NULL");
     if ((real_capacity > 0 && (!real || !fdr)) || (perm_capacity > 0 && !perm))
         return fail(c, KRUX_ERR_ARG, "hit list or fdr is NULL");
-    HIP_TRY(c, hipSetDevice(c->device));
-    krux_status s = KRUX_OK;
+    krux_status s = begin_call(c, (hipStream_t)stream);
+    if (s != KRUX_OK) return s;
     const int64_t big = std::max<int64_t>(std::max(real_capacity, perm_capacity), 1);
     const size_t tmp_bytes = kx_sort_keys_tmp_bytes(big);
     unsigned long long* kr = (unsigned long long*)ws(c, S_KEYS, (size_t)std::max<int64_t>(real_capacity, 1) * 16, &s);
@@ -892,6 +950,7 @@ krux_status krux_test_grouped(krux_ctx* c, const int16_t* ranks2, const int64_t*
         return fail(c, KRUX_ERR_ARG, "hits / hit_capacity");
     if (hit_capacity > (int64_t)UINT32_MAX) return fail(c, KRUX_ERR_ARG, "hit_capacity too large");
     if (min_group < 1) return fail(c, KRUX_ERR_ARG, "min_group < 1");
+    if ((s = begin_call(c, st, false)) != KRUX_OK) return s;
     auto plain = [&]() {
         return test_impl(c, ranks2, tiesum, T, K, geno, M, ld_geno, snp_base, p_c, KRUX_MODE_HITS,
                          precision, hits, hit_capacity, n_hits, min_p, nullptr, nullptr, nullptr,
@@ -1084,6 +1143,7 @@ krux_status krux_test_multi(krux_ctx* c, const int16_t* ranks2, const int64_t* t
     if (mode != KRUX_MODE_HITS && mode != KRUX_MODE_FULL)
         return fail(c, KRUX_ERR_ARG, "mode %d (HITS or FULL)", mode);
     hipStream_t st = (hipStream_t)stream;
+    if ((s = begin_call(c, st)) != KRUX_OK) return s;
     kx::MultiArgs a{};
     a.ranks2 = ranks2; a.tiesum = tiesum; a.T = T; a.K = K; a.M = M; a.snp_base = snp_base;
     a.pstride = (K + 15) & ~15;
@@ -1094,6 +1154,8 @@ krux_status krux_test_multi(krux_ctx* c, const int16_t* ranks2, const int64_t* t
             return fail(c, KRUX_ERR_ARG, "hits / hit_capacity");
         if (hit_capacity > (int64_t)UINT32_MAX)
             return fail(c, KRUX_ERR_ARG, "hit_capacity too large");
+        if (snp_base < 0 || snp_base + M > INT32_MAX)
+            return fail(c, KRUX_ERR_ARG, "snp_base + M outside int32");
         for (int df = 1; df < n_classes; ++df) a.hc[df] = threshold_any_df(p_c, df);
     } else if (T * M > 0 && (!H || !p)) {
         return fail(c, KRUX_ERR_ARG, "H / p is NULL");
@@ -1137,6 +1199,8 @@ krux_status krux_test_batched(krux_ctx* c, const krux_cohort* co, int32_t n, int
                               double p_c, int32_t precision, void* stream) {
     if (!c) return fail(nullptr, KRUX_ERR_ARG, "ctx is NULL");
     if (n < 0 || (n > 0 && !co)) return fail(c, KRUX_ERR_ARG, "cohorts");
+    krux_status s0 = begin_call(c, (hipStream_t)stream);
+    if (s0 != KRUX_OK) return s0;
     for (int i = 0; i < n; ++i) {
         krux_status s = test_impl(c, co[i].ranks2, co[i].tiesum, co[i].T, co[i].K, co[i].geno, M,
                                   co[i].ld_geno, 0, p_c, KRUX_MODE_HITS, precision, co[i].hits,
@@ -1213,6 +1277,7 @@ krux_status krux_autotune(krux_ctx* c, const int16_t* ranks2, const int64_t* tie
     Variant v;
     if ((s = choose_variant(c, K, precision, &v)) != KRUX_OK) return s;
     hipStream_t st = (hipStream_t)stream;
+    if ((s = begin_call(c, st, false)) != KRUX_OK) return s;
     const int64_t cap = 1 << 16;
     krux_hit* hits = (krux_hit*)ws(c, S_TUNE_HITS, (size_t)cap * sizeof(krux_hit), &s);
     int64_t* nh = (int64_t*)ws(c, S_TUNE_N, 256, &s);

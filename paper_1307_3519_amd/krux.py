@@ -25,7 +25,7 @@ EXPORTS = ("krux_create", "krux_destroy", "krux_last_error", "krux_threshold",
            "krux_test_grouped", "krux_test_multi",
            "krux_test_batched",
            "krux_timer_start", "krux_timer_read", "krux_autotune", "krux_load_tuning",
-           "krux_tuning_of")
+           "krux_tuning_of", "krux_set_pair_buffer_limits")
 
 
 class KruxError(RuntimeError):
@@ -95,6 +95,8 @@ def library():
                                   ctypes.POINTER(ctypes.c_double), P]
     lib.krux_load_tuning.restype = ctypes.c_int
     lib.krux_load_tuning.argtypes = [P, ctypes.c_char_p]
+    lib.krux_set_pair_buffer_limits.restype = ctypes.c_int
+    lib.krux_set_pair_buffer_limits.argtypes = [P, i64, i64]
     lib.krux_tuning_of.restype = ctypes.c_int
     lib.krux_tuning_of.argtypes = [P, i32, i32, ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
@@ -158,6 +160,12 @@ class Context:
         n = ctypes.c_int64()
         self._check(self.lib.krux_timer_read(self.h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    def set_pair_buffer_limits(self, candidates=0, missing_pairs=0):
+        """Caps (entries, 0 = built in) on the screened-pair buffers; pairs
+        beyond them are evaluated inside the scan kernels."""
+        self._check(self.lib.krux_set_pair_buffer_limits(self.h, int(candidates),
+                                                         int(missing_pairs)))
 
     # ------------------------------------------------------------------ tuning
     def autotune(self, ranks2, tiesum, geno, precision="fp16", cache_path=None):
