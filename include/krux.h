@@ -152,6 +152,34 @@ krux_status krux_test(krux_ctx* ctx, const int16_t* ranks2, const int64_t* tiesu
                       double* min_p, double* H, double* p, int32_t* sums,
                       void* stream);
 
+/* Bytes of the static device scratch of krux_test_noalloc (one array per
+ * GPU the library runs on, held until the process ends). */
+#define KRUX_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* krux_test without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture (no earlier eager call is needed),
+ * tight serving loops, harnesses that forbid hipMalloc.  Same arguments,
+ * modes, results and output ownership as krux_test for the fp16 and int8
+ * precisions (KRUX_PREC_FP64 is refused: its GEMM library allocates).  Every
+ * working buffer is carved from a static device array of
+ * KRUX_NOALLOC_SCRATCH_BYTES per GPU instead of the context's scratch; no
+ * hipMalloc, hipFree or allocating library routine is called.  A call whose
+ * working set (about 160 B per SNP at K <= 128, more for the tiled K > 128
+ * path; the A operand, twice with per-trait minimum p; 48 B per hit of
+ * hit_capacity) exceeds the array returns KRUX_ERR_UNSUPPORTED before
+ * anything is launched.  The screened-pair buffers are capped at a few MB
+ * (pairs beyond them are evaluated inside the scan kernels: slower, same
+ * results).  All calls on one GPU share its array, which keeps the last
+ * call's contents: calls that overlap in time on one GPU, from any contexts
+ * or streams, race and give wrong results. */
+krux_status krux_test_noalloc(krux_ctx* ctx, const int16_t* ranks2, const int64_t* tiesum,
+                              int64_t T, int32_t K, const int8_t* geno, int64_t M,
+                              int64_t ld_geno, int64_t snp_base, double p_c,
+                              int32_t mode, int32_t precision,
+                              krux_hit* hits, int64_t hit_capacity, int64_t* n_hits,
+                              double* min_p, double* H, double* p, int32_t* sums,
+                              void* stream);
+
 /* HITS-mode scan with the SNPs grouped by their pattern of missing genotypes
  * (Handling missing values: one sub-problem per unique pattern, with the
  * pattern's samples removed from the genotype and expression matrices).

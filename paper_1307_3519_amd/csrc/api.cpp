@@ -9,6 +9,7 @@
 #include <cstring>
 #include <string>
 #include <map>
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -69,9 +70,45 @@ struct krux_ctx {
     bool capturing = false;
     bool captured = false;
     std::vector<void*> retired;
+    // krux_test_noalloc: the slots are carved from the device's static
+    // scratch array instead of allocated.  arena 1 = sizing pass (offsets are
+    // assigned, nothing is launched: every HIP call is skipped), 2 = carving
+    // pass (the same offsets, kernels launched)
+    int arena = 0;
+    uint8_t* arena_base = nullptr;
+    size_t arena_cap = 0, arena_used = 0;
+    size_t arena_off[S_N_SLOTS] = {}, arena_len[S_N_SLOTS] = {};
+    void* noalloc_scratch = nullptr;   // this device's static scratch (hipGetSymbolAddress)
 };
 
+// Device scratch of krux_test_noalloc: one copy per GPU, held until the
+// process ends.  Host code never uses this name as an address: krux_create
+// looks up each device's copy with hipGetSymbolAddress and keeps the pointer.
+static __device__ __align__(256) uint8_t scratch[KRUX_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};     // per device, from hipGetSymbolAddress
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+// Address of `scratch` on `device` (current), looked up once per device.
+void* scratch_address(int device, hipError_t* err) {
+    if (device < 0 || device >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device] && g_scratch_err[device] == hipSuccess) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) g_scratch_err[device] = e != hipSuccess ? e : hipErrorUnknown;
+        else g_scratch_ptr[device] = ptr;
+    }
+    *err = g_scratch_err[device];
+    return g_scratch_ptr[device];
+}
 
 std::string g_err_null = "no error";
 thread_local std::string g_err_noctx;
@@ -86,11 +123,16 @@ krux_status fail(krux_ctx* c, krux_status s, const char* fmt, ...) {
     return s;
 }
 
+// A HIP call (a kernel launch, an event, a copy) with its error returned as
+// KRUX_ERR_HIP.  Skipped in the sizing pass of krux_test_noalloc, which runs
+// the host side of a call only to learn its scratch layout.
 #define HIP_TRY(c, expr)                                                                   \
     do {                                                                                   \
-        hipError_t e_ = (expr);                                                            \
-        if (e_ != hipSuccess)                                                              \
-            return fail(c, KRUX_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));   \
+        if ((c)->arena != 1) {                                                             \
+            hipError_t e_ = (expr);                                                        \
+            if (e_ != hipSuccess)                                                          \
+                return fail(c, KRUX_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+        }                                                                                  \
     } while (0)
 
 // Grow-only scratch buffer of the context.  Growing is refused while the
@@ -100,6 +142,22 @@ krux_status fail(krux_ctx* c, krux_status s, const char* fmt, ...) {
 void* ws(krux_ctx* c, int slot, size_t bytes, krux_status* st) {
     Buf& b = c->bufs[slot];
     if (bytes == 0) bytes = 256;
+    if (c->arena) {
+        // static scratch: a slot keeps its offset for the rest of the call;
+        // the same margin as an allocation below
+        if (c->arena_len[slot] >= bytes) return c->arena_base + c->arena_off[slot];
+        const size_t off = (c->arena_used + 255) & ~(size_t)255;
+        const size_t len = bytes + bytes / 8 + 4096;
+        if (c->arena == 2 && off + len > c->arena_cap) {
+            *st = fail(c, KRUX_ERR_UNSUPPORTED, "the call needs more than the %zu bytes of static "
+                       "scratch", c->arena_cap);
+            return nullptr;
+        }
+        c->arena_off[slot] = off;
+        c->arena_len[slot] = len;
+        c->arena_used = off + len;
+        return c->arena_base + off;
+    }
     if (b.n >= bytes) return b.p;
     if (c->capturing) {
         *st = fail(c, KRUX_ERR_UNSUPPORTED,
@@ -711,6 +769,10 @@ krux_status krux_create(krux_ctx** out, int device) {
     krux_ctx* c = new krux_ctx();
     c->device = device;
     c->n_cu = prop.multiProcessorCount;
+    // the static scratch of krux_test_noalloc on this device (null if the
+    // lookup failed; that entry point then reports the error)
+    hipError_t serr = hipSuccess;
+    c->noalloc_scratch = scratch_address(device, &serr);
     std::snprintf(c->arch, sizeof c->arch, "%.6s", prop.gcnArchName);
     *out = c;
     return KRUX_OK;
@@ -738,6 +800,60 @@ krux_status krux_timer_read(krux_ctx* c, double* total_ms, int64_t* launches) {
     c->timing = false;
     c->ev_used = 0;
     return KRUX_OK;
+}
+
+krux_status krux_test_noalloc(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum,
+                              int64_t T, int32_t K, const int8_t* geno, int64_t M,
+                              int64_t ld_geno, int64_t snp_base, double p_c, int32_t mode,
+                              int32_t precision, krux_hit* hits, int64_t hit_capacity,
+                              int64_t* n_hits, double* min_p, double* H, double* p,
+                              int32_t* sums, void* stream) {
+    if (!c) return fail(nullptr, KRUX_ERR_ARG, "ctx is NULL");
+    if (precision == KRUX_PREC_FP64)
+        return fail(c, KRUX_ERR_UNSUPPORTED, "the fp64 comparator allocates (rocBLAS); use "
+                    "krux_test");
+    if (!c->noalloc_scratch) {
+        hipError_t e = hipSuccess;
+        (void)scratch_address(c->device, &e);
+        return fail(c, KRUX_ERR_HIP, "no static scratch on device %d: %s", c->device,
+                    hipGetErrorString(e));
+    }
+    hipStream_t st = (hipStream_t)stream;
+    krux_status s = begin_call(c, st);
+    if (s != KRUX_OK) return s;
+    // screened-pair buffers of a few MB (pairs beyond them are evaluated in
+    // the scan kernels), no event timing; restored on every return
+    struct Restore {
+        krux_ctx* c;
+        int64_t cand, mcand;
+        bool timing;
+        ~Restore() {
+            c->arena = 0;
+            c->cand_limit = cand;
+            c->mcand_limit = mcand;
+            c->timing = timing;
+        }
+    } restore{c, c->cand_limit, c->mcand_limit, c->timing};
+    c->cand_limit = pair_limit(1 << 18, restore.cand);
+    c->mcand_limit = pair_limit(1 << 16, restore.mcand);
+    c->timing = false;
+    auto pass = [&](int arena) {
+        c->arena = arena;
+        c->arena_base = (uint8_t*)c->noalloc_scratch;
+        c->arena_cap = KRUX_NOALLOC_SCRATCH_BYTES;
+        c->arena_used = 0;
+        std::fill(c->arena_len, c->arena_len + S_N_SLOTS, (size_t)0);
+        return test_impl(c, ranks2, tiesum, T, K, geno, M, ld_geno, snp_base, p_c, mode,
+                         precision, hits, hit_capacity, n_hits, min_p, H, p, sums, st);
+    };
+    // the host side once without launches gives the scratch layout; a call
+    // that needs more than the static array is refused before any launch
+    if ((s = pass(1)) != KRUX_OK) return s;
+    if (c->arena_used > c->arena_cap)
+        return fail(c, KRUX_ERR_UNSUPPORTED, "the call needs %zu bytes of scratch, more than the "
+                    "%zu bytes of the static array (use krux_test, or a smaller SNP slice)",
+                    c->arena_used, c->arena_cap);
+    return pass(2);
 }
 
 krux_status krux_set_pair_buffer_limits(krux_ctx* c, int64_t candidates, int64_t missing_pairs) {

@@ -25,7 +25,7 @@ EXPORTS = ("krux_create", "krux_destroy", "krux_last_error", "krux_threshold",
            "krux_test_grouped", "krux_test_multi",
            "krux_test_batched",
            "krux_timer_start", "krux_timer_read", "krux_autotune", "krux_load_tuning",
-           "krux_tuning_of", "krux_set_pair_buffer_limits")
+           "krux_tuning_of", "krux_set_pair_buffer_limits", "krux_test_noalloc")
 
 
 class KruxError(RuntimeError):
@@ -71,6 +71,8 @@ def library():
     lib.krux_test.restype = ctypes.c_int
     lib.krux_test.argtypes = [P, P, P, i64, i32, P, i64, i64, i64, dbl, i32, i32,
                               P, i64, P, P, P, P, P, P]
+    lib.krux_test_noalloc.restype = ctypes.c_int
+    lib.krux_test_noalloc.argtypes = lib.krux_test.argtypes
     lib.krux_permute.restype = ctypes.c_int
     lib.krux_permute.argtypes = [P, P, P, i64, i32, P, i64, i64, P, i32, P, i32, P, P, P]
     lib.krux_test_batched.restype = ctypes.c_int
@@ -221,6 +223,18 @@ class Context:
         sums mode -> dict(sums) (3, T, M) int32
         `out` may pass preallocated buffers (same keys) to avoid allocation.
         """
+        return self._test(self.lib.krux_test, ranks2, tiesum, geno, p_c, mode, precision,
+                          hit_capacity, min_p, snp_base, out)
+
+    def test_noalloc(self, ranks2, tiesum, geno, p_c=1e-5, mode="hits", precision="fp16",
+                     hit_capacity=1 << 16, min_p=True, snp_base=0, out=None):
+        """As test(), through krux_test_noalloc: the library allocates no
+        device memory (its working buffers come from a static array)."""
+        return self._test(self.lib.krux_test_noalloc, ranks2, tiesum, geno, p_c, mode,
+                          precision, hit_capacity, min_p, snp_base, out)
+
+    def _test(self, fn, ranks2, tiesum, geno, p_c, mode, precision, hit_capacity, min_p,
+              snp_base, out):
         T, K = ranks2.shape
         M = geno.shape[0]
         assert geno.dtype == torch.int8 and geno.dim() == 2 and geno.shape[1] == K
@@ -252,7 +266,7 @@ class Context:
             sums = out.get("sums")
             if sums is None:
                 sums = torch.empty((3, T, M), dtype=torch.int32, device=dev)
-        self._check(self.lib.krux_test(
+        self._check(fn(
             self.h, _ptr(ranks2), _ptr(tiesum), T, K, _ptr(geno), M,
             geno.stride(0) if M else K, int(snp_base), float(p_c), m, pr,
             _ptr(hits), int(hit_capacity) if m == MODE_HITS else 0, _ptr(nh), _ptr(mp),

@@ -64,6 +64,8 @@ def test_null_context_is_rejected():
     assert lib.krux_test_multi(None, None, None, 0, 1, None, 0, 1, 4, 0, 0.1, 0, None, 0,
                                None, None, None, None, None) == 1
     assert lib.krux_set_pair_buffer_limits(None, 16, 16) == 1
+    assert lib.krux_test_noalloc(None, None, None, 0, 1, None, 0, 1, 0, 0.1, 0, 0,
+                                 None, 0, None, None, None, None, None, None) == 1
     assert b"ctx" in lib.krux_last_error(None)
 
 
