@@ -24,7 +24,7 @@ SOURCES = ["scan_f16_diag.hip", "scan_f16_miss.hip", "scan_f16_full.hip", "scan_
            "scan_cand.hip", "scan_tiled_f16.hip", "scan_tiled_i8.hip", "rank.hip", "prep.hip", "scan.hip", "sort.hip", "group.hip", "multi.hip", "fp64.hip", "api.cpp"]
 
 
-HEADERS = [os.path.join(CSRC, h) for h in ("kx_common.h", "kx_args.h", "kx_host.h",
+HEADERS = [os.path.join(CSRC, h) for h in ("kx_common.h", "kx_args.h", "kx_host.h", "radix.h",
                                             "scan_kernel.h", "scan_tiled.h")] + [
     os.path.join(HERE, "..", "include", "krux.h")]
 

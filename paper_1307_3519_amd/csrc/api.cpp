@@ -548,21 +548,27 @@ double screen_level_for_min_p(double p_c, int64_t M) {
     return std::max(p_c, std::min(1.0, 64.0 / (double)std::max<int64_t>(M, 1)));
 }
 
+int bit_length(int64_t v) {
+    int b = 0;
+    while (b < 63 && ((int64_t)1 << b) <= v) ++b;
+    return b;
+}
+
 // The staged hits (appended in any order) sorted by (row, snp) into the
-// caller's buffer; *n_hits receives the true count.
+// caller's buffer; *n_hits receives the true count.  Rows are below `rows`,
+// SNP numbers below `snp_end`.
 krux_status sort_stage(krux_ctx* c, const kx::HitRec* stage, const unsigned long long* nh,
                        int64_t cap, krux_hit* hits, int64_t* n_hits, int64_t rows,
-                       hipStream_t st) {
+                       int64_t snp_end, hipStream_t st) {
     krux_status s = KRUX_OK;
     size_t tmp_bytes = kx_sort_tmp_bytes(std::max<int64_t>(cap, 1));
     unsigned long long* keys = (unsigned long long*)ws(c, S_KEYS, (size_t)std::max<int64_t>(cap, 1) * 16, &s);
     uint32_t* idx = (uint32_t*)ws(c, S_IDX, (size_t)std::max<int64_t>(cap, 1) * 8, &s);
     void* tmp = ws(c, S_SORT_TMP, tmp_bytes, &s);
     if (s != KRUX_OK) return s;
-    int tb = 1;
-    while (tb < 64 && ((int64_t)1 << tb) < std::max<int64_t>(rows, 1)) ++tb;
     HIP_TRY(c, kx_sort_hits(stage, nh, cap, keys, idx, tmp, tmp_bytes, (kx::HitRec*)hits, n_hits,
-                            std::min(64, 32 + tb), st));
+                            std::min(32, bit_length(rows - 1)), std::min(32, bit_length(snp_end - 1)),
+                            st));
     return KRUX_OK;
 }
 
@@ -724,7 +730,7 @@ krux_status test_impl(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum,
         HIP_TRY(c, kx_launch_bits_to_double(minp, T, min_p, st));
     }
     // deterministic order of the hit list
-    return sort_stage(c, stage, nh, cap, hits, n_hits, T, st);
+    return sort_stage(c, stage, nh, cap, hits, n_hits, T, snp_base + M, st);
 }
 
 }  // namespace
@@ -988,7 +994,7 @@ krux_status permute_impl(krux_ctx* c, const int16_t* ranks2, const int64_t* ties
             return s;
         HIP_TRY(c, kx_launch_bits_to_double(minp, V, min_p, st));
     }
-    if (n_hits) return sort_stage(c, stage, nh, hit_capacity, hits, n_hits, V, st);
+    if (n_hits) return sort_stage(c, stage, nh, hit_capacity, hits, n_hits, V, M, st);
     return KRUX_OK;
 }
 
@@ -1190,7 +1196,8 @@ krux_status krux_test_grouped(krux_ctx* c, const int16_t* ranks2, const int64_t*
                                          grid, st));
         if (min_p) HIP_TRY(c, kx_launch_min_merge(pmin, acc, T, grid, st));
     }
-    if ((s = sort_stage(c, stage, cnt + 1, cap, hits, n_hits, T, st)) != KRUX_OK) return s;
+    if ((s = sort_stage(c, stage, cnt + 1, cap, hits, n_hits, T, snp_base + M, st)) != KRUX_OK)
+        return s;
     HIP_TRY(c, kx_launch_set_counts(n_hits, cnt + 2, cnt + 1, cap, st));
     if (min_p) HIP_TRY(c, hipMemcpyAsync(min_p, acc, (size_t)T * 8, hipMemcpyDeviceToDevice, st));
     return KRUX_OK;
@@ -1306,7 +1313,7 @@ krux_status krux_test_multi(krux_ctx* c, const int16_t* ranks2, const int64_t* t
     }
     if (mode == KRUX_MODE_HITS) {
         if (a.minp_bits) HIP_TRY(c, kx_launch_bits_to_double(a.minp_bits, T, min_p, st));
-        return sort_stage(c, stage, nh, hit_capacity, hits, n_hits, T, st);
+        return sort_stage(c, stage, nh, hit_capacity, hits, n_hits, T, snp_base + M, st);
     }
     return KRUX_OK;
 }

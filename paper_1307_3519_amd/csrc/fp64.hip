@@ -290,9 +290,13 @@ krux_status kx_fp64_test(krux_ctx* c, const int16_t* ranks2, const int64_t* ties
     uint32_t* idx = (uint32_t*)kx_ws(c, kx_slot_idx(), (size_t)std::max<int64_t>(cap, 1) * 8, &s);
     void* tmp = kx_ws(c, kx_slot_sort_tmp(), tmp_bytes, &s);
     if (s != KRUX_OK) return s;
-    int tb = 1;
-    while (tb < 31 && ((int64_t)1 << tb) < std::max<int64_t>(T, 1)) ++tb;
+    // digits that can be non-zero: traits below T, SNP numbers below snp_base + M
+    auto bits = [](int64_t v) {
+        int b = 0;
+        while (b < 32 && ((int64_t)1 << b) <= v) ++b;
+        return b;
+    };
     e = kx_sort_hits(stage, nh, cap, keys, idx, tmp, tmp_bytes, (kx::HitRec*)hits, n_hits,
-                     std::min(64, 32 + tb), st);
+                     bits(T - 1), bits(snp_base + M - 1), st);
     return hip_fail(c, e, "sort hits");
 }

@@ -51,7 +51,8 @@ hipError_t kx_launch_expand_i8(const int8_t* G, int gstride, const kx::SnpInfo* 
 size_t kx_sort_tmp_bytes(int64_t cap);
 hipError_t kx_sort_hits(const kx::HitRec* stage, const unsigned long long* n_hits, int64_t cap,
                         unsigned long long* keys, uint32_t* idx, void* tmp, size_t tmp_bytes,
-                        kx::HitRec* out, int64_t* n_out, int key_bits, hipStream_t st);
+                        kx::HitRec* out, int64_t* n_out, int trait_bits, int snp_bits,
+                        hipStream_t st);
 hipError_t kx_launch_miss_keys(const int8_t* geno, int64_t M, int64_t ld, int K, uint64_t* key,
                                int grid, hipStream_t st);
 size_t kx_group_tmp_bytes(int64_t M);

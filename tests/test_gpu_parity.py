@@ -164,6 +164,26 @@ def test_hits_planted_and_capacity(kx):
     del planted
 
 
+@pytest.mark.parametrize("prec", ["fp16", "int8"])
+def test_hits_many_sorted(kx, prec):
+    # ~1.2e5 hits: many tiles of the hit sort, two digits of trait and SNP
+    # numbers each, snp_base pushing SNP numbers past 2^16
+    say("hits many", prec)
+    x, g = _inputs(404, 400, 102, 6000)
+    r, ts = _ranks(kx, x)
+    p_c = 0.05
+    res = kx.test(r, ts, _dev(g), p_c=p_c, mode="hits", precision=prec, hit_capacity=1 << 18,
+                  min_p=False, snp_base=70000)
+    torch.cuda.synchronize()
+    from paper_1307_3519_amd.krux import unpack_hits
+    n, h = unpack_hits(res)
+    o = oracle.scan(x, g, p_cs=(p_c,), hits=True)
+    assert n == o["n_hits"] > 100000
+    assert np.array_equal(h["trait"], o["hits"]["trait"])
+    assert np.array_equal(h["snp"] - 70000, o["hits"]["snp"])
+    assert_H(h["H"], o["hits"]["H"], "hit H")
+
+
 def test_degenerate_inputs(kx):
     say("degenerate")
     K = 40

@@ -1,10 +1,12 @@
-"""HIP graph capture of the batched entry points.
+"""HIP graph capture of the entry points that enqueue kernels only.
 
-krux_permute (all permutations of one call) and krux_test_batched (all
-cohorts) enqueue only kernels on the caller's stream, with no host
-synchronisation, so a call can be captured once into a HIP graph and the
-graph replayed as one launch.  Each replay is checked against the eager
-result, with unrelated eager work of the same library between replays.
+krux_permute (all permutations of one call), krux_test_batched (all
+cohorts), krux_test in hits mode, the permuted hit lists with the FDR curve
+and krux_test_noalloc enqueue only kernels on the caller's stream (no host
+synchronisation, no memset: the hit sort is the library's own radix sort),
+so a call can be captured once into a HIP graph and replayed as one launch.
+Each replay is checked against the eager result, with unrelated eager work
+of the same library between replays.
 """
 import numpy as np
 import pytest
@@ -111,3 +113,114 @@ def test_batched_cohorts_graph_replays(kx):
             assert np.array_equal(b["min_p"].cpu().numpy(), mp)
         _other_work(kx)
         torch.cuda.synchronize()
+
+
+def _same_hits(a, b):
+    from paper_1307_3519_amd.krux import unpack_hits
+    na, ha = unpack_hits(a)
+    nb, hb = unpack_hits(b)
+    assert na == nb
+    for f in ("trait", "snp", "H", "p"):
+        assert np.array_equal(ha[f], hb[f]), f
+    return na
+
+
+def test_hits_graph_replays(kx):
+    print("[case] hits graph", flush=True)
+    K, T, M = 102, 400, 3000
+    x, g = _inputs(61, T, K, M, 0.01)
+    xd, gd = _dev(x), _dev(g)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        r, ts, _ = kx.rank(xd)
+        eager = kx.test(r, ts, gd, p_c=1e-3, hit_capacity=1 << 14, min_p=True)
+    torch.cuda.synchronize()
+    ref_mp = eager["min_p"].cpu().numpy().copy()
+    out = {k: eager[k].clone() if torch.is_tensor(eager[k]) else eager[k] for k in eager}
+    ref = dict(out)
+    ref["n_hits_t"] = eager["n_hits_t"].clone()
+    ref["hits_raw"] = eager["hits_raw"].clone()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        rr, tt, _ = kx.rank(xd, out=(r, ts))
+        kx.test(rr, tt, gd, p_c=1e-3, hit_capacity=1 << 14, min_p=True, out=out)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        out["n_hits_t"].fill_(-1)
+        out["hits_raw"].fill_(0)
+        out["min_p"].fill_(-1.0)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert _same_hits(out, ref) > 0, rep
+        assert np.array_equal(out["min_p"].cpu().numpy(), ref_mp), rep
+        _other_work(kx)
+        torch.cuda.synchronize()
+
+
+def test_fdr_curve_graph_replays(kx):
+    print("[case] fdr graph", flush=True)
+    K, T, M, P = 102, 200, 1500, 6
+    x, g = _inputs(63, T, K, M)
+    perms = _dev(datagen.permutations(datagen.streams(64)["perms"], P, K))
+    xd, gd = _dev(x), _dev(g)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        r, ts, _ = kx.rank(xd)
+        real = kx.test(r, ts, gd, p_c=1e-3, hit_capacity=1 << 13, min_p=False)
+        ph = kx.permute_hits(r, ts, gd, perms, p_c=1e-3, hit_capacity=1 << 14)
+        fdr = kx.fdr_curve(real, ph, P)
+    torch.cuda.synchronize()
+    n_real = int(real["n_hits_t"].item())
+    assert n_real > 0 and int(ph["n_hits_t"].item()) > 0
+    ref = fdr[:n_real].cpu().numpy().copy()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        kx.test(r, ts, gd, p_c=1e-3, hit_capacity=1 << 13, min_p=False, out=real)
+        ph2 = kx.permute_hits(r, ts, gd, perms, p_c=1e-3, hit_capacity=1 << 14)
+        f2 = kx.fdr_curve(real, ph2, P)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        f2.fill_(-1.0)
+        ph2["n_hits_t"].fill_(-1)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert _same_hits(ph2, ph) > 0, rep
+        assert np.array_equal(f2[:n_real].cpu().numpy(), ref), rep
+        _other_work(kx)
+        torch.cuda.synchronize()
+
+
+def test_noalloc_captured_on_a_fresh_context():
+    # krux_test_noalloc needs no earlier eager call: its buffers are static
+    from paper_1307_3519_amd import krux
+    print("[case] noalloc graph", flush=True)
+    ctx = krux.Context(0)
+    try:
+        K, T, M = 102, 500, 4000
+        x, g = _inputs(9, T, K, M, 0.01)
+        xd, gd = _dev(x), _dev(g)
+        r, ts, _ = ctx.rank(xd)
+        out = {"hits_raw": torch.empty((1 << 14) * 24, dtype=torch.uint8, device="cuda"),
+               "n_hits_t": torch.zeros(1, dtype=torch.int64, device="cuda"),
+               "min_p": torch.empty(T, dtype=torch.float64, device="cuda")}
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            res = ctx.test_noalloc(r, ts, gd, p_c=1e-3, hit_capacity=1 << 14, out=out)
+        torch.cuda.synchronize()
+        ref = ctx.test(r, ts, gd, p_c=1e-3, hit_capacity=1 << 14, min_p=True)
+        torch.cuda.synchronize()
+        for rep in range(3):
+            out["n_hits_t"].fill_(-1)
+            out["min_p"].fill_(-1.0)
+            graph.replay()
+            torch.cuda.synchronize()
+            assert _same_hits(res, ref) > 0, rep
+            assert torch.equal(res["min_p"], ref["min_p"]), rep
+            # other work on the static array between replays
+            ctx.test_noalloc(r, ts, gd[:500], p_c=1e-2, hit_capacity=1 << 10)
+            torch.cuda.synchronize()
+    finally:
+        ctx.close()
