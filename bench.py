@@ -34,7 +34,11 @@ Workloads (--workload; seeded synthetic data shaped like the paper's
       2% of the traits (1-5 each); hits at p < 1e-5 plus the per-trait minimum
       p, timed beside the same traits without NaN values
 
-Prints ONE JSON line on stdout; progress goes to stderr.
+The default run (paper_scale_hits) also measures precision_K500, permutations
+and cohorts_missing with fewer steps and reports them under "other_configs",
+and checks the paper-scale results against the CPU oracle on a prefix of the
+SNPs ("parity", "parity_checks").  Prints ONE JSON line on stdout; progress
+goes to stderr.
 """
 import argparse
 import json
@@ -122,10 +126,24 @@ def roofline(kernel, pairs, flops_per_pair, kern_ms, peak, unit, traffic=None):
             "flops_per_pair": flops_per_pair}
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def oracle_baseline(args, T, n_total, label, run_sample):
     """Times the oracle on a bounded prefix of the SNPs: run_sample(n) scans
-    all traits against the first n SNPs."""
+    all traits against the first n SNPs and returns the oracle's result.
+    Returns (cpu_baseline dict, that result for the timed sample, n); the
+    timed sample runs on all the oracle's threads, a smaller one on one."""
     import oracle
+    threads = oracle.num_threads()
     probe = max(1, min(n_total, 200))
     t0 = time.perf_counter()
     run_sample(probe)
@@ -133,13 +151,56 @@ def oracle_baseline(args, T, n_total, label, run_sample):
     n_snp = int(min(n_total, max(probe, args.cpu_seconds * rate / max(T, 1))))
     log("oracle baseline: %d traits x %d SNPs (probe %.3e pairs/s)" % (T, n_snp, rate))
     t0 = time.perf_counter()
-    run_sample(n_snp)
+    res = run_sample(n_snp)
     dt = time.perf_counter() - t0
-    log("oracle: %.3e pairs/s on %d threads" % (T * n_snp / dt, oracle.num_threads()))
-    return {"value": T * n_snp / dt, "unit": "pairs/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
+    log("oracle: %.3e pairs/s on %d threads" % (T * n_snp / dt, threads))
+    # one thread, on about a quarter of the time budget
+    n1 = int(min(n_snp, max(1, args.cpu_seconds / 4.0 * (rate / threads) / max(T, 1))))
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        run_sample(n1)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(threads)
+    log("oracle: %.3e pairs/s on 1 thread" % (T * n1 / dt1))
+    base = {"value": T * n_snp / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": "all %d traits x the first %d of %d SNPs (%s), %.1f s"
-                      % (T, n_snp, n_total, label, dt)}
+                      % (T, n_snp, n_total, label, dt),
+            "one_thread": {"value": T * n1 / dt1, "unit": "pairs/s",
+                           "sample": "all %d traits x the first %d SNPs, %.1f s" % (T, n1, dt1)}}
+    return base, res, n_snp
+
+
+def oracle_rate(*args):
+    return oracle_baseline(*args)[0]
+
+
+def hits_match(got, want, snp_offset=0):
+    """Identical (trait, snp) lists, H within 1e-12 relative, p within 1e-10
+    relative (absolute floor 1e-300)."""
+    import numpy as np
+    if len(got["trait"]) != len(want["trait"]):
+        return False
+    if not (np.array_equal(got["trait"], want["trait"])
+            and np.array_equal(got["snp"] - snp_offset, want["snp"])):
+        return False
+    rel = np.abs(got["H"] - want["H"]) / np.maximum(np.abs(want["H"]), 1e-300)
+    dp = np.abs(got["p"] - want["p"]) <= np.maximum(1e-10 * np.abs(want["p"]), 1e-300)
+    return bool(rel.max(initial=0.0) <= 1e-12 and dp.all())
+
+
+def min_p_match(got, want):
+    import numpy as np
+    return bool(np.all(np.abs(got - want) <= np.maximum(1e-10 * np.abs(want), 1e-300)))
+
+
+def oracle_scan_hits(oracle, x, g, p_c, min_p=True):
+    """The oracle's hits (+ minimum p) in one pass, with a hit buffer large
+    enough for the null rate and the planted pairs."""
+    cap = max(1 << 16, int(x.shape[0] * g.shape[0] * p_c * 20))
+    return oracle.scan(x, g, p_cs=(p_c,), hits=True, min_p=min_p, hit_cap=cap)
 
 
 # ---------------------------------------------------------------- workloads
@@ -173,6 +234,7 @@ def paper_scale_hits(args, ctx, torch, np, datagen, krux):
     pairs = float(T) * float(M)
     value = pairs / (ms / 1e3)
     hits16 = krux.unpack_hits(res)
+    minp = {"fp16": None if args.no_minp else res["min_p"].cpu().numpy()}
     planted = set(map(tuple, w["planted"][:, :2].tolist()))
     found = set(zip(hits16[1]["trait"].tolist(), hits16[1]["snp"].tolist()))
     log("fp16: %.3f ms/step, %.3e pairs/s, hits %d, planted recovered %d/%d"
@@ -195,6 +257,7 @@ def paper_scale_hits(args, ctx, torch, np, datagen, krux):
         log("fp64 GEMM comparator: 1 warmup + 2 timed steps")
         ms64, res64, _, _ = runner.run(step_for("fp64"), 2, 1)
         same = same_hits(krux.unpack_hits(res64), hits16)
+        minp["fp64"] = None if args.no_minp else res64["min_p"].cpu().numpy()
         log("fp64: %.3f ms/step, %.3e pairs/s, identical hits %s" % (ms64, pairs / (ms64 / 1e3), same))
         out["fp64_gemm"] = {"value": pairs / (ms64 / 1e3), "unit": "pairs/s", "ms_per_step": ms64,
                             "identical_hits": same,
@@ -204,6 +267,7 @@ def paper_scale_hits(args, ctx, torch, np, datagen, krux):
         log("int8 path: %d warmup + %d timed steps" % (max(1, args.warmup // 2), n8))
         ms8, res8, k8ms, _ = runner.run(step_for("int8"), n8, max(1, args.warmup // 2))
         same8 = same_hits(krux.unpack_hits(res8), hits16)
+        minp["int8"] = None if args.no_minp else res8["min_p"].cpu().numpy()
         out["int8"] = {"value": pairs / (ms8 / 1e3), "unit": "pairs/s", "ms_per_step": ms8,
                        "kernel_ms": k8ms,
                        "kernel_tops": pairs * flops_per_pair / (k8ms / 1e3) / 1e12,
@@ -211,11 +275,40 @@ def paper_scale_hits(args, ctx, torch, np, datagen, krux):
                        "identical_hits": same8}
         log("int8: %.3f ms/step, identical hits %s" % (ms8, same8))
 
+    if not args.no_minp:
+        # per-trait minimum p of the three paths on the whole workload
+        for prec in ("int8", "fp64"):
+            if minp.get(prec) is not None:
+                out["int8" if prec == "int8" else "fp64_gemm"]["identical_min_p"] = bool(
+                    np.array_equal(minp[prec], minp["fp16"]))
     if not args.no_cpu:
         import oracle
-        out["cpu_baseline"] = oracle_baseline(
+        base, o, n = oracle_baseline(
             args, T, M, "hits at p<1e-5 + per-trait min p",
-            lambda n: oracle.scan(w["expr"], w["geno"][:n], p_cs=(p_c,), hits=True, min_p=True))
+            lambda n: oracle_scan_hits(oracle, w["expr"], w["geno"][:n], p_c))
+        out["cpu_baseline"] = base
+        # parity with the oracle at this shape: (1) the hits of the whole
+        # run that fall in the oracle's SNP prefix, (2) a GPU scan of that
+        # prefix (hits and per-trait minimum p), (3) the minima of the
+        # three GPU paths on the whole workload against each other
+        h = hits16[1]
+        sel = h["snp"] < n
+        pre = {k: v[sel] for k, v in h.items()}
+        r, ts, _ = ctx.rank(x)
+        sub = ctx.test(r, ts, g[:n], p_c=p_c, mode="hits", precision="fp16",
+                       hit_capacity=1 << 17, min_p=True)
+        n_sub, h_sub = krux.unpack_hits(sub)
+        checks = {"oracle_snps": n, "oracle_hits": int(o["n_hits"]),
+                  "full_run_hits_in_prefix": hits_match(pre, o["hits"]),
+                  "prefix_scan_hits": n_sub == o["n_hits"] and hits_match(h_sub, o["hits"]),
+                  "prefix_scan_min_p": min_p_match(sub["min_p"].cpu().numpy(), o["min_p"])}
+        if not args.no_minp and not args.no_compare:
+            checks["min_p_fp16_eq_fp64_eq_int8"] = bool(
+                np.array_equal(minp["fp16"], minp["fp64"])
+                and np.array_equal(minp["fp16"], minp["int8"]))
+        out["parity"] = all(v for k, v in checks.items() if isinstance(v, bool))
+        out["parity_checks"] = checks
+        log("parity with the oracle: %s %s" % (out["parity"], checks))
     out["paper_context"] = {"kruX_matlab_single_cpu_pairs_per_s": 4.2e6,
                             "note": "derived from the paper's ~2,500 s for 19,610 x 530,222 "
                                     "pairs on one CPU; another machine and method, context only"}
@@ -279,7 +372,7 @@ def precision_k500(args, ctx, torch, np, datagen, krux):
     log("sums slice identical: %s" % out["sums_slice"])
     if not args.no_cpu:
         import oracle
-        out["cpu_baseline"] = oracle_baseline(
+        out["cpu_baseline"] = oracle_rate(
             args, T, M, "hits at p<1e-5 + per-trait min p",
             lambda n: oracle.scan(w["expr"], w["geno"][:n], p_cs=(p_c,), hits=True, min_p=True))
     return out
@@ -378,7 +471,7 @@ def permutations(args, ctx, torch, np, datagen, krux):
                         "outputs": "real hit list, permuted hit lists, FDR at every real hit"}
     if not args.no_cpu:
         import oracle
-        out["cpu_baseline"] = oracle_baseline(
+        out["cpu_baseline"] = oracle_rate(
             args, T, M, "one permutation, counts + min p",
             lambda n: oracle.scan(w["expr"], w["geno"][:n], p_cs=p_cs, perm=w["perms"][0],
                                   min_p=True))
@@ -433,7 +526,7 @@ def cohorts_missing(args, ctx, torch, np, datagen, krux):
     if not args.no_cpu:
         import oracle
         c0 = cs[2]          # the K = 102 cohort
-        out["cpu_baseline"] = oracle_baseline(
+        out["cpu_baseline"] = oracle_rate(
             args, c0["T"], M, "cohort K=%d, hits" % c0["K"],
             lambda n: oracle.scan(c0["expr"], c0["geno"][:n], p_cs=(p_c,), hits=True))
     return out
@@ -485,7 +578,7 @@ def missing_expression(args, ctx, torch, np, datagen, krux):
         import oracle
         rows = np.flatnonzero(np.isnan(x_nan).any(axis=1))
         xs = x_nan[rows]
-        out["cpu_baseline"] = oracle_baseline(
+        out["cpu_baseline"] = oracle_rate(
             args, len(rows), M, "the traits with NaN values, hits at p<1e-5 + per-trait min p",
             lambda n: oracle.scan(xs, w["geno"][:n], p_cs=(p_c,), hits=True, min_p=True))
     return out
@@ -539,7 +632,7 @@ def sample_missing(args, ctx, torch, np, datagen, krux):
     out["n_hits"] = b[0]
     if not args.no_cpu:
         import oracle
-        out["cpu_baseline"] = oracle_baseline(
+        out["cpu_baseline"] = oracle_rate(
             args, T, M, "hits at p<1e-5" + (" + per-trait min p" if minp else ""),
             lambda n: oracle.scan(w["expr"], g_np[:n], p_cs=(p_c,), hits=True, min_p=minp))
     return out
@@ -604,6 +697,9 @@ def multi_allelic(args, ctx, torch, np, datagen, krux):
     return out
 
 
+# keys of a workload's line that its sub-object in the default line leaves out
+SUB_DROP = ("n_gpus", "higher_is_better", "scaling", "vs_baseline", "data")
+
 WORKLOADS = {"paper_scale_hits": paper_scale_hits, "precision_K500": precision_k500,
              "permutations": permutations, "cohorts_missing": cohorts_missing,
              "missing_expression": missing_expression, "sample_missing": sample_missing,
@@ -623,6 +719,10 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the fp64 / int8 paths")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-minp", action="store_true", help="hit list only (no per-trait min p)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="paper_scale_hits only: skip the other three configurations "
+                         "(precision_K500, permutations, cohorts_missing) that the default "
+                         "run adds as sub-objects of the JSON line")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 256 MiB device-to-device copy first (reference for "
                          "scaling the HBM byte counters of a profiler run)")
@@ -647,6 +747,19 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     out = WORKLOADS[args.workload](args, ctx, torch, np, datagen, krux)
+    if args.workload == "paper_scale_hits" and not args.no_extra:
+        # the other configurations of the method, measured in the same run
+        # (fewer steps, no CPU baseline) and reported beside the headline
+        import copy
+        out["other_configs"] = {}
+        for name in ("precision_K500", "permutations", "cohorts_missing"):
+            sub = copy.copy(args)
+            sub.no_cpu = True
+            sub.T = sub.M = sub.P = None
+            sub.steps, sub.warmup = min(args.steps, 10), min(args.warmup, 3)
+            log("configuration %s" % name)
+            r = WORKLOADS[name](sub, ctx, torch, np, datagen, krux)
+            out["other_configs"][name] = {k: v for k, v in r.items() if k not in SUB_DROP}
     ctx.close()
     print(json.dumps(out), flush=True)
 

@@ -59,6 +59,8 @@ def _load(path=None):
         P = ctypes.c_void_p
         i64, i32, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_set_num_threads.restype = None
+        lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
         lib.oracle_rational_to_double_parts.restype = dbl
         lib.oracle_rational_to_double_parts.argtypes = [ctypes.c_uint64] * 4
         lib.oracle_pvalue.restype = dbl
@@ -82,6 +84,11 @@ def _ptr(a):
 
 def num_threads():
     return _load().oracle_num_threads()
+
+
+def set_num_threads(n):
+    """Threads of later scans (OpenMP)."""
+    _load().oracle_set_num_threads(int(n))
 
 
 def rational_to_double(num, den):

@@ -45,8 +45,10 @@
 
 typedef unsigned __int128 u128;
 
-/* Number of OpenMP threads a scan will use. */
+/* Number of OpenMP threads a scan will use, and a way to change it (the
+ * benchmark times the oracle on all cores and on one). */
 int oracle_num_threads(void) { return omp_get_max_threads(); }
+void oracle_set_num_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 
 /* ------------------------------------------------------------------------ */
 /* Exact rational -> nearest double (round half to even).                    */
