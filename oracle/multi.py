@@ -70,25 +70,24 @@ def one_pair(x, g, n_classes):
     0..n_classes-1 -> dict(H, p, df, n, s2, tiesum, kobs); s2 holds the
     groups' sums of doubled midranks over the kept samples."""
     x = np.asarray(x, dtype=np.float32)
-    g = np.asarray(g)
-    keep = [k for k in range(len(x)) if not np.isnan(x[k]) and 0 <= int(g[k]) < n_classes]
-    vals = [float(x[k]) for k in keep]
+    g = np.asarray(g).astype(np.int64)
+    keep = np.flatnonzero(~np.isnan(x) & (g >= 0) & (g < n_classes))
+    vals = x[keep].astype(np.float64)
     kp = len(keep)
-    a2 = {}
-    for k, v in zip(keep, vals):
-        less = sum(1 for w in vals if w < v)
-        eq = sum(1 for w in vals if w == v)
-        a2[k] = 2 * less + eq + 1
+    # doubled midrank of each kept sample by counting: 2 #below + #equal + 1
+    less = (vals[None, :] < vals[:, None]).sum(axis=1)
+    eq = (vals[None, :] == vals[:, None]).sum(axis=1)
+    a2 = [int(v) for v in 2 * less + eq + 1]
     tiesum = 0
-    for v in set(vals):
-        t = vals.count(v)
+    for v in set(vals.tolist()):
+        t = int((vals == v).sum())
         tiesum += t ** 3 - t
     n = [0] * n_classes
     s2 = [0] * n_classes
-    for k in keep:
+    for j, k in enumerate(keep):
         c = int(g[k])
         n[c] += 1
-        s2[c] += a2[k]
+        s2[c] += a2[j]
     nonempty = sum(1 for c in n if c > 0)
     df = nonempty - 1 if nonempty > 0 else 0
     E = kp ** 3 - kp - tiesum

@@ -182,7 +182,8 @@ MULTI_MUTATIONS = {
     "df_off_by_one": ("df = nonempty - 1 if nonempty > 0 else 0", "df = nonempty if nonempty > 0 else 0"),
     "odd_tail_no_erfc": ("total = math.erfc(math.sqrt(x))", "total = 0.0"),
     "even_tail_sum_short": ("for k in range(1, df // 2):", "for k in range(1, df // 2 - 1):"),
-    "missing_code_kept": ("0 <= int(g[k]) < n_classes", "int(g[k]) < n_classes"),
+    "missing_code_kept": ("(g >= 0) & (g < n_classes)", "(g < n_classes)"),
+    "rank_ties_not_averaged": ("2 * less + eq + 1", "2 * less + 1"),
     "scan_hit_at_threshold": ('o["H"] > threshold(p_c, o["df"])', 'o["H"] >= threshold(p_c, o["df"])'),
     "scan_df_plus_one": ('threshold(p_c, o["df"])', 'threshold(p_c, o["df"] + 1)'),
     "scan_df_minus_one": ('threshold(p_c, o["df"])', 'threshold(p_c, max(o["df"] - 1, 1))'),
