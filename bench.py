@@ -507,18 +507,47 @@ def cohorts_missing(args, ctx, torch, np, datagen, krux):
                                 min_p=False)
 
     steps = max(1, min(args.steps, 5))
-    log("cohorts: 1 warmup + %d timed steps" % steps)
-    ms, res, kms, _ = runner.run(step, steps, 1)
+    log("cohorts: 1 warmup + %d timed steps (eager)" % steps)
+    ms_eager, res, kms, _ = runner.run(step, steps, 1)
     pairs = float(sum(c["T"] for c in cs)) * M
     flops = float(sum(c["T"] * 4 * c["K"] for c in cs)) * M
     n_hits = [krux.unpack_hits(r)[0] for r in res]
-    log("cohorts: %.1f ms/step, %.3e pairs/s, hits %s" % (ms, pairs / (ms / 1e3), n_hits))
+    log("cohorts eager: %.1f ms/step, %.3e pairs/s, hits %s" % (ms_eager, pairs / (ms_eager / 1e3),
+                                                              n_hits))
+    # the whole step (ranks of every cohort, every cohort's scan) captured
+    # once into a HIP graph and replayed as one launch per step
+    ranks = [ctx.rank(d["x"]) for d in dev]
+    gbufs = ctx.test_batched_buffers([dict(ranks2=r[0]) for r in ranks], hit_capacity=1 << 16)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batch = []
+        for d, (r, ts, _) in zip(dev, ranks):
+            rr, tt, _ = ctx.rank(d["x"], out=(r, ts))
+            batch.append(dict(ranks2=rr, tiesum=tt, geno=d["geno"]))
+        ctx.test_batched(batch, M, p_c=p_c, precision="fp16", hit_capacity=1 << 16, min_p=False,
+                         out=gbufs)
+    graph.replay()
+    torch.cuda.synchronize()
+    same = all(same_hits(krux.unpack_hits(a), krux.unpack_hits(b)) for a, b in zip(gbufs, res))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    same = same and all(same_hits(krux.unpack_hits(a), krux.unpack_hits(b))
+                        for a, b in zip(gbufs, res))
+    log("cohorts, one graph launch per step: %.1f ms/step, %.3e pairs/s, hits identical %s"
+        % (ms, pairs / (ms / 1e3), same))
     out = base_line(args, "SNP-trait pairs/sec over uneven cohorts", pairs / (ms / 1e3), "pairs/s",
                     ms, "f16", {"workload": "cohorts_missing", "K": [c["K"] for c in cs],
                                 "T": [c["T"] for c in cs], "M": M, "p_missing": 0.02, "p_c": p_c,
-                                "outputs": "hits per cohort"})
+                                "outputs": "hits per cohort",
+                                "timing": "the whole step captured as one HIP graph, replayed"})
     out["steps"] = steps
     out["warmup"] = 1
+    out["eager"] = {"ms_per_step": ms_eager, "value": pairs / (ms_eager / 1e3), "unit": "pairs/s"}
+    out["graph_identical_hits"] = same
     out["roofline"] = roofline("scan kernels of all cohorts", pairs, flops / pairs, kms,
                                PEAK_FP16_TFLOPS, "TFLOP/s")
     out["n_hits"] = n_hits
@@ -652,36 +681,29 @@ def multi_allelic(args, ctx, torch, np, datagen, krux):
     x = torch.from_numpy(w["expr"]).cuda()
     g = torch.from_numpy(g_np).cuda()
     runner = Runner(ctx, torch)
-    steps = max(1, min(args.steps, 5))
+    steps = max(1, min(args.steps, 10))
 
     def step():
         r, ts, _ = ctx.rank(x)
         return ctx.test_multi(r, ts, g, G, p_c=p_c, mode="hits", hit_capacity=1 << 17,
                               min_p=not args.no_minp)
 
-    log("multi-allelic: 1 warmup + %d timed steps" % steps)
-    ms, res, _, _ = runner.run(step, steps, 1)
+    log("multi-allelic: 3 warmup + %d timed steps" % steps)
+    ms, res, kms, kn = runner.run(step, steps, 3)
     n_hits = krux.unpack_hits(res)[0]
     pairs = float(T) * float(M)
-    log("multi-allelic: %.2f ms/step, %.3e pairs/s, hits %d" % (ms, pairs / (ms / 1e3), n_hits))
+    log("multi-allelic: %.2f ms/step, %.3e pairs/s, hits %d, MFMA screen %.3f ms"
+        % (ms, pairs / (ms / 1e3), n_hits, kms))
     out = base_line(args, "SNP-trait pairs/sec, multi-allelic markers", pairs / (ms / 1e3),
-                    "pairs/s", ms, "int32/f64", {
+                    "pairs/s", ms, "f16", {
                         "workload": "multi_allelic", "K": K, "T": T, "M": M, "classes": G,
                         "p_c": p_c, "outputs": "sorted hit list" +
                         ("" if args.no_minp else " + per-trait min p")})
-    out["steps"], out["warmup"] = steps, 1
+    out["steps"], out["warmup"] = steps, 3
     out["n_hits"] = n_hits
-    # VALU-bound lane kernel: per four samples, about 8 operations for the
-    # code bits and the missing code, then per class 1..G-1 two ANDs and two
-    # dot4 products (an operation count, not a measured one; the p-value of
-    # every pair for the minimum p is not counted)
-    ops = pairs * (K / 4.0) * (4 * (G - 1) + 8)
-    kern_ms = ms
-    out["roofline"] = {"bound": "alu", "kernel": "scan_multi<4, SCREEN>",  # and multi_pack
-                       "achieved": ops / (kern_ms / 1e3) / 1e12,
-                       "peak": 256 * 4 * 16 * 2.4e9 / 1e12, "unit": "Tops/s (int32 lane ops)",
-                       "frac": ops / (kern_ms / 1e3) / (256 * 4 * 16 * 2.4e9),
-                       "traffic": None, "note": "step time used for the kernel time"}
+    # G - 1 indicator columns of a K-long contraction per pair
+    out["roofline"] = roofline("scan_multi_mfma<KS=7, G=4>", pairs, 2 * K * (G - 1), kms,
+                               PEAK_FP16_TFLOPS, "TFLOP/s")
     if not args.no_cpu:
         from oracle import multi
         t0 = time.perf_counter()

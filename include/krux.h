@@ -201,16 +201,21 @@ krux_status krux_test_grouped(krux_ctx* ctx, const int16_t* ranks2, const int64_
  * calculation for df up to l).  Genotype codes 0..n_classes-1 are classes,
  * any other code is missing (the sample is removed from the pair and the
  * ranks recomputed, as in krux_test); a 0 rank is a missing expression value.
- * df = non-empty classes - 1, p = the chi-square tail at df.  H is computed
- * in double from exact integer group sums (relative error a few ulp, not the
- * once-rounded rational of krux_test).  No GEMM: one GPU lane per pair.
+ * df = non-empty classes - 1, p = the chi-square tail at df.  H is the exact
+ * rational value rounded once to the nearest double, as in krux_test.  In
+ * HITS mode with K <= 128 and n_classes <= 5, the pairs whose samples all
+ * have a class and an expression value go through the MFMA rank-sum GEMM
+ * (n_classes - 1 indicator columns per SNP) with an fp32 screen and exact
+ * evaluation of the pairs that pass; every other pair (and FULL mode) is
+ * evaluated exactly by one GPU lane.
  *   n_classes  2..8 (l + 1); K <= 2048.
  *   mode       KRUX_MODE_HITS: hits (sorted by (trait, snp)) with
  *              H > H_c(df), the largest double whose chi-square tail at df is
  *              >= p_c; *n_hits the true count; min_p (device, T doubles, may
  *              be NULL) the minimum p over the SNPs per trait.
  *              KRUX_MODE_FULL: H and p (device, T x M doubles).
- * Other arguments as krux_test; unused outputs may be NULL. */
+ * Other arguments as krux_test (snp_base + M must fit int32); unused outputs
+ * may be NULL. */
 krux_status krux_test_multi(krux_ctx* ctx, const int16_t* ranks2, const int64_t* tiesum,
                             int64_t T, int32_t K, const int8_t* geno, int64_t M, int64_t ld_geno,
                             int32_t n_classes, int64_t snp_base, double p_c, int32_t mode,
@@ -304,7 +309,8 @@ krux_status krux_set_pair_buffer_limits(krux_ctx* ctx, int64_t candidates,
  * krux_permute (one per cohort for krux_test_batched) brackets its two scan
  * launches with HIP events on the launch stream: the complete-SNP kernel and
  * the missing-genotype kernel (which returns at once when no SNP has a
- * missing genotype).  krux_timer_read synchronises those events, returns the
+ * missing genotype); a krux_test_multi call on the MFMA path brackets its
+ * screen kernel.  krux_timer_read synchronises those events, returns the
  * summed kernel time (host, ms) and the number of timed launches (two per
  * main pass), and stops the timer.  Meant for benchmarks. */
 krux_status krux_timer_start(krux_ctx* ctx);

@@ -21,10 +21,10 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Wno-unused-result", "-I" + os.path.join(HERE, "..", "include")]
 SOURCES = ["scan_f16_diag.hip", "scan_f16_miss.hip", "scan_f16_full.hip", "scan_f16_sums.hip",
            "scan_i8_diag.hip", "scan_i8_miss.hip", "scan_i8_full.hip", "scan_i8_sums.hip",
-           "scan_cand.hip", "scan_tiled_f16.hip", "scan_tiled_i8.hip", "rank.hip", "prep.hip", "scan.hip", "sort.hip", "group.hip", "multi.hip", "fp64.hip", "api.cpp"]
+           "scan_cand.hip", "scan_tiled_f16.hip", "scan_tiled_i8.hip", "rank.hip", "prep.hip", "scan.hip", "sort.hip", "group.hip", "multi.hip", "multi_mfma.hip", "fp64.hip", "api.cpp"]
 
 
-HEADERS = [os.path.join(CSRC, h) for h in ("kx_common.h", "kx_args.h", "kx_host.h", "radix.h",
+HEADERS = [os.path.join(CSRC, h) for h in ("kx_common.h", "kx_args.h", "kx_host.h", "radix.h", "multi_common.h",
                                             "scan_kernel.h", "scan_tiled.h")] + [
     os.path.join(HERE, "..", "include", "krux.h")]
 

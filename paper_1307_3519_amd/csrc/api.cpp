@@ -27,7 +27,7 @@ enum Slot {
     S_TUNE_HITS, S_TUNE_N,
     S_AH, S_AH2, S_BF, S_BF3, S_NAN_FLAG, S_NAN_LIST, S_NAN_N,
     S_G_KEYS, S_G_QMASK, S_G_SNPS, S_G_SAMPLES, S_G_EXPR, S_G_R, S_G_TS, S_G_GENO, S_G_STAGE,
-    S_G_CNT, S_G_MINP, S_G_PHITS, S_G_PN, S_G_PMINP,
+    S_G_CNT, S_G_MINP, S_G_PHITS, S_G_PN, S_G_PMINP, S_MINFO, S_MFLAG,
     S_N_SLOTS
 };
 
@@ -1269,7 +1269,9 @@ krux_status krux_test_multi(krux_ctx* c, const int16_t* ranks2, const int64_t* t
     if ((s = begin_call(c, st)) != KRUX_OK) return s;
     kx::MultiArgs a{};
     a.ranks2 = ranks2; a.tiesum = tiesum; a.T = T; a.K = K; a.M = M; a.snp_base = snp_base;
-    a.pstride = (K + 15) & ~15;
+    a.G = n_classes;
+    a.pstride = (K + 31) & ~31;
+    a.record_hits = 1;
     if (mode == KRUX_MODE_HITS) {
         if (!valid_p(p_c)) return fail(c, KRUX_ERR_ARG, "p_c = %g not in (0, 1]", p_c);
         if (!n_hits) return fail(c, KRUX_ERR_ARG, "n_hits is NULL");
@@ -1283,7 +1285,6 @@ krux_status krux_test_multi(krux_ctx* c, const int16_t* ranks2, const int64_t* t
     } else if (T * M > 0 && (!H || !p)) {
         return fail(c, KRUX_ERR_ARG, "H / p is NULL");
     }
-    HIP_TRY(c, hipSetDevice(c->device));
     kx::HitRec* stage = nullptr;
     unsigned long long* nh = nullptr;
     if (mode == KRUX_MODE_HITS) {
@@ -1302,14 +1303,87 @@ krux_status krux_test_multi(krux_ctx* c, const int16_t* ranks2, const int64_t* t
     }
     if (T > 0 && M > 0) {
         uint8_t* packed = (uint8_t*)ws(c, S_G_GENO, (size_t)M * a.pstride, &s);
+        kx::MultiInfo* info = (kx::MultiInfo*)ws(c, S_MINFO, (size_t)M * sizeof(kx::MultiInfo), &s);
+        int32_t* any_missing = (int32_t*)ws(c, S_MFLAG, 256, &s);
         if (s != KRUX_OK) return s;
         HIP_TRY(c, kx_launch_multi_pack(geno, ld_geno, M, K, n_classes, a.pstride, packed,
                                         c->n_cu * 8, st));
+        HIP_TRY(c, kx_launch_multi_info(packed, a.pstride, M, K, n_classes, info, any_missing,
+                                        c->n_cu * 8, st));
         a.packed = packed;
-        const int64_t items = T * ((M + 63) / 64);
-        const int grid = (int)std::min<int64_t>((items + 3) / 4, (int64_t)c->n_cu * 8);
-        HIP_TRY(c, kx_launch_multi(&a, n_classes, mode == KRUX_MODE_FULL ? kx::FULL : kx::SCREEN,
-                                   grid, st));
+        a.info = info;
+        a.any_missing = any_missing;
+        const int64_t nb = (M + 63) / 64;
+        const int lane_grid = (int)std::min<int64_t>((T * nb + 3) / 4, (int64_t)c->n_cu * 8);
+        // complete pairs of K <= 128 with at most five classes take the MFMA
+        // screen; every other pair is evaluated per lane
+        const bool gemm = mode == KRUX_MODE_HITS && K <= 128 && n_classes <= 5;
+        if (!gemm) {
+            HIP_TRY(c, kx_launch_multi(&a, n_classes, mode == KRUX_MODE_FULL ? kx::FULL : kx::SCREEN,
+                                       lane_grid, st));
+        } else {
+            NanSide ns;
+            if ((s = flag_nan(c, ranks2, T, K, st, &ns)) != KRUX_OK) return s;
+            const Variant v{kx::F16, (int)ceil_div(K, 16), kx::DIAG, false, false};
+            RankSide rk;
+            if ((s = prep_ranks(c, v, ranks2, tiesum, T, K, nullptr, nullptr, nullptr, T, S_A,
+                                S_THETA, S_ROWV, st, &rk, S_AH, ns.flag)) != KRUX_OK)
+                return s;
+            a.A = rk.A; a.theta = rk.theta; a.row_v = rk.row_v; a.n_rows = T;
+            a.n_snp_tiles = ceil_div(M, kx::kTile);
+            a.tiles_per_range = trait_range(v, T, a.n_snp_tiles, c->n_cu);
+            a.nan_flag = ns.flag;
+            a.n_nan = ns.n;
+            const double p_screen = min_p ? screen_level_for_min_p(p_c, M) : p_c;
+            for (int df = 1; df < n_classes; ++df) {
+                // 1/H_c(df) capped: at p_screen = 1 (H_c = 0) every pair with
+                // a non-zero class sum passes, and no 0 * inf appears
+                const double h = threshold_any_df(p_screen, df);
+                a.inv_hc[df] = (float)std::min(1.0 / std::max(h, 1e-300), 1e30);
+            }
+            a.cand_cap = pair_limit(candidate_capacity(T, M, p_screen), c->cand_limit);
+            a.cand = (uint2*)ws(c, S_CAND, (size_t)a.cand_cap * sizeof(uint2), &s);
+            a.n_cand = (unsigned long long*)ws(c, S_NCAND, 256, &s);   // cleared by prep
+            if (s != KRUX_OK) return s;
+            const int64_t items = ceil_div(ceil_div(T, kx::kTile), a.tiles_per_range) *
+                                  ceil_div(a.n_snp_tiles, kx::kWavesPerBlock);
+            hipEvent_t ev[2] = {nullptr, nullptr};
+            if (c->timing) {
+                while (c->ev.size() < c->ev_used + 2) {
+                    hipEvent_t e;
+                    HIP_TRY(c, hipEventCreate(&e));
+                    c->ev.push_back(e);
+                }
+                ev[0] = c->ev[c->ev_used];
+                ev[1] = c->ev[c->ev_used + 1];
+                c->ev_used += 2;
+                HIP_TRY(c, hipEventRecord(ev[0], st));
+            }
+            HIP_TRY(c, kx_launch_multi_mfma(&a, n_classes, (int)ceil_div(K, 16),
+                                            (int)std::min<int64_t>(items, INT32_MAX), st));
+            if (ev[1]) HIP_TRY(c, hipEventRecord(ev[1], st));
+            HIP_TRY(c, kx_launch_multi_exact(&a, n_classes, c->n_cu * 8, st));
+            // pairs of traits with a NaN value and of SNPs with a removed code
+            a.only_incomplete = 1;
+            HIP_TRY(c, kx_launch_multi(&a, n_classes, kx::SCREEN, lane_grid, st));
+            a.only_incomplete = 0;
+            if (a.minp_bits) {
+                // traits whose smallest evaluated p is not below the screen
+                // level: every pair of theirs, minimum p only
+                int32_t* list = (int32_t*)ws(c, S_LIST_A, (size_t)T * 4, &s);
+                int32_t* cnt = (int32_t*)ws(c, S_COUNT_A, 256, &s);
+                if (s != KRUX_OK) return s;
+                const double bound = p_screen * (1.0 - 1e-12);
+                unsigned long long limit;
+                std::memcpy(&limit, &bound, 8);
+                HIP_TRY(c, kx_launch_list_unresolved(a.minp_bits, limit, nullptr, nullptr, T, list,
+                                                     cnt, st));
+                a.trait_list = list;
+                a.n_list = cnt;
+                a.record_hits = 0;
+                HIP_TRY(c, kx_launch_multi(&a, n_classes, kx::SCREEN, lane_grid, st));
+            }
+        }
     }
     if (mode == KRUX_MODE_HITS) {
         if (a.minp_bits) HIP_TRY(c, kx_launch_bits_to_double(a.minp_bits, T, min_p, st));

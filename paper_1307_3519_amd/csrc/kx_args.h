@@ -85,13 +85,26 @@ struct ScanArgs {
 
 // Multi-allelic scan (classes 0..n_classes-1, at most kMaxClasses).
 constexpr int kMaxClasses = 8;
+
+// Per-SNP constants of a multi-allelic scan (over the samples whose code is a
+// class; a SNP with a removed code is evaluated per pair, not screened).
+struct alignas(16) MultiInfo {
+    float w[kMaxClasses];     // 1/N_c, 0 for an empty class
+    int16_t n[kMaxClasses];   // class sizes
+    int16_t nmiss;            // samples whose code is not a class
+    int16_t df;               // non-empty classes - 1 (0 for at most one)
+    int16_t pad[2];
+};
+static_assert(sizeof(MultiInfo) == 64, "MultiInfo is 64 bytes");
+
 struct MultiArgs {
     const int16_t* ranks2;   // T x K doubled midranks, 0 = missing value
     const int64_t* tiesum;   // T
     int64_t T;
     int K;
+    int G;                   // classes
     const uint8_t* packed;   // M rows of pstride bytes: class 0..G-1, else 0xFF
-    int pstride;             // a multiple of 16, >= K
+    int pstride;             // a multiple of 32, >= K
     int64_t M;
     double hc[kMaxClasses];  // hc[df]: threshold on H at df (hits)
     HitRec* hits;
@@ -101,6 +114,26 @@ struct MultiArgs {
     double* H_out;           // full mode: T x M
     double* p_out;
     unsigned long long* minp_bits;  // hits mode: [T] bits of the per-trait min p, or null
+    // which pairs the lane-per-pair kernel evaluates
+    const MultiInfo* info;        // [M] per-SNP constants, or null
+    const uint8_t* nan_flag;      // [T] 1: the trait has a missing expression value, or null
+    const int32_t* trait_list;    // traits to scan, or null for 0..T-1
+    const int32_t* n_list;        // device count of trait_list
+    int only_incomplete;          // 1: only pairs of a NaN trait or of a SNP with nmiss > 0
+    int record_hits;              // 0: minimum p only
+    const int32_t* n_nan;         // device: number of NaN traits
+    const int32_t* any_missing;   // device: 1 if some SNP has nmiss > 0
+    // MFMA screen of the complete pairs (SNP-stationary, fp16)
+    const void* A;                // centred ranks in fragment order (prep_ranks_f16)
+    const float* theta;           // [tiles] min over the tile's rows of K^3 - K - sumT
+    const int32_t* row_v;         // [tiles * 32] trait of each operand row, -1 padding
+    int64_t n_rows;
+    int64_t n_snp_tiles;
+    int tiles_per_range;
+    float inv_hc[kMaxClasses];    // screen level: 1/H_c(df) (capped), [0] = 0
+    uint2* cand;                  // screened pairs {operand row, SNP}
+    int64_t cand_cap;
+    unsigned long long* n_cand;
 };
 
 // Extra operands of the tiled large-K kernels.

@@ -13,6 +13,7 @@ struct PrepArgs;
 struct ScanArgs;
 struct TiledArgs;
 struct MultiArgs;
+struct MultiInfo;
 }
 
 extern "C" {
@@ -82,6 +83,12 @@ hipError_t kx_launch_set_counts(int64_t* n_out, const unsigned long long* total,
                                 unsigned long long* stored, int64_t cap, hipStream_t st);
 hipError_t kx_launch_multi_pack(const int8_t* geno, int64_t ld, int64_t M, int K, int G,
                                 int stride, uint8_t* out, int grid, hipStream_t st);
+hipError_t kx_launch_multi_info(const uint8_t* packed, int pstride, int64_t M, int K, int G,
+                                kx::MultiInfo* info, int32_t* any_missing, int grid,
+                                hipStream_t st);
+hipError_t kx_launch_multi_exact(const kx::MultiArgs* a, int n_classes, int grid, hipStream_t st);
+hipError_t kx_launch_multi_mfma(const kx::MultiArgs* a, int n_classes, int ks, int grid,
+                                hipStream_t st);
 hipError_t kx_launch_multi(const kx::MultiArgs* a, int n_classes, int mode, int grid,
                            hipStream_t st);
 size_t kx_sort_keys_tmp_bytes(int64_t cap);

@@ -1,45 +1,26 @@
 // multi.hip -- multi-allelic markers: genotype classes 0..l (l + 1 <= 8
 // groups), eq. (2) over the classes present among a pair's kept samples and
 // the chi-square tail for df = (non-empty classes - 1) (P-value calculation).
-// One wave per (trait, 64 SNPs), one lane per pair: the trait's ranks are
-// staged in LDS, the lane sums them per class and re-ranks its pair when
-// samples are removed (a genotype code outside 0..l where the trait has a
-// value: Handling missing values).  No GEMM: the two-allele path keeps the
-// MFMA scan.
-#include "kx_args.h"
+//
+//   multi_pack     genotype rows copied to an aligned stride, codes 0..l
+//                  kept and every other code 0xFF
+//   multi_info     per-SNP class sizes, removed samples, df and 1/N_c
+//   scan_multi     one wave per (trait, 64 SNPs), one lane per pair: the
+//                  trait's ranks are staged in LDS, the lane sums them per
+//                  class and re-ranks its pair when samples are removed (a
+//                  code outside 0..l where the trait has a value: Handling
+//                  missing values); evaluates every pair, or only the pairs
+//                  the MFMA screen cannot take (a trait with a NaN value or a
+//                  SNP with a removed code), or a list of traits (minimum p)
+//   multi_exact    exact H and p of the pairs that passed the MFMA screen
+//                  (multi_mfma.hip), one lane per pair
+// H is the exact rational of eq. (2) divided by the tie factor, rounded once.
+#include "multi_common.h"
 
 namespace kx {
 
-// Upper tail of chi-square with df degrees of freedom at H: Q(df/2, H/2) from
-// its closed forms, exp(-x) sum_{k < df/2} x^k / k! for even df and
-// erfc(sqrt x) + exp(-x) sum_{k=1}^{(df-1)/2} x^(k-1/2) / Gamma(k + 1/2) for
-// odd df (x = H/2).
-__device__ inline double chi2_upper(double H, int df) {
-    if (df <= 0) return 1.0;
-    const double x = 0.5 * H;
-    if ((df & 1) == 0) {
-        double term = 1.0, total = 1.0;
-        for (int k = 1; k < df / 2; ++k) {
-            term *= x / k;
-            total += term;
-        }
-        return exp(-x) * total;
-    }
-    double total = erfc(sqrt(x));
-    if (df > 1) {
-        double term = sqrt(x) / 0.88622692545275801365;   // Gamma(3/2) = sqrt(pi)/2
-        double s = term;
-        for (int k = 2; k <= (df - 1) / 2; ++k) {
-            term *= x / (k - 0.5);
-            s += term;
-        }
-        total += exp(-x) * s;
-    }
-    return total;
-}
-
-// Genotype rows copied to a 16-byte-aligned stride, classes 0..G-1 kept and
-// every other code (and the padding past K) set to 0xFF.
+// Genotype rows copied to an aligned stride, classes 0..G-1 kept and every
+// other code (and the padding past K) set to 0xFF.
 __global__ void multi_pack(const int8_t* __restrict__ geno, int64_t ld, int64_t M, int K, int G,
                            int stride, uint8_t* __restrict__ out) {
     const int64_t n = M * stride;
@@ -49,6 +30,63 @@ __global__ void multi_pack(const int8_t* __restrict__ geno, int64_t ld, int64_t 
         const int k = (int)(i - m * stride);
         const int code = k < K ? geno[m * ld + k] : -1;
         out[i] = (code >= 0 && code < G) ? (uint8_t)code : (uint8_t)0xFF;
+    }
+}
+
+// Per-SNP constants: class sizes over the samples with a class code, the
+// number of removed samples, df and 1/N_c.  One wave per SNP.  A SNP with a
+// removed sample sets *any_missing.
+__global__ __launch_bounds__(256) void multi_info(const uint8_t* __restrict__ packed, int pstride,
+                                                  int64_t M, int K, int G,
+                                                  MultiInfo* __restrict__ info,
+                                                  int32_t* __restrict__ any_missing) {
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t m = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); m < M;
+         m += waves) {
+        const uint8_t* row = packed + m * (int64_t)pstride;
+        int n[kMaxClasses];
+#pragma unroll
+        for (int c = 0; c < kMaxClasses; ++c) n[c] = 0;
+        int nq = 0;
+        for (int k = lane; k < K; k += kWave) {
+            const int code = row[k];
+#pragma unroll
+            for (int c = 0; c < kMaxClasses; ++c) n[c] += code == c;
+            nq += code == 0xFF;
+        }
+        MultiInfo out{};
+        int ne = 0;
+#pragma unroll
+        for (int c = 0; c < kMaxClasses; ++c) {
+            int v = n[c];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            out.n[c] = (int16_t)(c < G ? v : 0);
+            out.w[c] = (c < G && v > 0) ? 1.0f / (float)v : 0.0f;
+            ne += c < G && v > 0;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) nq += __shfl_xor(nq, o, 64);
+        out.nmiss = (int16_t)nq;
+        out.df = (int16_t)(ne > 0 ? ne - 1 : 0);
+        if (lane == 0) {
+            info[m] = out;
+            if (nq > 0) *any_missing = 1;
+        }
+    }
+}
+
+// Exact H and p of the pairs that passed the MFMA screen, one lane each.
+template <int G>
+__global__ __launch_bounds__(256) void multi_exact(MultiArgs a) {
+    int64_t n = (int64_t)*a.n_cand;
+    if (n > a.cand_cap) n = a.cand_cap;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint2 e = a.cand[i];
+        const int64_t trait = a.row_v[e.x];
+        if (trait >= 0) multi_eval_complete<G>(a, trait, (int64_t)e.y);
     }
 }
 
@@ -66,13 +104,28 @@ __global__ __launch_bounds__(256) void scan_multi(MultiArgs a) {
     uint32_t* sob = shi + KW;
     int16_t* srk = (int16_t*)(sob + KW);
     const bool wide = 2 * K > 255;
+    // nothing for this pass when no trait has a NaN value and no SNP a removed code
+    if (a.only_incomplete && *a.n_nan == 0 && *a.any_missing == 0) return;
+    int64_t n_tr = a.T;
+    if (a.trait_list) {
+        const int64_t d = *a.n_list;
+        n_tr = d < n_tr ? d : n_tr;
+    }
     const int64_t nb = (a.M + kWave - 1) / kWave;
-    const int64_t items = a.T * nb;
+    const int64_t items = n_tr * nb;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
     double pmin = 2.0;                               // the lane's smallest p of the item
     for (int64_t it = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; it < items; it += waves) {
-        const int64_t trait = it / nb;
-        const int64_t blk = it - trait * nb;
+        const int64_t ti = it / nb;
+        const int64_t blk = it - ti * nb;
+        const int64_t trait = a.trait_list ? (int64_t)a.trait_list[ti] : ti;
+        const int64_t m = blk * kWave + lane;
+        bool work = m < a.M;
+        if (a.only_incomplete) {
+            const bool nan_trait = a.nan_flag && a.nan_flag[trait];
+            work = work && (nan_trait || a.info[m].nmiss > 0);
+            if (!__any(work)) continue;              // uniform: nothing for this wave
+        }
         int kobs = 0;
         for (int i = lane; i < KW; i += kWave) {
             uint32_t lo = 0, hi = 0, ob = 0;
@@ -93,8 +146,7 @@ __global__ __launch_bounds__(256) void scan_multi(MultiArgs a) {
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) kobs += __shfl_xor(kobs, o, 64);
         __builtin_amdgcn_wave_barrier();
-        const int64_t m = blk * kWave + lane;
-        if (m < a.M) {
+        if (work) {
             const uint8_t* row = a.packed + m * (int64_t)a.pstride;
             // classes 1..G-1 by indicator; class 0 from the totals below
             uint32_t sl[G], sh[G], n[G];
@@ -172,38 +224,31 @@ __global__ __launch_bounds__(256) void scan_multi(MultiArgs a) {
             }
             const int64_t kp = kobs - (int64_t)nq;
             int ne = 0;
+            int nn[G];
+            int64_t D[G];
 #pragma unroll
-            for (int c = 0; c < G; ++c) ne += n[c] > 0;
-            const int df = ne > 0 ? ne - 1 : 0;
-            const int64_t E = kp * kp * kp - kp - ts;
-            double H = 0.0;
-            if (df > 0 && kp >= 2 && E > 0) {
-                // D_c^2 < 2^53 and N_c are exact doubles; all terms are
-                // non-negative (relative error a few ulp)
-                double f = 0.0;
-#pragma unroll
-                for (int c = 0; c < G; ++c)
-                    if (n[c]) {
-                        const double d = (double)(s[c] - (int64_t)n[c] * (kp + 1));
-                        f += d * d / (double)n[c];
-                    }
-                H = 3.0 * (double)(kp - 1) * f / (double)E;
+            for (int c = 0; c < G; ++c) {
+                nn[c] = (int)n[c];
+                ne += n[c] > 0;
+                D[c] = s[c] - (int64_t)n[c] * (kp + 1);
             }
+            const int df = ne > 0 ? ne - 1 : 0;
+            const double H = exact_H_classes<G>(D, nn, kp, ts, df);
             if (MODE == FULL) {
                 a.H_out[trait * a.M + m] = H;
                 a.p_out[trait * a.M + m] = chi2_upper(H, df);
             } else {
-                if (a.minp_bits) pmin = fmin(pmin, chi2_upper(H, df));
-                if (df > 0 && H > a.hc[df]) {
-                const unsigned long long idx = atomicAdd(a.n_hits, 1ull);
-                if ((int64_t)idx < a.hit_cap) {
-                    HitRec h;
-                    h.trait = (int32_t)trait;
-                    h.snp = (int32_t)(a.snp_base + m);
-                    h.H = H;
-                    h.p = chi2_upper(H, df);
-                    a.hits[idx] = h;
-                }
+                if (a.minp_bits && df > 0) pmin = fmin(pmin, chi2_upper(H, df));
+                if (a.record_hits && df > 0 && H > a.hc[df]) {
+                    const unsigned long long idx = atomicAdd(a.n_hits, 1ull);
+                    if ((int64_t)idx < a.hit_cap) {
+                        HitRec h;
+                        h.trait = (int32_t)trait;
+                        h.snp = (int32_t)(a.snp_base + m);
+                        h.H = H;
+                        h.p = chi2_upper(H, df);
+                        a.hits[idx] = h;
+                    }
                 }
             }
         }
@@ -217,6 +262,10 @@ __global__ __launch_bounds__(256) void scan_multi(MultiArgs a) {
         }
         __builtin_amdgcn_wave_barrier();
     }
+}
+
+__global__ void fill_flag(int32_t* f) {
+    if (threadIdx.x == 0) *f = 0;
 }
 
 template <int G>
@@ -237,6 +286,27 @@ extern "C" hipError_t kx_launch_multi_pack(const int8_t* geno, int64_t ld, int64
     if (M * stride <= 0) return hipSuccess;
     hipLaunchKernelGGL(kx::multi_pack, dim3(grid), dim3(256), 0, st, geno, ld, M, K, G, stride,
                        out);
+    return hipGetLastError();
+}
+
+extern "C" hipError_t kx_launch_multi_info(const uint8_t* packed, int pstride, int64_t M, int K,
+                                           int G, kx::MultiInfo* info, int32_t* any_missing,
+                                           int grid, hipStream_t st) {
+    hipLaunchKernelGGL(kx::fill_flag, dim3(1), dim3(64), 0, st, any_missing);
+    if (M > 0)
+        hipLaunchKernelGGL(kx::multi_info, dim3(grid), dim3(256), 0, st, packed, pstride, M, K, G,
+                           info, any_missing);
+    return hipGetLastError();
+}
+
+extern "C" hipError_t kx_launch_multi_exact(const kx::MultiArgs* a, int n_classes, int grid,
+                                            hipStream_t st) {
+    switch (n_classes) {
+#define KX_CASE(g) case g: hipLaunchKernelGGL(kx::multi_exact<g>, dim3(grid), dim3(256), 0, st, *a); break;
+        KX_CASE(2) KX_CASE(3) KX_CASE(4) KX_CASE(5) KX_CASE(6) KX_CASE(7) KX_CASE(8)
+#undef KX_CASE
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -509,38 +509,89 @@ def test_grouped_degenerate_cases(kx):
 
 
 # ---------------------------------------------------------------- multi-allelic markers
-MULTI_CASES = [  # (K, T, M, n_classes)
-    (40, 8, 70, 4),
-    (37, 6, 65, 6),
-    (150, 5, 30, 5),
-    (30, 5, 40, 8),
+# (K, T, M, n_classes, missing genotypes, NaN values): the MFMA screen takes
+# the complete pairs at K <= 128 with up to five classes (one to eight
+# k-steps, one to four indicator columns), the lane kernel every other pair
+MULTI_CASES = [
+    (40, 8, 70, 4, 0.03, 0.03),
+    (37, 6, 65, 6, 0.03, 0.03),
+    (150, 5, 30, 5, 0.03, 0.03),
+    (30, 5, 40, 8, 0.03, 0.03),
+    (102, 40, 130, 4, 0.0, 0.0),
+    (102, 37, 100, 4, 0.005, 0.005),
+    (17, 35, 70, 3, 0.0, 0.0),
+    (128, 33, 64, 5, 0.0, 0.0),
+    (64, 40, 90, 2, 0.0, 0.0),
+    (90, 36, 80, 5, 0.0, 0.0),
+    (1000, 3, 5, 4, 0.02, 0.0),
+    (700, 3, 6, 8, 0.02, 0.02),
 ]
 
 
-@pytest.mark.parametrize("K,T,M,G", MULTI_CASES)
-def test_multi_allelic(kx, K, T, M, G):
-    from oracle import multi
-    from paper_1307_3519_amd.krux import unpack_hits
-    say("multi", K, T, M, G)
-    rng = np.random.default_rng(K * 100 + G)
+def _multi_inputs(K, T, M, G, pm, nan):
+    rng = np.random.default_rng(K * 100 + G + T)
     x = np.round(rng.lognormal(size=(T, K)), 1).astype(np.float32)      # ties
-    x[rng.random(x.shape) < 0.03] = np.nan
-    x[0, :] = np.nan
+    if nan:
+        x[rng.random(x.shape) < nan] = np.nan
+        x[0, :] = np.nan
     q = rng.dirichlet(np.ones(G), size=M)
     g = np.array([rng.choice(G, size=K, p=q[m]) for m in range(M)], dtype=np.int8)
-    g[rng.random(g.shape) < 0.03] = -1
-    g[rng.random(g.shape) < 0.01] = G + 1                                # also missing
+    if pm:
+        g[rng.random(g.shape) < pm] = -1
+        g[rng.random(g.shape) < pm / 3] = G + 1                          # also missing
     g[1, :] = 0                                                          # one class only
+    # an effect on a few traits so that small p-values occur
+    for t in range(2, min(T, 6)):
+        m = 2 + t
+        x[t] = np.where(np.isnan(x[t]), x[t], x[t] + 0.7 * np.clip(g[m], 0, G)).astype(np.float32)
+    return x, g
+
+
+@pytest.mark.parametrize("K,T,M,G,pm,nan", MULTI_CASES)
+def test_multi_allelic(kx, K, T, M, G, pm, nan):
+    from oracle import multi
+    from paper_1307_3519_amd.krux import unpack_hits
+    say("multi", K, T, M, G, pm, nan)
+    x, g = _multi_inputs(K, T, M, G, pm, nan)
     r, ts = _ranks(kx, x)
     gd = _dev(g)
     p_c = 0.05
     o = multi.scan(x, g, G, p_c=p_c)
     full = kx.test_multi(r, ts, gd, G, mode="full")
-    res = kx.test_multi(r, ts, gd, G, p_c=p_c, mode="hits", hit_capacity=4096, snp_base=3)
+    res = kx.test_multi(r, ts, gd, G, p_c=p_c, mode="hits", hit_capacity=1 << 14, snp_base=3)
     torch.cuda.synchronize()
-    assert_H(full["H"].cpu().numpy(), o["H"], "multi H")
+    # H is the correctly rounded rational on both sides
+    assert np.array_equal(full["H"].cpu().numpy(), o["H"])
     assert_p(full["p"].cpu().numpy(), o["p"], "multi p")
     n, h = unpack_hits(res)
     assert n == len(o["hits"]) and n > 0
     assert list(zip(h["trait"].tolist(), (h["snp"] - 3).tolist())) == o["hits"]
+    assert np.array_equal(h["H"], o["H"][h["trait"], h["snp"] - 3])
     assert_p(res["min_p"].cpu().numpy(), o["p"].min(axis=1), "multi min p")
+
+
+def test_multi_allelic_small_p_and_overflow():
+    # the MFMA screen at p < 1e-4 (few candidates) and with a candidate
+    # buffer of 8 entries (the rest evaluated inside the screen kernel)
+    from oracle import multi
+    from paper_1307_3519_amd import krux
+    from paper_1307_3519_amd.krux import unpack_hits
+    say("multi small p / overflow")
+    K, T, M, G = 102, 40, 120, 4
+    x, g = _multi_inputs(K, T, M, G, 0.0, 0.0)
+    o = multi.scan(x, g, G)
+    for limit, p_c in ((0, 1e-4), (8, 0.05)):
+        ctx = krux.Context(0)
+        try:
+            ctx.set_pair_buffer_limits(limit, 0)
+            r, ts, _ = ctx.rank(_dev(x))
+            res = ctx.test_multi(r, ts, _dev(g), G, p_c=p_c, mode="hits", hit_capacity=1 << 14)
+            torch.cuda.synchronize()
+            n, h = unpack_hits(res)
+            want = [(t, m) for t in range(T) for m in range(M)
+                    if o["p"][t, m] < 1.0 and o["H"][t, m] > multi.threshold(
+                        p_c, multi.one_pair(x[t], g[m], G)["df"])]
+            assert n == len(want) and list(zip(h["trait"].tolist(), h["snp"].tolist())) == want
+            assert_p(res["min_p"].cpu().numpy(), o["p"].min(axis=1), "multi min p")
+        finally:
+            ctx.close()
