@@ -11,8 +11,12 @@ namespace kx {
 // missing sample q, s_i(q) = #{kept k in group i above q} - #{kept k in group i
 // below q}.  At most L_q = (a_q - 2) / 2 samples lie below q and at most
 // G_q = K - a_q / 2 above it (a_q: doubled midrank, its tie group holds q), so
-// s_i(q) lies in [-min(N_i, L_q), min(N_i, G_q)].  The largest f over these
-// intervals, with E' >= K'^3 - K' - sumT, bounds H'.  Returns false when the
+// s_i(q) lies in [-min(N_i, L_q), min(N_i, G_q)].  The kept samples'
+// re-centred ranks sum to zero, so the shifts also satisfy
+// sum_i sum_q s_i(q) = -(sum of the missing samples' centred ranks).  The
+// largest f over these intervals and that plane (at a vertex of the polygon
+// they cut, f being convex), with E' >= K'^3 - K' - sumT, bounds H'.
+// Returns false when the
 // bound stays below the pass's screen level (never for a level of 0), or when
 // the pair can only matter for its row's minimum p and cannot lower it.  All
 // lanes of the wave take part; the result is uniform.
@@ -97,13 +101,40 @@ __device__ inline bool missing_pair_may_pass(const ScanArgs& a, int64_t v, int64
     const int64_t E = cube_minus(kp) - a.tiesum[trait];
     if (kp < 2 || E <= 0) return true;          // no bound: evaluate
     const int64_t D[3] = {-(int64_t)d1 - d2 - sq, d1, d2};
-    double f = 0.0;
+    // D'_i = D_i - s_i with s_i in [lo_i, hi_i], and the kept samples'
+    // re-centred ranks sum to zero: sum_i s_i = sum_i D_i = -sq.  f is convex,
+    // so its largest value over the box cut by that plane is at a vertex (two
+    // shifts at an end of their interval, the third from the sum and within
+    // its own); the box alone (each |D'_i| at its largest) is the fallback
+    double f = -1.0;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        if (n[i] == 0) continue;
-        const int64_t x0 = D[i] - hi[i], x1 = D[i] - lo[i];
-        const int64_t x = max(x0 < 0 ? -x0 : x0, x1 < 0 ? -x1 : x1);
-        f += (double)(x * x) / (double)n[i];
+    for (int j = 0; j < 3; ++j) {
+        const int o1 = j == 0 ? 1 : 0, o2 = j == 2 ? 1 : 2;
+#pragma unroll
+        for (int sg = 0; sg < 4; ++sg) {
+            const int64_t s1 = (sg & 1) ? hi[o1] : lo[o1];
+            const int64_t s2 = (sg & 2) ? hi[o2] : lo[o2];
+            const int64_t sj = -(int64_t)sq - s1 - s2;
+            if (sj < lo[j] || sj > hi[j]) continue;
+            const int64_t x[3] = {j == 0 ? D[0] - sj : o1 == 0 ? D[0] - s1 : D[0] - s2,
+                                  j == 1 ? D[1] - sj : o1 == 1 ? D[1] - s1 : D[1] - s2,
+                                  j == 2 ? D[2] - sj : o1 == 2 ? D[2] - s1 : D[2] - s2};
+            double fv = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                if (n[i]) fv += (double)(x[i] * x[i]) / (double)n[i];
+            f = fv > f ? fv : f;
+        }
+    }
+    if (f < 0.0) {
+        f = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            if (n[i] == 0) continue;
+            const int64_t x0 = D[i] - hi[i], x1 = D[i] - lo[i];
+            const int64_t x = max(x0 < 0 ? -x0 : x0, x1 < 0 ? -x1 : x1);
+            f += (double)(x * x) / (double)n[i];
+        }
     }
     const double Hup = 3.0 * (double)(kp - 1) * f / (double)E * (1.0 + 1e-9);
     if (Hup < a.hc_screen[df]) return false;
