@@ -575,6 +575,9 @@ void scan_kernel(ScanArgs a) {
     constexpr int NSLOT = PF == 5 ? 8 : 4;
     // fp16 DIAG: second column scaled by q (diag_zscale), screen Y^2 + Z^2
     constexpr bool ZS = E == F16 && FORM == DIAG;
+    // int8 DIAG: the same two-square screen with Z scaled in fp32 after the
+    // conversion (the int8 B operand cannot carry q)
+    constexpr bool ZF = E == I8 && FORM == DIAG;
     constexpr uint32_t kDiagFlags = ZS ? kCandZs : 0u;
 
     __shared__ int4 s_queue[QUEUE ? kWavesPerBlock : 1][QUEUE ? kQueueCap : 1];
@@ -666,8 +669,16 @@ void scan_kernel(ScanArgs a) {
         const float qn0 = (float)inf.nmiss * inf.n0, qn1 = (float)inf.nmiss * inf.n1,
                     qn2 = (float)inf.nmiss * inf.n2;
         const float delta = (float)(cube_minus(a.K) - cube_minus(kp));
-        // ZS: candidate iff Y^2 + Z^2 > theta * invc (inf when wy * fac = 0)
-        const float invc = ZS ? 1.0f / (inf.wy * fac) : 0.0f;
+        // ZS: candidate iff Y^2 + Z^2 > theta * invc (inf when wy * fac = 0);
+        // ZF: Y^2 + (zq Z)^2 with zq = sqrt(wz / wy) rounded up
+        const float invc = (ZS || ZF) ? 1.0f / (inf.wy * fac) : 0.0f;
+        float zq = 0.0f;
+        if constexpr (ZF) {
+            if (inf.wy > 0.0f) {
+                zq = sqrtf(inf.wz / inf.wy);
+                zq = __uint_as_float(__float_as_uint(zq) + 1u);   // next float up
+            }
+        }
 
         const int64_t t0 = rg * a.tiles_per_range;
         const int64_t t1 = (t0 + a.tiles_per_range < n_tiles) ? t0 + a.tiles_per_range : n_tiles;
@@ -679,6 +690,9 @@ void scan_kernel(ScanArgs a) {
         auto screen = [&](const acc_t (&acc)[NC], const float th, int r) -> float {
             if constexpr (ZS) {
                 float y = T_::val(acc[0], r), z = T_::val(acc[1], r);
+                return fmaf(y, y, z * z) - th * invc;
+            } else if constexpr (ZF) {
+                float y = T_::val(acc[0], r), z = zq * T_::val(acc[1], r);
                 return fmaf(y, y, z * z) - th * invc;
             } else if constexpr (FORM == DIAG) {
                 float y = T_::val(acc[0], r), z = T_::val(acc[1], r);
@@ -737,12 +751,16 @@ void scan_kernel(ScanArgs a) {
         };
         // largest screen value of a tile (VALU only, no branches)
         auto screen_max = [&](const acc_t (&acc)[NC], const float th) -> float {
-            if constexpr (ZS) {
+            if constexpr (ZS || ZF) {
                 float smax = 0.0f;
 #pragma unroll
                 for (int r = 0; r < 16; r += 2) {
-                    const float y0 = T_::val(acc[0], r), z0 = T_::val(acc[1], r);
-                    const float y1 = T_::val(acc[0], r + 1), z1 = T_::val(acc[1], r + 1);
+                    float z0 = T_::val(acc[1], r), z1 = T_::val(acc[1], r + 1);
+                    if constexpr (ZF) {
+                        z0 *= zq;
+                        z1 *= zq;
+                    }
+                    const float y0 = T_::val(acc[0], r), y1 = T_::val(acc[0], r + 1);
                     smax = fmaxf(smax, fmaxf(fmaf(y0, y0, z0 * z0), fmaf(y1, y1, z1 * z1)));
                 }
                 return smax - th * invc;
