@@ -61,21 +61,68 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 PROFILE = os.path.join(ROOT, "profiles", "scan_f16_diag_screen_K102_T20000_M500000.txt")
 
 
+DOMINANT_KERNEL = "_ZN2kx11scan_kernelILi0ELi7ELi0ELi0ELi4ELi3EEEvNS_8ScanArgsE"
+
+
+def _elf_symbols(elf, names):
+    """Bytes of the named symbols of an ELF64 image (code objects here)."""
+    import struct
+    shoff, = struct.unpack_from("<Q", elf, 0x28)
+    shentsize, shnum = struct.unpack_from("<HH", elf, 0x3A)
+    secs = [struct.unpack_from("<IIQQQQIIQQ", elf, shoff + k * shentsize) for k in range(shnum)]
+    out = {}
+    for sh in secs:
+        if sh[1] != 2:                      # SHT_SYMTAB
+            continue
+        strtab = secs[sh[6]]
+        for k in range(sh[5] // 24):
+            st_name, st_info, st_other, st_shndx, st_value, st_size = struct.unpack_from(
+                "<IBBHQQ", elf, sh[4] + 24 * k)
+            o = strtab[4] + st_name
+            name = elf[o:elf.index(b"\0", o)].decode()
+            if name in names and 0 < st_shndx < len(secs):
+                sec = secs[st_shndx]
+                start = sec[4] + st_value - sec[3]
+                out[name] = elf[start:start + st_size]
+    return out
+
+
+def kernel_digest(lib_path, symbol):
+    """sha256 of a kernel's gfx950 machine code and kernel descriptor, read from
+    the code objects embedded in the library, or None if not found."""
+    import hashlib
+    import struct
+    data = open(lib_path, "rb").read()
+    magic = b"__CLANG_OFFLOAD_BUNDLE__"
+    pos = data.find(magic)
+    while pos >= 0:
+        n, = struct.unpack_from("<Q", data, pos + len(magic))
+        off = pos + len(magic) + 8
+        for _ in range(n):
+            o, size, tl = struct.unpack_from("<QQQ", data, off)
+            triple = data[off + 24:off + 24 + tl]
+            off += 24 + tl
+            if b"gfx950" in triple and size:
+                found = _elf_symbols(data[pos + o:pos + o + size], (symbol, symbol + ".kd"))
+                if symbol in found:
+                    return hashlib.sha256(found[symbol] + found.get(symbol + ".kd", b"")).hexdigest()
+        pos = data.find(magic, pos + 1)
+    return None
+
+
 def measured_traffic():
     """HBM bytes per main-pass launch of the dominant kernel from the committed
     counter summary (FETCH_SIZE and WRITE_SIZE runs, scaled by a plain copy),
-    or None when the kernel's sources changed since the counters were taken."""
-    import hashlib
+    or None when the kernel's machine code in the built library differs from
+    the one the counters were taken on."""
     try:
         fields = {}
         for line in open(PROFILE):
             if ":" in line:
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
-        h = hashlib.sha256()
-        for src in fields["sources"].split():
-            h.update(open(os.path.join(ROOT, src), "rb").read())
-        if h.hexdigest() != fields["source_sha256"]:
+        from paper_1307_3519_amd import krux
+        if kernel_digest(krux.LIB_PATH, fields["kernel_symbol"]) != fields["kernel_sha256"]:
             return None
         return float(fields["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -745,11 +792,18 @@ def main():
                     help="paper_scale_hits only: skip the other three configurations "
                          "(precision_K500, permutations, cohorts_missing) that the default "
                          "run adds as sub-objects of the JSON line")
+    ap.add_argument("--kernel-digest", action="store_true",
+                    help="print the sha256 of the dominant kernel's machine code in the built "
+                         "library (recorded with its counter summary) and exit")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 256 MiB device-to-device copy first (reference for "
                          "scaling the HBM byte counters of a profiler run)")
     args = ap.parse_args()
 
+    if args.kernel_digest:
+        from paper_1307_3519_amd import krux
+        print(DOMINANT_KERNEL, kernel_digest(krux.LIB_PATH, DOMINANT_KERNEL))
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the scan shards over SNP slices with no "

@@ -341,7 +341,8 @@ krux_status krux_load_tuning(krux_ctx* ctx, const char* cache_path);
 
 /* The configuration in use for (K, precision).  K <= 128 kernel: ring
  * (0 register double buffer, 1 LDS ring with the two-tile pipeline, 2 LDS
- * ring one tile at a time, 3 LDS ring two tiles per step) and range_kb
+ * ring one tile at a time, 3 LDS ring two tiles per step, 4 LDS ring with two
+ * SNP tiles per wave) and range_kb
  * (trait-range operand budget).
  * K > 128 kernel: grouped (XCD-grouped item order) and shape (0 wide tiles,
  * one wave per SIMD; 1 two waves per SIMD).  -1 / 0 mean the built-in rule.

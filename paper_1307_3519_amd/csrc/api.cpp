@@ -43,7 +43,8 @@ struct Buf {
 struct Tuning {
     int ring = -1;       // SNP-stationary kernel: 0 register double buffer, 1 LDS ring,
                          // 2 LDS ring without the two-tile pipeline (3 waves per SIMD),
-                         // 3 LDS ring, two tiles per step
+                         // 3 LDS ring, two tiles per step, 4 LDS ring with two SNP
+                         // tiles per wave
     int range_kb = 0;    // SNP-stationary kernel: trait-range operand budget
     int grouped = -1;    // tiled kernel: XCD-grouped item order
     int shape = -1;      // tiled kernel: tile shape (0 wide, 1 two waves per SIMD)
@@ -1419,7 +1420,7 @@ const char* prec_name(int p) {
 std::vector<Tuning> tuning_candidates(const Variant& v) {
     std::vector<Tuning> out;
     if (!v.tiled) {
-        for (int ring = 0; ring <= 3; ++ring)
+        for (int ring = 0; ring <= 4; ++ring)
             for (int kb : {640, 1280, 2560, 5120}) {
                 Tuning t;
                 t.ring = ring;

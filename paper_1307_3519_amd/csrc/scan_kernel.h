@@ -1027,6 +1027,172 @@ void scan_kernel(ScanArgs a) {
     if constexpr (MODE == SCREEN) flush_stage(a, &s_args, stage, sn, lane);
 }
 
+// Complete-SNP screen (DIAG form) with two SNP tiles per wave: every A tile
+// the block copies into its LDS ring feeds 2 SNP tiles x 2 columns x KS
+// MFMAs per wave, so the ring's LDS reads, barrier and copies per MFMA are
+// half those of the one-tile pipeline (PF 4), at two waves per SIMD (the B
+// fragments of both tiles stay in registers).  The screen is the two-square
+// form of the one-tile kernel (fp16: Z pre-scaled by q in B; int8: scaled in
+// fp32 after the conversion).
+template <int E, int KS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void scan_kernel_ns2(ScanArgs a) {
+    using T_ = ET<E>;
+    using frag = typename T_::frag;
+    using acc_t = typename T_::acc;
+    constexpr int NC = 2, NS = 2, NSLOT = 4;
+    constexpr int TPB = kWavesPerBlock * NS;          // SNP tiles per block
+    constexpr bool ZS = E == F16;
+    constexpr uint32_t kFlags = ZS ? kCandZs : 0u;
+    __shared__ uint4 s_stage[kWavesPerBlock][kStageCap];
+    __shared__ ScanArgs s_args;
+    __shared__ frag s_ring[NSLOT * KS * kWave];
+    if (threadIdx.x == 0) s_args = a;
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint4* stage = s_stage[wave];
+    int sn = 0;
+    if (a.want_flag == 1 && a.tile_flags[a.n_snp_tiles] == 0) return;
+    int64_t n_rows = a.n_rows;
+    if (a.d_nrows) {
+        const int64_t d = *a.d_nrows;
+        n_rows = d < n_rows ? d : n_rows;
+    }
+    const int64_t n_tiles = (n_rows + kTile - 1) / kTile;
+    const int64_t n_ranges = (n_tiles + a.tiles_per_range - 1) / a.tiles_per_range;
+    const int64_t n_blocks = (a.n_snp_tiles + TPB - 1) / TPB;
+    const int64_t items = n_ranges * n_blocks;
+    const frag* A = (const frag*)a.A;
+    const float kslack = 1.0f + kScreenSlack;
+    constexpr int LPW = (KS + kWavesPerBlock - 1) / kWavesPerBlock;   // copies per wave
+
+    for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
+        const int64_t rg = item / n_blocks;
+        const int64_t sb = item % n_blocks;
+        // the wave's SNP tiles (uniform); a lane's SNP is st * 32 + lane % 32
+        const int64_t st0 = sb * TPB + wave * NS;
+        bool act[NS];
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            const int64_t st = st0 + j;
+            act[j] = st < a.n_snp_tiles && (a.want_flag < 0 || a.tile_flags[st] == a.want_flag);
+            any = any || act[j];
+        }
+        // block-uniform skip: the waves meet at the ring's barriers
+        if (!__syncthreads_or(any)) continue;
+        frag B[NS][KS][NC];
+        float invc[NS], zq[NS];
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            const int64_t mj = (st0 + j) * kTile + (lane & 31);
+            SnpInfo inf{};
+            if (act[j]) inf = gload(a.info + mj);
+            const float cz = ZS ? diag_zscale(inf) : 1.f;
+            const int8_t* grow = a.G + mj * (int64_t)a.gstride + T_::per_lane * (lane >> 5);
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                int8_t codes[T_::per_lane];
+                if constexpr (T_::per_lane == 8) {
+                    const uint2 w = act[j] ? gload((const uint2*)(grow + s * T_::kps))
+                                           : make_uint2(~0u, ~0u);
+                    __builtin_memcpy(codes, &w, 8);
+                } else {
+                    const uint4 w = act[j] ? gload((const uint4*)(grow + s * T_::kps))
+                                           : make_uint4(~0u, ~0u, ~0u, ~0u);
+                    __builtin_memcpy(codes, &w, 16);
+                }
+                B[j][s][0] = T_::make(codes, 0.f, inf.cy1, inf.cy2);
+                B[j][s][1] = T_::make(codes, 0.f, 0.f, cz);
+            }
+            const float fac = 3.0f * (float)(a.K - 1) * kslack * a.inv_hc[snp_df(inf)];
+            invc[j] = 1.0f / (inf.wy * fac);          // inf when the SNP is never screened in
+            zq[j] = 0.0f;
+            if (!ZS && inf.wy > 0.0f)
+                zq[j] = __uint_as_float(__float_as_uint(sqrtf(inf.wz / inf.wy)) + 1u);
+        }
+        const int64_t t0 = rg * a.tiles_per_range;
+        const int64_t t1 = (t0 + a.tiles_per_range < n_tiles) ? t0 + a.tiles_per_range : n_tiles;
+        auto issue = [&](const int64_t tt) {
+            const int64_t tc = tt < t1 ? tt : t1 - 1;
+#pragma unroll
+            for (int jj = 0; jj < LPW; ++jj) {
+                int ks = wave + jj * kWavesPerBlock;
+                ks = ks < KS ? ks : KS - 1;
+                const frag* src = A + (tc * KS + ks) * kWave + lane;
+                const uint32_t dst = (uint32_t)(uintptr_t)(
+                    (__attribute__((address_space(3))) frag*)&s_ring[((tt & (NSLOT - 1)) * KS + ks) * kWave]);
+                asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
+                             :
+                             : "s"(__builtin_amdgcn_readfirstlane(dst)), "v"(src)
+                             : "memory");
+            }
+        };
+        // every wave is done with the ring of the previous item
+        __builtin_amdgcn_s_waitcnt(0);
+        block_barrier();
+        issue(t0);
+        issue(t0 + 1);
+        for (int64_t t = t0; t < t1; ++t) {
+            issue(t + 2);
+            // this wave's copies of tile t have landed, then the barrier
+            __builtin_amdgcn_s_waitcnt((2 * LPW) | (0x7 << 4) | (0xF << 8));
+            block_barrier();
+            frag Af[KS];
+#pragma unroll
+            for (int s = 0; s < KS; ++s) Af[s] = s_ring[((t & (NSLOT - 1)) * KS + s) * kWave + lane];
+            const float th = cload(a.theta + t);
+            acc_t acc[NS][NC];
+#pragma unroll
+            for (int j = 0; j < NS; ++j)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) acc[j][c] = acc_t{};
+#pragma unroll
+            for (int s = 0; s < KS; ++s)
+#pragma unroll
+                for (int j = 0; j < NS; ++j)
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) acc[j][c] = T_::mma(Af[s], B[j][s][c], acc[j][c]);
+            // largest Y^2 + Z^2 of each SNP tile (Z scaled), against theta * invc
+            float g = -__builtin_inff();
+#pragma unroll
+            for (int j = 0; j < NS; ++j) {
+                float smax = 0.0f;
+#pragma unroll
+                for (int r = 0; r < 16; r += 2) {
+                    float z0 = T_::val(acc[j][1], r), z1 = T_::val(acc[j][1], r + 1);
+                    if constexpr (!ZS) {
+                        z0 *= zq[j];
+                        z1 *= zq[j];
+                    }
+                    const float y0 = T_::val(acc[j][0], r), y1 = T_::val(acc[j][0], r + 1);
+                    smax = fmaxf(smax, fmaxf(fmaf(y0, y0, z0 * z0), fmaf(y1, y1, z1 * z1)));
+                }
+                g = fmaxf(g, smax - th * invc[j]);
+            }
+            if (__any(g > 0.0f)) {
+                const int64_t rb = t * kTile + 4 * (lane >> 5);
+#pragma unroll
+                for (int j = 0; j < NS; ++j) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const float y = T_::val(acc[j][0], r), zr = T_::val(acc[j][1], r);
+                        const float z = ZS ? zr : zq[j] * zr;
+                        const bool cand = act[j] && fmaf(y, y, z * z) - th * invc[j] > 0.0f;
+                        stage_candidates(a, &s_args, stage, sn, lane, cand,
+                                         rb + 8 * (r >> 2) + (r & 3),
+                                         (st0 + j) * kTile + (lane & 31), y, zr, kFlags);
+                    }
+                }
+            }
+        }
+        // the copies past the range end are still landing in the ring
+        __builtin_amdgcn_s_waitcnt(0);
+    }
+    flush_stage(a, &s_args, stage, sn, lane);
+}
+
 }  // namespace kx
 
 // ---------------------------------------------------------------------------
@@ -1056,10 +1222,27 @@ inline hipError_t launch_one(const kx::ScanArgs& a, int grid, hipStream_t st) {
 // Complete-SNP screen pass with the A-operand pipeline selected by a.ring:
 // 0 register double buffer (2 waves per SIMD), 1 LDS ring with the two-tile
 // software pipeline, 2 LDS ring one tile at a time (3 waves per SIMD),
-// 3 LDS ring two tiles per step (2 waves per SIMD).
+// 3 LDS ring two tiles per step (2 waves per SIMD), 4 LDS ring one tile at a
+// time with two SNP tiles per wave (2 waves per SIMD).
+template <int E, int KS>
+inline hipError_t launch_ns2(const kx::ScanArgs& a, int grid, hipStream_t st) {
+    auto kern = kx::scan_kernel_ns2<E, KS>;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 256, 0) != hipSuccess || occ < 1)
+        occ = 1;
+    int dev = 0, n_cu = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t resident = (int64_t)n_cu * occ;
+    const int g = (int)(grid < resident ? grid : resident);
+    hipLaunchKernelGGL(kern, dim3(g), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
 template <int E, int KS>
 inline hipError_t launch_diag_screen(const kx::ScanArgs& a, int grid, hipStream_t st) {
     switch (a.ring) {
+        case 4: return launch_ns2<E, KS>(a, grid, st);
         case 3: return launch_one<E, KS, kx::DIAG, kx::SCREEN, 5, 2>(a, grid, st);
         case 2: return launch_one<E, KS, kx::DIAG, kx::SCREEN, 4, 3>(a, grid, st);
         case 1: return launch_one<E, KS, kx::DIAG, kx::SCREEN, 3>(a, grid, st);

@@ -39,7 +39,7 @@ def test_autotune_choice_persists_and_keeps_results(tmp_path, K, prec, pm):
         assert ms > 0.0
         chosen = ctx.tuning_of(K, prec)
         if K <= 128:
-            assert chosen["ring"] in (0, 1, 2, 3) and chosen["range_kb"] in (640, 1280, 2560, 5120)
+            assert chosen["ring"] in (0, 1, 2, 3, 4) and chosen["range_kb"] in (640, 1280, 2560, 5120)
         else:
             assert chosen["grouped"] in (0, 1) and chosen["shape"] in (0, 1)
         res = ctx.test(r, ts, gd, p_c=0.01, precision=prec, hit_capacity=1 << 14, min_p=True)
@@ -64,15 +64,17 @@ def test_autotune_choice_persists_and_keeps_results(tmp_path, K, prec, pm):
         ctx2.close()
 
 
-@pytest.mark.parametrize("ring", [0, 1, 2, 3])
+@pytest.mark.parametrize("ring", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("prec", ["fp16", "int8"])
-def test_every_pipeline_matches_oracle(tmp_path, ring, prec):
+@pytest.mark.parametrize("K,M", [(102, 900), (48, 1000), (17, 333)])
+def test_every_pipeline_matches_oracle(tmp_path, ring, prec, K, M):
     # each SNP-stationary pipeline forced through a cache entry: register
-    # double buffer, LDS ring (pipelined), LDS ring one tile at a time, two per step
+    # double buffer, LDS ring (pipelined), LDS ring one tile at a time, two
+    # per step, two SNP tiles per wave; SNP counts that leave partial blocks
     from paper_1307_3519_amd import krux
-    print("[case] pipeline", ring, prec, flush=True)
-    K, T, M = 102, 300, 900
-    x, g = _inputs(70 + ring, T, K, M, 0.01)
+    print("[case] pipeline", ring, prec, K, M, flush=True)
+    T = 300
+    x, g = _inputs(70 + ring + K, T, K, M, 0.01)
     cache = tmp_path / "tune.jsonl"
     cache.write_text('{"arch": "gfx950", "K": %d, "precision": "%s", "mode": "hits", '
                      '"ring": %d, "range_kb": 640, "grouped": -1, "shape": -1, "ms": 0}\n' % (K, prec, ring))
