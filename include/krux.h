@@ -205,9 +205,10 @@ krux_status krux_test_grouped(krux_ctx* ctx, const int16_t* ranks2, const int64_
  * rational value rounded once to the nearest double, as in krux_test.  In
  * HITS mode with K <= 128 and n_classes <= 5, the pairs whose samples all
  * have a class and an expression value go through the MFMA rank-sum GEMM
- * (n_classes - 1 indicator columns per SNP) with an fp32 screen and exact
- * evaluation of the pairs that pass; every other pair (and FULL mode) is
- * evaluated exactly by one GPU lane.
+ * (n_classes - 1 indicator columns per SNP) with an fp32 screen, and the
+ * pairs that pass are evaluated exactly from the GEMM's class sums (exact
+ * integers); every other pair (and FULL mode) is evaluated exactly by one GPU
+ * lane over its samples.
  *   n_classes  2..8 (l + 1); K <= 2048.
  *   mode       KRUX_MODE_HITS: hits (sorted by (trait, snp)) with
  *              H > H_c(df), the largest double whose chi-square tail at df is
@@ -294,13 +295,15 @@ krux_status krux_test_batched(krux_ctx* ctx, const krux_cohort* cohorts,
 /* Limits on the two screened-pair buffers of the context (entries; 0 = the
  * built-in sizes, which grow with the expected number of screened pairs):
  * `candidates` bounds the buffer of pairs of complete SNPs that pass the fp32
- * screen (16 B each; built in: at least 2^22), `missing_pairs` the buffer of
+ * screen (16 B each, 32 B in krux_test_multi; built in: at least 2^22),
+ * `missing_pairs` the buffer of
  * pairs of SNPs with missing genotypes that pass the missing-genotype bound
  * (16 B each; built in: at least 2^16).  Pairs beyond a full buffer are
  * evaluated inside the scan kernels instead (slower, identical results), so
  * a limit bounds scratch memory, and a tiny limit exercises those paths.
  * Applies to later krux_test / krux_permute / krux_permute_hits /
- * krux_test_grouped / krux_test_batched calls on this context. */
+ * krux_test_grouped / krux_test_batched / krux_test_multi calls on this
+ * context. */
 krux_status krux_set_pair_buffer_limits(krux_ctx* ctx, int64_t candidates,
                                         int64_t missing_pairs);
 

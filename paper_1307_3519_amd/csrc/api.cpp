@@ -1343,7 +1343,7 @@ krux_status krux_test_multi(krux_ctx* c, const int16_t* ranks2, const int64_t* t
                 a.inv_hc[df] = (float)std::min(1.0 / std::max(h, 1e-300), 1e30);
             }
             a.cand_cap = pair_limit(candidate_capacity(T, M, p_screen), c->cand_limit);
-            a.cand = (uint2*)ws(c, S_CAND, (size_t)a.cand_cap * sizeof(uint2), &s);
+            a.cand = (kx::MultiCand*)ws(c, S_CAND, (size_t)a.cand_cap * sizeof(kx::MultiCand), &s);
             a.n_cand = (unsigned long long*)ws(c, S_NCAND, 256, &s);   // cleared by prep
             if (s != KRUX_OK) return s;
             const int64_t items = ceil_div(ceil_div(T, kx::kTile), a.tiles_per_range) *

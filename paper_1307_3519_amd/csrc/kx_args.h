@@ -97,6 +97,17 @@ struct alignas(16) MultiInfo {
 };
 static_assert(sizeof(MultiInfo) == 64, "MultiInfo is 64 bytes");
 
+// A multi-allelic pair that passed the MFMA screen: its operand row, SNP and
+// the centred doubled-rank sums D_1..D_{G-1} of classes 1..G-1 (exact
+// integers from the screen's GEMM; D_0 = -(D_1 + ... + D_{G-1}), the centred
+// ranks of a trait without missing values summing to zero).
+struct alignas(16) MultiCand {
+    uint32_t row;
+    uint32_t snp;
+    int32_t d[6];
+};
+static_assert(sizeof(MultiCand) == 32, "MultiCand is 32 bytes");
+
 struct MultiArgs {
     const int16_t* ranks2;   // T x K doubled midranks, 0 = missing value
     const int64_t* tiesum;   // T
@@ -131,7 +142,7 @@ struct MultiArgs {
     int64_t n_snp_tiles;
     int tiles_per_range;
     float inv_hc[kMaxClasses];    // screen level: 1/H_c(df) (capped), [0] = 0
-    uint2* cand;                  // screened pairs {operand row, SNP}
+    MultiCand* cand;              // screened pairs with their class sums
     int64_t cand_cap;
     unsigned long long* n_cand;
 };

@@ -13,7 +13,7 @@
 //                  the MFMA screen cannot take (a trait with a NaN value or a
 //                  SNP with a removed code), or a list of traits (minimum p)
 //   multi_exact    exact H and p of the pairs that passed the MFMA screen
-//                  (multi_mfma.hip), one lane per pair
+//                  (multi_mfma.hip) from their class sums, one lane per pair
 // H is the exact rational of eq. (2) divided by the tie factor, rounded once.
 #include "multi_common.h"
 
@@ -84,9 +84,9 @@ __global__ __launch_bounds__(256) void multi_exact(MultiArgs a) {
     if (n > a.cand_cap) n = a.cand_cap;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const uint2 e = a.cand[i];
-        const int64_t trait = a.row_v[e.x];
-        if (trait >= 0) multi_eval_complete<G>(a, trait, (int64_t)e.y);
+        const MultiCand e = a.cand[i];
+        const int64_t trait = a.row_v[e.row];
+        if (trait >= 0) multi_eval_sums<G>(a, trait, e);
     }
 }
 

@@ -1,6 +1,7 @@
 // multi_common.h -- device helpers of the multi-allelic scan (genotype
 // classes 0..l, l + 1 <= 8): the chi-square tail for any df, the statistic as
-// an exact rational rounded once, and the exact evaluation of one pair.
+// an exact rational rounded once, and the exact evaluation of a screened pair
+// from its class sums.
 #pragma once
 #include "kx_args.h"
 
@@ -137,38 +138,25 @@ __device__ inline void multi_record(const MultiArgs& a, int64_t trait, int64_t m
     }
 }
 
-// Exact evaluation of one complete pair (every sample has an expression value
-// and a class; the MFMA screen passes only such pairs) by one lane: class sums
-// of the doubled ranks, then H and p.
+// Exact evaluation of one screened complete pair from its class sums (the
+// MFMA screen's integers) and the SNP's class sizes: no pass over the samples.
 template <int G>
-__device__ inline void multi_eval_complete(const MultiArgs& a, int64_t trait, int64_t m) {
-    const int K = a.K;
-    const uint8_t* codes = a.packed + m * (int64_t)a.pstride;
-    const int16_t* rk = a.ranks2 + trait * (int64_t)K;
-    int64_t s[G];
-    int n[G];
-#pragma unroll
-    for (int c = 0; c < G; ++c) { s[c] = 0; n[c] = 0; }
-    for (int k = 0; k < K; ++k) {
-        const int code = codes[k];
-        const int ak = rk[k];
-#pragma unroll
-        for (int c = 0; c < G; ++c) {
-            const bool in = code == c;
-            s[c] += in ? ak : 0;
-            n[c] += in ? 1 : 0;
-        }
-    }
-    int ne = 0;
+__device__ inline void multi_eval_sums(const MultiArgs& a, int64_t trait, const MultiCand& e) {
+    const int64_t m = (int64_t)e.snp;
+    const MultiInfo inf = a.info[m];
     int64_t D[G];
+    int n[G];
+    int64_t d0 = 0;
 #pragma unroll
-    for (int c = 0; c < G; ++c) {
-        ne += n[c] > 0;
-        D[c] = s[c] - (int64_t)n[c] * (K + 1);
+    for (int c = 1; c < G; ++c) {
+        D[c] = (int64_t)e.d[c - 1];
+        d0 -= D[c];
+        n[c] = inf.n[c];
     }
-    const int df = ne > 0 ? ne - 1 : 0;
-    const double H = exact_H_classes<G>(D, n, K, a.tiesum[trait], df);
-    multi_record(a, trait, m, H, df);
+    D[0] = d0;
+    n[0] = inf.n[0];
+    const double H = exact_H_classes<G>(D, n, a.K, a.tiesum[trait], inf.df);
+    multi_record(a, trait, m, H, inf.df);
 }
 
 }  // namespace kx

@@ -15,8 +15,9 @@
 // pair in fp32 against the chi-square threshold of its df at the screen
 // level (slack 1e-5, the smallest K^3 - K - sumT of the tile); the pairs
 // that pass are staged per wave in LDS and written to a candidate buffer
-// {operand row, SNP}, which multi_exact evaluates exactly.  When the buffer is
-// full the pair is evaluated here.  Lanes of SNPs with a removed code and
+// {operand row, SNP, D_1..D_{G-1}} (the class sums are exact integers in
+// fp32), from which multi_exact evaluates H exactly.  When the buffer is full
+// the pair is evaluated here.  Lanes of SNPs with a removed code and
 // rows of traits with a NaN value never pass: scan_multi takes those pairs.
 #include "multi_common.h"
 
@@ -29,24 +30,24 @@ constexpr int kMultiStage = 64;
 
 // Out of line: keeps the exact evaluation's registers out of the scan loop.
 template <int G>
-__device__ __attribute__((noinline)) void multi_eval_fallback(const MultiArgs& a, int64_t row,
-                                                              int64_t m) {
-    const int64_t trait = a.row_v[row];
-    if (trait >= 0) multi_eval_complete<G>(a, trait, m);
+__device__ __attribute__((noinline)) void multi_eval_fallback(const MultiArgs& a,
+                                                              const MultiCand& e) {
+    const int64_t trait = a.row_v[e.row];
+    if (trait >= 0) multi_eval_sums<G>(a, trait, e);
 }
 
 template <int G>
-__device__ inline void multi_flush(const MultiArgs& a, const MultiArgs* a_lds, uint2* stage,
+__device__ inline void multi_flush(const MultiArgs& a, const MultiArgs* a_lds, MultiCand* stage,
                                    int& sn, int lane) {
     if (sn == 0) return;
     unsigned long long base = 0;
     if (lane == 0) base = atomicAdd(a.n_cand, (unsigned long long)sn);
     base = __shfl(base, 0, 64);
     for (int i = lane; i < sn; i += kWave) {
-        const uint2 e = stage[i];
+        const MultiCand e = stage[i];
         const unsigned long long idx = base + (unsigned long long)i;
         if ((int64_t)idx < a.cand_cap) a.cand[idx] = e;
-        else multi_eval_fallback<G>(*a_lds, (int64_t)e.x, (int64_t)e.y);
+        else multi_eval_fallback<G>(*a_lds, e);
     }
     sn = 0;
     __builtin_amdgcn_wave_barrier();
@@ -66,13 +67,13 @@ template <int KS, int G>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void scan_multi_mfma(MultiArgs a) {
     constexpr int NC = G - 1;
-    __shared__ uint2 s_stage[kWavesPerBlock][kMultiStage];
+    __shared__ MultiCand s_stage[kWavesPerBlock][kMultiStage];
     __shared__ MultiArgs s_args;
     if (threadIdx.x == 0) s_args = a;
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    uint2* stage = s_stage[wave];
+    MultiCand* stage = s_stage[wave];
     int sn = 0;
     const int64_t n_tiles = (a.n_rows + kTile - 1) / kTile;
     const int64_t tpr = a.tiles_per_range;
@@ -145,9 +146,14 @@ void scan_multi_mfma(MultiArgs a) {
                     if (!msk) continue;
                     const int n = __popcll(msk);
                     if (sn + n > kMultiStage) multi_flush<G>(a, &s_args, stage, sn, lane);
-                    if (cand)
-                        stage[sn + __popcll(msk & lt)] =
-                            make_uint2((uint32_t)(rb + 8 * (r >> 2) + (r & 3)), (uint32_t)m);
+                    if (cand) {
+                        MultiCand e;
+                        e.row = (uint32_t)(rb + 8 * (r >> 2) + (r & 3));
+                        e.snp = (uint32_t)m;
+#pragma unroll
+                        for (int c = 0; c < 6; ++c) e.d[c] = c < NC ? (int32_t)acc[c < NC ? c : 0][r] : 0;
+                        stage[sn + __popcll(msk & lt)] = e;
+                    }
                     sn += n;
                     __builtin_amdgcn_wave_barrier();
                 }

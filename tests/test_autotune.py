@@ -95,3 +95,44 @@ def test_every_pipeline_matches_oracle(tmp_path, ring, prec, K, M):
         assert np.all(np.abs(mp - o["min_p"]) <= np.maximum(1e-10 * np.abs(o["min_p"]), 1e-300))
     finally:
         ctx.close()
+
+
+_TILE_ORACLE = {}
+
+
+@pytest.mark.parametrize("shape", [0, 1])
+@pytest.mark.parametrize("prec", ["fp16", "int8"])
+@pytest.mark.parametrize("K,T,M,pm", [(233, 300, 19000, 0.0001), (500, 520, 12000, 0.0),
+                                      (150, 64, 40000, 0.001)])
+def test_every_tile_shape_matches_oracle(tmp_path, shape, prec, K, T, M, pm):
+    # each tile shape of the K > 128 kernel forced through a cache entry, with
+    # more work items than resident blocks (several items per block), ragged
+    # trait blocks, and a mix of complete SNP tiles and tiles with missing
+    # genotypes
+    from paper_1307_3519_amd import krux
+    print("[case] tile shape", shape, prec, K, T, M, pm, flush=True)
+    x, g = _inputs(90 + K, T, K, M, pm)
+    key = (K, T, M, pm)
+    if key not in _TILE_ORACLE:
+        _TILE_ORACLE[key] = oracle.scan(x, g, p_cs=(1e-3,), hits=True, min_p=True)
+    o = _TILE_ORACLE[key]
+    cache = tmp_path / "tune.jsonl"
+    cache.write_text('{"arch": "gfx950", "K": %d, "precision": "%s", "mode": "hits", '
+                     '"ring": -1, "range_kb": 0, "grouped": 1, "shape": %d, "ms": 0}\n'
+                     % (K, prec, shape))
+    ctx = krux.Context(0)
+    try:
+        ctx.load_tuning(str(cache))
+        assert ctx.tuning_of(K, prec)["shape"] == shape
+        r, ts, _ = ctx.rank(_dev(x))
+        res = ctx.test(r, ts, _dev(g), p_c=1e-3, precision=prec, hit_capacity=1 << 16, min_p=True)
+        torch.cuda.synchronize()
+        n, h = krux.unpack_hits(res)
+        assert n == o["n_hits"] and n > 0
+        assert np.array_equal(h["trait"], o["hits"]["trait"])
+        assert np.array_equal(h["snp"], o["hits"]["snp"])
+        assert np.array_equal(h["H"], o["hits"]["H"])
+        mp = res["min_p"].cpu().numpy()
+        assert np.all(np.abs(mp - o["min_p"]) <= np.maximum(1e-10 * np.abs(o["min_p"]), 1e-300))
+    finally:
+        ctx.close()
