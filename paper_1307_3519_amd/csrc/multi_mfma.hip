@@ -28,6 +28,12 @@ typedef float mf32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kMultiStage = 64;
 
+// A value no kernel writes while this one runs, read through the scalar cache
+// (uniform address): its wait does not cover the vector loads in flight.
+__device__ inline float const_load(const float* p) {
+    return *(const __attribute__((address_space(4))) float*)p;
+}
+
 // Out of line: keeps the exact evaluation's registers out of the scan loop.
 template <int G>
 __device__ __attribute__((noinline)) void multi_eval_fallback(const MultiArgs& a,
@@ -80,7 +86,7 @@ void scan_multi_mfma(MultiArgs a) {
     const int64_t n_ranges = (n_tiles + tpr - 1) / tpr;
     const int64_t n_blocks = (a.n_snp_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
     const int64_t items = n_ranges * n_blocks;
-    const mhalf8* A = (const mhalf8*)a.A;
+    const uint4* A = (const uint4*)a.A;
     const float kslack = 1.0f + kScreenSlack;
     const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
 
@@ -110,10 +116,18 @@ void scan_multi_mfma(MultiArgs a) {
         }
         const int64_t t0 = rg * tpr;
         const int64_t t1 = t0 + tpr < n_tiles ? t0 + tpr : n_tiles;
-        for (int64_t t = t0; t < t1; ++t) {
-            mhalf8 Acur[KS];
+        // (as 16-byte words: a loop-carried vector of halves is split by the
+        // compiler into 16-bit pieces and reassembled before every MFMA)
+        auto load_tile = [&](int64_t t, uint4 (&Ad)[KS]) {
 #pragma unroll
-            for (int s = 0; s < KS; ++s) Acur[s] = A[(t * KS + s) * kWave + lane];
+            for (int s = 0; s < KS; ++s) Ad[s] = A[(t * KS + s) * kWave + lane];
+        };
+        // The A fragments of the next tile are loaded into the same registers
+        // once the current tile's MFMAs have been issued, so that the loads
+        // land while the current tile is screened.
+        uint4 Ac[KS];
+        if (t0 < t1) load_tile(t0, Ac);
+        for (int64_t t = t0; t < t1; ++t) {
             mf32x16 acc[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) acc[c] = mf32x16{};
@@ -121,8 +135,10 @@ void scan_multi_mfma(MultiArgs a) {
             for (int s = 0; s < KS; ++s)
 #pragma unroll
                 for (int c = 0; c < NC; ++c)
-                    acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Acur[s], B[s][c], acc[c], 0, 0, 0);
-            const float th = a.theta[t];
+                    acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(mhalf8, Ac[s]),
+                                                                     B[s][c], acc[c], 0, 0, 0);
+            const float th = const_load(a.theta + t);
+            if (t + 1 < t1) load_tile(t + 1, Ac);
             // screen value of a pair: sum_c w_c D_c^2 - theta, D_0 = -sum_{c>0} D_c
             auto screen = [&](int r) {
                 float d0 = 0.0f, v = -th;
@@ -137,26 +153,25 @@ void scan_multi_mfma(MultiArgs a) {
             float vmax = -__builtin_inff();
 #pragma unroll
             for (int r = 0; r < 16; ++r) vmax = fmaxf(vmax, screen(r));
-            if (__any(vmax > 0.0f)) {
-                const int64_t rb = t * kTile + 4 * (lane >> 5);
+            if (!__any(vmax > 0.0f)) continue;
+            const int64_t rb = t * kTile + 4 * (lane >> 5);
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const bool cand = screen(r) > 0.0f;
-                    const unsigned long long msk = __ballot(cand);
-                    if (!msk) continue;
-                    const int n = __popcll(msk);
-                    if (sn + n > kMultiStage) multi_flush<G>(a, &s_args, stage, sn, lane);
-                    if (cand) {
-                        MultiCand e;
-                        e.row = (uint32_t)(rb + 8 * (r >> 2) + (r & 3));
-                        e.snp = (uint32_t)m;
+            for (int r = 0; r < 16; ++r) {
+                const bool cand = screen(r) > 0.0f;
+                const unsigned long long msk = __ballot(cand);
+                if (!msk) continue;
+                const int n = __popcll(msk);
+                if (sn + n > kMultiStage) multi_flush<G>(a, &s_args, stage, sn, lane);
+                if (cand) {
+                    MultiCand e;
+                    e.row = (uint32_t)(rb + 8 * (r >> 2) + (r & 3));
+                    e.snp = (uint32_t)m;
 #pragma unroll
-                        for (int c = 0; c < 6; ++c) e.d[c] = c < NC ? (int32_t)acc[c < NC ? c : 0][r] : 0;
-                        stage[sn + __popcll(msk & lt)] = e;
-                    }
-                    sn += n;
-                    __builtin_amdgcn_wave_barrier();
+                    for (int c = 0; c < 6; ++c) e.d[c] = c < NC ? (int32_t)acc[c < NC ? c : 0][r] : 0;
+                    stage[sn + __popcll(msk & lt)] = e;
                 }
+                sn += n;
+                __builtin_amdgcn_wave_barrier();
             }
         }
     }
