@@ -47,7 +47,8 @@ struct Tuning {
                          // tiles per wave
     int range_kb = 0;    // SNP-stationary kernel: trait-range operand budget
     int grouped = -1;    // tiled kernel: XCD-grouped item order
-    int shape = -1;      // tiled kernel: tile shape (0 wide, 1 two waves per SIMD)
+    int shape = -1;      // tiled kernel: tile shape (0 wide, 1 two waves per SIMD, 2 the same
+                         // with the B side from the packed genotype codes)
     double ms = 0.0;     // time of the tuning run
 };
 
@@ -383,21 +384,37 @@ krux_status choose_variant(krux_ctx* c, int K, int precision, Variant* v) {
     return fail(c, KRUX_ERR_UNSUPPORTED, "precision %d not handled by the MFMA path", precision);
 }
 
-krux_status expand_columns(krux_ctx* c, const Variant& v, const SnpSide& sn, hipStream_t st,
-                           Columns* out) {
+// Tile shape of the tiled kernel for (K, precision): the tuned one, else
+// two waves per SIMD, with the B side from the packed codes where the
+// complete-SNP screen is PLAIN (K > 400: kernel 3.99 -> 3.87 ms and no
+// column expansion at K = 500; at K = 200 the DIAG screen of shape 1 is
+// the faster one).
+int tile_shape_for(krux_ctx* c, int K, int precision) {
+    auto it = c->tuned.find({K, precision});
+    const int t = it != c->tuned.end() ? it->second.shape : -1;
+    return t >= 0 ? t : (K > 400 ? 2 : 1);
+}
+
+// Expanded B columns of the tiled kernel; with the codes shape (2) the
+// complete-SNP screen reads the packed genotype rows, and only the
+// missing-genotype columns are built.
+krux_status expand_columns(krux_ctx* c, const Variant& v, const SnpSide& sn, int shape,
+                           hipStream_t st, Columns* out) {
     if (!v.tiled) return KRUX_OK;
     krux_status s = KRUX_OK;
     const int64_t n_pad = ceil_div(std::max<int64_t>(sn.n_snp_tiles, 1), 4) * 4;
     const size_t per_col = (size_t)n_pad * v.ks * kx::kWave * 16;
-    out->Bf = ws(c, S_BF, per_col * 2, &s);
+    if (shape != 2) out->Bf = ws(c, S_BF, per_col * 2, &s);
     out->Bf3 = ws(c, S_BF3, per_col * 3, &s);
     if (s != KRUX_OK) return s;
     int grid = (int)std::min<int64_t>(ceil_div(n_pad * v.ks * 3 * kx::kWave, 256), (int64_t)c->n_cu * 16);
     if (v.elem == kx::F16) {
-        HIP_TRY(c, kx_launch_expand_f16(sn.G, sn.gstride, sn.info, n_pad, v.ks, v.form, out->Bf, grid, st));
+        if (shape != 2)
+            HIP_TRY(c, kx_launch_expand_f16(sn.G, sn.gstride, sn.info, n_pad, v.ks, v.form, out->Bf, grid, st));
         HIP_TRY(c, kx_launch_expand_f16(sn.G, sn.gstride, sn.info, n_pad, v.ks, kx::MISS3, out->Bf3, grid, st));
     } else {
-        HIP_TRY(c, kx_launch_expand_i8(sn.G, sn.gstride, sn.info, n_pad, v.ks, v.form, out->Bf, grid, st));
+        if (shape != 2)
+            HIP_TRY(c, kx_launch_expand_i8(sn.G, sn.gstride, sn.info, n_pad, v.ks, v.form, out->Bf, grid, st));
         HIP_TRY(c, kx_launch_expand_i8(sn.G, sn.gstride, sn.info, n_pad, v.ks, kx::MISS3, out->Bf3, grid, st));
     }
     return KRUX_OK;
@@ -410,6 +427,8 @@ krux_status launch_scan(krux_ctx* c, const kx::ScanArgs& a, const Variant& v, co
         HIP_TRY(c, kx_launch_scan(&a, v.elem, v.ks, form, mode, grid, st));
         return KRUX_OK;
     }
+    // the codes shape builds indicator columns only: PLAIN in place of DIAG
+    if (a.tile_shape == 2 && form == kx::DIAG) form = kx::PLAIN;
     kx::TiledArgs ta{};
     ta.Bf = form == kx::MISS3 ? col.Bf3 : col.Bf;
     ta.A_hi = A_hi;
@@ -466,7 +485,7 @@ void apply_tuning(krux_ctx* c, int K, int precision, const Variant& v, int64_t n
     a->group_items = t.grouped >= 0 ? t.grouped : 1;
     // two waves per SIMD (shape 1) measured 25-35 % faster than the wide
     // tiles at K = 200 and 500, fp16 and int8
-    a->tile_shape = t.shape >= 0 ? t.shape : 1;
+    a->tile_shape = tile_shape_for(c, K, precision);
 }
 
 // Work items of one scan launch (an upper bound; the kernels stop early).
@@ -675,7 +694,8 @@ krux_status test_impl(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum,
     SnpSide sn;
     if ((s = pack_snps(c, geno, M, ld_geno, K, v.form == kx::DIAG, row_bytes(v), st, &sn)) != KRUX_OK) return s;
     Columns col;
-    if ((s = expand_columns(c, v, sn, st, &col)) != KRUX_OK) return s;
+    if ((s = expand_columns(c, v, sn, tile_shape_for(c, K, precision), st, &col)) != KRUX_OK)
+        return s;
     NanSide ns;
     if ((s = flag_nan(c, ranks2, T, K, st, &ns)) != KRUX_OK) return s;
     RankSide rk;
@@ -952,7 +972,8 @@ krux_status permute_impl(krux_ctx* c, const int16_t* ranks2, const int64_t* ties
     SnpSide sn;
     if ((s = pack_snps(c, geno, M, ld_geno, K, v.form == kx::DIAG, row_bytes(v), st, &sn)) != KRUX_OK) return s;
     Columns col;
-    if ((s = expand_columns(c, v, sn, st, &col)) != KRUX_OK) return s;
+    if ((s = expand_columns(c, v, sn, tile_shape_for(c, K, KRUX_PREC_FP16), st, &col)) != KRUX_OK)
+        return s;
     NanSide ns;
     if ((s = flag_nan(c, ranks2, T, K, st, &ns)) != KRUX_OK) return s;
     RankSide rk;
@@ -1428,7 +1449,7 @@ std::vector<Tuning> tuning_candidates(const Variant& v) {
                 out.push_back(t);
             }
     } else {
-        for (int shape = 0; shape <= 1; ++shape)
+        for (int shape = 0; shape <= 2; ++shape)
             for (int g = 0; g <= 1; ++g) {
                 Tuning t;
                 t.grouped = g;

@@ -62,7 +62,13 @@ __device__ inline float screen_value(const LaneK& c, float th, float v0, float v
 //        to 256 registers, fewest LDS reads per MFMA), one wave per SIMD;
 //  V = 1 ("two waves"): 4 (or 2) trait tiles x 1 SNP tile per wave, so that
 //        two waves share each SIMD and one wave's epilogue overlaps the
-//        other's MFMAs; its LDS ring is kept small enough for two blocks.
+//        other's MFMAs; its LDS ring is kept small enough for two blocks;
+//  V = 2 ("codes", PLAIN form): the tiles of V = 1, with the B side copied
+//        as the packed genotype codes (1 byte per sample instead of 2 bytes
+//        per sample and column) and turned into fragments in registers (byte
+//        permutes), so that a chunk is 18 KB instead of 24 KB, the LDS ring
+//        holds four chunks instead of three, and no expanded columns are
+//        built.
 template <int FORM, bool SPLIT, int V>
 struct TiledShape {
     static constexpr int NC = FORM == MISS3 ? 3 : 2;
@@ -71,14 +77,49 @@ struct TiledShape {
     static constexpr int WT = V == 0 ? ((FORM != MISS3 && NP * 4 * WS * NC * 16 <= 256) ? 4 : 2)
                                      : (NP * NC <= 2 ? 4 : 2);
     static constexpr int ACC = NP * WT * WS * NC * 16;   // accumulator registers
-    static constexpr int WPE_MIN = (V == 1 && ACC <= 128) ? 2 : 1;
+    static constexpr int WPE_MIN = (V != 0 && ACC <= 128) ? 2 : 1;
     static constexpr int RING_BYTES = V == 0 ? 128 * 1024 : 72 * 1024;
     static constexpr int KC = 2;                         // k-steps per chunk
-    static constexpr int NF = 2 * WT * KC * NP + 2 * WS * KC * NC;   // fragments per chunk
-    // ring of R chunk slots of NF fragments (64 lanes x 16 bytes each)
-    static constexpr int R = NF * kWave * 16 * 4 <= RING_BYTES ? 4 : 3;
+    // V = 2: 1 KB copies of codes per SNP tile and chunk (64 lanes x 16
+    // codes: 32 fp16 samples or 64 int8 samples of 32 SNPs)
+    static constexpr int CPT = SPLIT ? 2 : 1;
+    static constexpr int NFA = 2 * WT * KC * NP;         // A fragments per chunk
+    static constexpr int NFB = V == 2 ? 2 * WS * CPT : 2 * WS * KC * NC;
+    static constexpr int NF = NFA + NFB;                 // 1 KB copies per chunk
+    // ring of R chunk slots of NF copies (64 lanes x 16 bytes each)
+    static constexpr int R = V == 2 ? (RING_BYTES / (NF * kWave * 16) < 8
+                                           ? RING_BYTES / (NF * kWave * 16) : 8)
+                                    : (NF * kWave * 16 * 4 <= RING_BYTES ? 4 : 3);
     static constexpr int RING_USED = R * NF * kWave * 16;
 };
+
+// Fragments of the B side built from packed genotype codes (V = 2): code
+// bytes 0..2 are genotype classes, 3 a missing genotype or padding.
+// v_perm_b32 picks bytes of {S0 (bytes 4-7), S1 (bytes 0-3)} by selector.
+//
+// fp16, one dword (two samples b, b + 1 of a lane's eight) of the indicator
+// of class k: the selector [4, code_b, 4, code_b+1] picks 0 for the low
+// bytes and byte code of 0x3C << 8k (fp16 1.0 = 0x3C00) for the high bytes.
+__device__ inline uint32_t f16_ind_sel(uint32_t w, int b) {
+    return __builtin_amdgcn_perm(0x04040404u, w,
+                                 0x04u | ((uint32_t)b << 8) | (0x04u << 16) | ((uint32_t)(b + 1) << 24));
+}
+__device__ inline uint32_t f16_ind(uint32_t sel, int k) {
+    return __builtin_amdgcn_perm(0u, k < 3 ? 0x3Cu << (8 * k) : 0u, sel);
+}
+// fp16 DIAG: the selector [2 code_b, 2 code_b + 1, 2 code_b+1, 2 code_b+1 + 1]
+// picks the two bytes of the code's fp16 entry of an 8-byte table.
+__device__ inline uint32_t f16_tab_sel(uint32_t w, int b) {
+    const uint32_t t = __builtin_amdgcn_perm(0u, w,
+                                             (uint32_t)b | ((uint32_t)b << 8) |
+                                                 ((uint32_t)(b + 1) << 16) | ((uint32_t)(b + 1) << 24));
+    return (t << 1) + 0x01000100u;
+}
+// int8, one dword (four samples) of the indicator of class k: the codes
+// themselves select byte code of 1 << 8k.
+__device__ inline uint32_t i8_ind(uint32_t w, int k) {
+    return __builtin_amdgcn_perm(0u, k < 3 ? 1u << (8 * k) : 0u, w);
+}
 
 // The missing-genotype form re-ranks pairs in its epilogue with per-wave LDS
 // scratch (coop_lds_entries); the ring is idle then and holds it when large
@@ -105,17 +146,25 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
     constexpr int BT = 2 * WT;                         // trait tiles per block
     constexpr int BS = 2 * WS;                         // SNP tiles per block
     constexpr int NFA = BT * KC * NP;                  // A fragments per chunk
-    constexpr int NFB = BS * KC * NC;                  // B fragments per chunk
+    constexpr int NFB = SH::NFB;                       // B fragments (or code copies) per chunk
     constexpr int NF = NFA + NFB;
-    static_assert(NF == SH::NF, "fragment count");
-    constexpr int FPW = NF / kWavesPerBlock;           // copies per wave per chunk (NF % 4 == 0)
-    static_assert(NF % kWavesPerBlock == 0, "every wave copies the same number of fragments");
+    static_assert(NFA == SH::NFA && NF == SH::NF, "fragment count");
+    constexpr bool CODES = V == 2;
+    static_assert(!CODES || (WS == 1 && FORM == PLAIN && SPLIT == (E == I8)),
+                  "the codes shape builds the PLAIN indicator columns of one SNP tile per wave");
+    // copies per wave per chunk: a contiguous run of NF / 4 copies, or (codes
+    // shape) copies wave, wave + 4, ..., which leaves some waves one fewer
+    constexpr int FPW = (NF + kWavesPerBlock - 1) / kWavesPerBlock;
+    constexpr int FPW_MIN = NF / kWavesPerBlock;
+    static_assert(CODES || NF % kWavesPerBlock == 0, "every wave copies the same number of fragments");
     constexpr bool QUEUE = FORM == MISS3;
     // ring of R chunk slots filled D = R - 1 chunks ahead by LDS-DMA copies
     constexpr int R = SH::R;
     static_assert(NF * kWave * 16 * R <= 128 * 1024, "ring fits the LDS budget");
     constexpr int D = R - 1;
-    constexpr int kWaitVm = (D - 1) * FPW;
+    // a wave with FPW copies per chunk waits for D - 1 more of its copies
+    // than it needs to (still exact for the chunk it is about to read)
+    constexpr int kWaitVm = (D - 1) * FPW_MIN;
     static_assert(kWaitVm <= 63, "wait count fits the vmcnt field");
 
     __shared__ frag s_buf[R][NF][kWave];
@@ -203,33 +252,45 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
         // item's first chunk, advanced by a fixed stride per chunk (up to the
         // last chunk, which the copies past the end repeat), so that a chunk
         // costs one 64-bit add per copy instead of the address arithmetic.
-        const frag* cp[FPW];
-        int cstride[FPW];                              // fragments per chunk
+        // (the codes shape copies the B side straight from the packed
+        // genotype rows: lane l takes 16 codes of SNP l % 32 of the tile, the
+        // first or second half of the chunk's samples per k-step part)
+        auto copy_of = [&](int i) { return CODES ? wave + kWavesPerBlock * i : wave * FPW + i; };
+        const uint8_t* cp[FPW];
+        int cstride[FPW];                              // bytes per chunk
 #pragma unroll
         for (int i = 0; i < FPW; ++i) {
-            const int f = wave * FPW + i;
+            const int f = copy_of(i);
             if (f < NFA) {
                 const int p = f / (BT * KC), r = f % (BT * KC);
                 const int tt = r / KC, kk = r % KC;
                 const int64_t tile = tb * BT + tt;
-                cp[i] = (p ? Ah : A) + (tile * KS + kk) * kWave + lane;
-                cstride[i] = KC * kWave;
+                cp[i] = (const uint8_t*)((p ? Ah : A) + (tile * KS + kk) * kWave + lane);
+                cstride[i] = KC * kWave * 16;
+            } else if constexpr (CODES) {
+                const int g = f < NF ? f - NFA : 0;
+                const int s2 = g / SH::CPT, part = g % SH::CPT;
+                const int64_t m = (sb * BS + s2) * kTile + (lane & 31);
+                cp[i] = (const uint8_t*)a.G + m * (int64_t)a.gstride + part * T_::kps +
+                        16 * (lane >> 5);
+                cstride[i] = KC * T_::kps;
             } else {
                 const int g = f - NFA;
                 const int s2 = g / (KC * NC), r = g % (KC * NC);
                 const int kk = r / NC, c = r % NC;
                 const int64_t st = sb * BS + s2;
-                cp[i] = Bf + ((st * KS + kk) * NC + c) * kWave + lane;
-                cstride[i] = KC * NC * kWave;
+                cp[i] = (const uint8_t*)(Bf + ((st * KS + kk) * NC + c) * kWave + lane);
+                cstride[i] = KC * NC * kWave * 16;
             }
         }
         int n_issued = 0;                              // chunks issued for this item
         auto issue_next = [&]() {
-            const uint32_t sbase = ring_lds + (uint32_t)((n_issued % R) * NF * kWave * 16) +
-                                   (uint32_t)(wave * FPW * kWave * 16);
+            const uint32_t sbase = ring_lds + (uint32_t)((n_issued % R) * NF * kWave * 16);
 #pragma unroll
             for (int i = 0; i < FPW; ++i) {
-                const uint32_t dst = sbase + (uint32_t)(i * kWave * 16);
+                const int f = copy_of(i);
+                if (CODES && f >= NF) continue;        // uniform per wave
+                const uint32_t dst = sbase + (uint32_t)(f * kWave * 16);
                 asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
                              :
                              : "s"(__builtin_amdgcn_readfirstlane(dst)), "v"(cp[i])
@@ -276,11 +337,44 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
 #pragma unroll
                     for (int ti = 0; ti < WT; ++ti)
                         fa[p][ti] = s_buf[buf][p * BT * KC + ((wave >> 1) * WT + ti) * KC + kk][lane];
+                if constexpr (CODES) {
+                    // indicator columns of classes 1 and 2 from this lane's codes
+                    // of the k-step
+                    const uint8_t* cb = (const uint8_t*)&s_buf[buf][NFA + (wave & 1) * SH::CPT][0];
+                    if constexpr (E == F16) {
+                        // samples 8 (lane / 32) .. + 7 of k-step kk: copy lane
+                        // l % 32 + 32 kk, bytes 8 (lane / 32) .. + 7
+                        const uint2 w = *(const uint2*)(cb + ((lane & 31) + 32 * kk) * 16 +
+                                                        8 * (lane >> 5));
+                        uint32_t sel[4];
 #pragma unroll
-                for (int j = 0; j < WS; ++j)
+                        for (int q = 0; q < 4; ++q) sel[q] = f16_ind_sel(q < 2 ? w.x : w.y, 2 * (q & 1));
 #pragma unroll
-                    for (int c = 0; c < NC; ++c)
-                        fb[j][c] = s_buf[buf][NFA + ((wave & 1) * WS + j) * KC * NC + kk * NC + c][lane];
+                        for (int c = 0; c < NC; ++c) {
+                            const int k = c + 1;
+                            const uint4 o = make_uint4(f16_ind(sel[0], k), f16_ind(sel[1], k),
+                                                       f16_ind(sel[2], k), f16_ind(sel[3], k));
+                            fb[0][c] = __builtin_bit_cast(frag, o);
+                        }
+                    } else {
+                        // samples 16 (lane / 32) .. + 15 of k-step kk: part kk,
+                        // this lane's 16 bytes
+                        const uint4 w = *(const uint4*)(cb + kk * kWave * 16 + lane * 16);
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) {
+                            const int k = c + 1;
+                            const uint4 o = make_uint4(i8_ind(w.x, k), i8_ind(w.y, k),
+                                                       i8_ind(w.z, k), i8_ind(w.w, k));
+                            fb[0][c] = __builtin_bit_cast(frag, o);
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < WS; ++j)
+#pragma unroll
+                        for (int c = 0; c < NC; ++c)
+                            fb[j][c] = s_buf[buf][NFA + ((wave & 1) * WS + j) * KC * NC + kk * NC + c][lane];
+                }
 #pragma unroll
                 for (int p = 0; p < NP; ++p)
 #pragma unroll
@@ -433,11 +527,18 @@ __global__ __launch_bounds__(256) void expand_columns(const int8_t* __restrict__
 
 template <int E, int FORM, int MODE, bool SPLIT>
 inline hipError_t launch_tiled(const ScanArgs& a, const TiledArgs& ta, int grid, hipStream_t st) {
-    const bool in_ring = ta.shape ? tiled_scratch_in_ring<FORM, SPLIT, 1>(a.K)
-                                  : tiled_scratch_in_ring<FORM, SPLIT, 0>(a.K);
+    // the codes shape (2) covers the complete-SNP screen (the host runs
+    // PLAIN in place of DIAG there); the missing-genotype form keeps the
+    // expanded columns of shape 1 (built from codes its registers overflow)
+    constexpr int V2 = FORM == PLAIN ? 2 : 1;
+    const bool in_ring = ta.shape == 2   ? tiled_scratch_in_ring<FORM, SPLIT, V2>(a.K)
+                         : ta.shape == 1 ? tiled_scratch_in_ring<FORM, SPLIT, 1>(a.K)
+                                         : tiled_scratch_in_ring<FORM, SPLIT, 0>(a.K);
     size_t lds = FORM == MISS3 && !in_ring
                      ? (size_t)kWavesPerBlock * coop_lds_entries(a.K) * sizeof(int16_t) : 0;
-    auto kern = ta.shape ? scan_tiled<E, FORM, MODE, SPLIT, 1> : scan_tiled<E, FORM, MODE, SPLIT, 0>;
+    auto kern = ta.shape == 2   ? scan_tiled<E, FORM, MODE, SPLIT, V2>
+                : ta.shape == 1 ? scan_tiled<E, FORM, MODE, SPLIT, 1>
+                                : scan_tiled<E, FORM, MODE, SPLIT, 0>;
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 256, lds) != hipSuccess || occ < 1)
         occ = 1;

@@ -41,7 +41,7 @@ def test_autotune_choice_persists_and_keeps_results(tmp_path, K, prec, pm):
         if K <= 128:
             assert chosen["ring"] in (0, 1, 2, 3, 4) and chosen["range_kb"] in (640, 1280, 2560, 5120)
         else:
-            assert chosen["grouped"] in (0, 1) and chosen["shape"] in (0, 1)
+            assert chosen["grouped"] in (0, 1) and chosen["shape"] in (0, 1, 2)
         res = ctx.test(r, ts, gd, p_c=0.01, precision=prec, hit_capacity=1 << 14, min_p=True)
         torch.cuda.synchronize()
         n, h = krux.unpack_hits(res)
@@ -100,15 +100,15 @@ def test_every_pipeline_matches_oracle(tmp_path, ring, prec, K, M):
 _TILE_ORACLE = {}
 
 
-@pytest.mark.parametrize("shape", [0, 1])
+@pytest.mark.parametrize("shape", [0, 1, 2])
 @pytest.mark.parametrize("prec", ["fp16", "int8"])
 @pytest.mark.parametrize("K,T,M,pm", [(233, 300, 19000, 0.0001), (500, 520, 12000, 0.0),
                                       (150, 64, 40000, 0.001)])
 def test_every_tile_shape_matches_oracle(tmp_path, shape, prec, K, T, M, pm):
-    # each tile shape of the K > 128 kernel forced through a cache entry, with
-    # more work items than resident blocks (several items per block), ragged
-    # trait blocks, and a mix of complete SNP tiles and tiles with missing
-    # genotypes
+    # each tile shape of the K > 128 kernel (wide, two waves per SIMD, B side
+    # from the packed codes) forced through a cache entry, with more work
+    # items than resident blocks (several items per block), ragged trait
+    # blocks, and a mix of complete SNP tiles and tiles with missing genotypes
     from paper_1307_3519_amd import krux
     print("[case] tile shape", shape, prec, K, T, M, pm, flush=True)
     x, g = _inputs(90 + K, T, K, M, pm)
@@ -134,5 +134,34 @@ def test_every_tile_shape_matches_oracle(tmp_path, shape, prec, K, T, M, pm):
         assert np.array_equal(h["H"], o["hits"]["H"])
         mp = res["min_p"].cpu().numpy()
         assert np.all(np.abs(mp - o["min_p"]) <= np.maximum(1e-10 * np.abs(o["min_p"]), 1e-300))
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("shape", [0, 1, 2])
+@pytest.mark.parametrize("prec", ["fp16", "int8"])
+@pytest.mark.parametrize("K,pm", [(233, 0.02), (1000, 0.02), (300, 0.0)])
+def test_every_tile_shape_full_and_sums(tmp_path, shape, prec, K, pm):
+    # full and sums modes run the three-column kernel over every pair
+    from paper_1307_3519_amd import krux
+    print("[case] tile shape full/sums", shape, prec, K, pm, flush=True)
+    T, M = 70, 150
+    x, g = _inputs(110 + K, T, K, M, pm)
+    o = oracle.scan(x, g, full=True, sums=True)
+    cache = tmp_path / "tune.jsonl"
+    cache.write_text('{"arch": "gfx950", "K": %d, "precision": "%s", "mode": "hits", '
+                     '"ring": -1, "range_kb": 0, "grouped": 1, "shape": %d, "ms": 0}\n'
+                     % (K, prec, shape))
+    ctx = krux.Context(0)
+    try:
+        ctx.load_tuning(str(cache))
+        r, ts, _ = ctx.rank(_dev(x))
+        gd = _dev(g)
+        res = ctx.test(r, ts, gd, mode="sums", precision=prec)
+        torch.cuda.synchronize()
+        assert np.array_equal(res["sums"].cpu().numpy().astype(np.int64), o["sums"])
+        res = ctx.test(r, ts, gd, mode="full", precision=prec)
+        torch.cuda.synchronize()
+        assert np.array_equal(res["H"].cpu().numpy(), o["H"])
     finally:
         ctx.close()
