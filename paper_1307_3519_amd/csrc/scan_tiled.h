@@ -302,22 +302,18 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
             }
             ++n_issued;
         };
+        // the item's first k-step starts its accumulators from zero (an
+        // MFMA with a zero C operand: no clearing of 64 to 192 registers per
+        // item), hence the first chunk's body separately
         acc_t acc[NP][WT][WS][NC];
-#pragma unroll
-        for (int p = 0; p < NP; ++p)
-#pragma unroll
-            for (int ti = 0; ti < WT; ++ti)
-#pragma unroll
-                for (int j = 0; j < WS; ++j)
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) acc[p][ti][j][c] = acc_t{};
 
         // every wave is done reading the ring of the previous item
         __builtin_amdgcn_s_waitcnt(0);
         block_barrier();
 #pragma unroll
         for (int d = 0; d < D; ++d) issue_next();
-        for (int ch = 0; ch < nchunks; ++ch) {
+        auto chunk = [&](int ch, auto first_c) {
+            constexpr bool FIRST = decltype(first_c)::value;
             // this wave's copies of chunk ch have landed (the D - 1 younger
             // chunks may still be in flight); the barrier publishes every
             // wave's copies and certifies that chunk ch - 1, whose slot the
@@ -383,9 +379,12 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
                         for (int j = 0; j < WS; ++j)
 #pragma unroll
                             for (int c = 0; c < NC; ++c)
-                                acc[p][ti][j][c] = T_::mma(fa[p][ti], fb[j][c], acc[p][ti][j][c]);
+                                acc[p][ti][j][c] = T_::mma(fa[p][ti], fb[j][c],
+                                                           FIRST && kk == 0 ? acc_t{} : acc[p][ti][j][c]);
             }
-        }
+        };
+        chunk(0, std::true_type{});
+        for (int ch = 1; ch < nchunks; ++ch) chunk(ch, std::false_type{});
         // the clamped copies past the last chunk are still landing; with the
         // re-rank scratch in the ring, every wave's copies must have landed
         __builtin_amdgcn_s_waitcnt(0);
