@@ -48,7 +48,8 @@ struct Tuning {
     int range_kb = 0;    // SNP-stationary kernel: trait-range operand budget
     int grouped = -1;    // tiled kernel: XCD-grouped item order
     int shape = -1;      // tiled kernel: tile shape (0 wide, 1 two waves per SIMD, 2 the same
-                         // with the B side from the packed genotype codes)
+                         // with the B side from the packed genotype codes, 3 codes with
+                         // eight-wave blocks)
     double ms = 0.0;     // time of the tuning run
 };
 
@@ -384,18 +385,22 @@ krux_status choose_variant(krux_ctx* c, int K, int precision, Variant* v) {
     return fail(c, KRUX_ERR_UNSUPPORTED, "precision %d not handled by the MFMA path", precision);
 }
 
-// Tile shape of the tiled kernel for (K, precision): the tuned one, else
-// two waves per SIMD, with the B side from the packed codes where the
-// complete-SNP screen is PLAIN (K > 400: kernel 3.99 -> 3.87 ms and no
-// column expansion at K = 500; at K = 200 the DIAG screen of shape 1 is
-// the faster one).
+// Tile shape of the tiled kernel for (K, precision): the tuned one, else,
+// where the complete-SNP screen is PLAIN (K > 400), the B side from the
+// packed codes, with eight-wave blocks in fp16 (shape 3) and four in int8
+// (shape 2), and shape 1 with the DIAG screen below.  Kernel times of one
+// A/B run, shapes 1 / 2 / 3: K = 500 fp16 3.87 / 3.77 / 3.53 ms, int8
+// 4.14 / 4.04 / 4.19 ms, K = 1000 fp16 8.66 / 7.27 / 6.27 ms, K = 200 fp16
+// 1.90 / 1.97 / 2.09 ms.
 int tile_shape_for(krux_ctx* c, int K, int precision) {
     auto it = c->tuned.find({K, precision});
     const int t = it != c->tuned.end() ? it->second.shape : -1;
-    return t >= 0 ? t : (K > 400 ? 2 : 1);
+    if (t >= 0) return t;
+    if (K <= 400) return 1;
+    return precision == KRUX_PREC_INT8 ? 2 : 3;
 }
 
-// Expanded B columns of the tiled kernel; with the codes shape (2) the
+// Expanded B columns of the tiled kernel; with the codes shapes (2, 3) the
 // complete-SNP screen reads the packed genotype rows, and only the
 // missing-genotype columns are built.
 krux_status expand_columns(krux_ctx* c, const Variant& v, const SnpSide& sn, int shape,
@@ -404,16 +409,16 @@ krux_status expand_columns(krux_ctx* c, const Variant& v, const SnpSide& sn, int
     krux_status s = KRUX_OK;
     const int64_t n_pad = ceil_div(std::max<int64_t>(sn.n_snp_tiles, 1), 4) * 4;
     const size_t per_col = (size_t)n_pad * v.ks * kx::kWave * 16;
-    if (shape != 2) out->Bf = ws(c, S_BF, per_col * 2, &s);
+    if (shape < 2) out->Bf = ws(c, S_BF, per_col * 2, &s);
     out->Bf3 = ws(c, S_BF3, per_col * 3, &s);
     if (s != KRUX_OK) return s;
     int grid = (int)std::min<int64_t>(ceil_div(n_pad * v.ks * 3 * kx::kWave, 256), (int64_t)c->n_cu * 16);
     if (v.elem == kx::F16) {
-        if (shape != 2)
+        if (shape < 2)
             HIP_TRY(c, kx_launch_expand_f16(sn.G, sn.gstride, sn.info, n_pad, v.ks, v.form, out->Bf, grid, st));
         HIP_TRY(c, kx_launch_expand_f16(sn.G, sn.gstride, sn.info, n_pad, v.ks, kx::MISS3, out->Bf3, grid, st));
     } else {
-        if (shape != 2)
+        if (shape < 2)
             HIP_TRY(c, kx_launch_expand_i8(sn.G, sn.gstride, sn.info, n_pad, v.ks, v.form, out->Bf, grid, st));
         HIP_TRY(c, kx_launch_expand_i8(sn.G, sn.gstride, sn.info, n_pad, v.ks, kx::MISS3, out->Bf3, grid, st));
     }
@@ -427,8 +432,8 @@ krux_status launch_scan(krux_ctx* c, const kx::ScanArgs& a, const Variant& v, co
         HIP_TRY(c, kx_launch_scan(&a, v.elem, v.ks, form, mode, grid, st));
         return KRUX_OK;
     }
-    // the codes shape builds indicator columns only: PLAIN in place of DIAG
-    if (a.tile_shape == 2 && form == kx::DIAG) form = kx::PLAIN;
+    // the codes shapes build indicator columns only: PLAIN in place of DIAG
+    if (a.tile_shape >= 2 && form == kx::DIAG) form = kx::PLAIN;
     kx::TiledArgs ta{};
     ta.Bf = form == kx::MISS3 ? col.Bf3 : col.Bf;
     ta.A_hi = A_hi;
@@ -1449,7 +1454,7 @@ std::vector<Tuning> tuning_candidates(const Variant& v) {
                 out.push_back(t);
             }
     } else {
-        for (int shape = 0; shape <= 2; ++shape)
+        for (int shape = 0; shape <= 3; ++shape)
             for (int g = 0; g <= 1; ++g) {
                 Tuning t;
                 t.grouped = g;

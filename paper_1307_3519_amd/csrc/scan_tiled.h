@@ -68,28 +68,37 @@ __device__ inline float screen_value(const LaneK& c, float th, float v0, float v
 //        per sample and column) and turned into fragments in registers (byte
 //        permutes), so that a chunk is 18 KB instead of 24 KB, the LDS ring
 //        holds four chunks instead of three, and no expanded columns are
-//        built.
+//        built;
+//  V = 3 ("codes, one block per CU", PLAIN form): eight waves per block
+//        (two per SIMD) as 2 trait groups x 4 SNP tiles, so that a chunk
+//        (16 KB of A, 4 KB of codes) feeds 128 MFMAs instead of 64 and one
+//        140 KB ring holds seven chunks.
 template <int FORM, bool SPLIT, int V>
 struct TiledShape {
     static constexpr int NC = FORM == MISS3 ? 3 : 2;
     static constexpr int NP = SPLIT ? 2 : 1;
+    static constexpr bool CODES = V >= 2;
+    static constexpr int NW = V == 3 ? 8 : 4;            // waves per block
+    static constexpr int GSW = NW / 2;                   // SNP groups (waves per trait group)
     static constexpr int WS = V == 0 ? ((NC == 2 && !SPLIT) ? 2 : 1) : 1;
     static constexpr int WT = V == 0 ? ((FORM != MISS3 && NP * 4 * WS * NC * 16 <= 256) ? 4 : 2)
                                      : (NP * NC <= 2 ? 4 : 2);
+    static constexpr int BT = 2 * WT;                    // trait tiles per block
+    static constexpr int BS = GSW * WS;                  // SNP tiles per block
     static constexpr int ACC = NP * WT * WS * NC * 16;   // accumulator registers
     static constexpr int WPE_MIN = (V != 0 && ACC <= 128) ? 2 : 1;
-    static constexpr int RING_BYTES = V == 0 ? 128 * 1024 : 72 * 1024;
+    static constexpr int RING_BYTES = V == 0 ? 128 * 1024 : V == 3 ? 140 * 1024 : 72 * 1024;
     static constexpr int KC = 2;                         // k-steps per chunk
-    // V = 2: 1 KB copies of codes per SNP tile and chunk (64 lanes x 16
-    // codes: 32 fp16 samples or 64 int8 samples of 32 SNPs)
+    // codes shapes: 1 KB copies of codes per SNP tile and chunk (64 lanes x
+    // 16 codes: 32 fp16 samples or 64 int8 samples of 32 SNPs)
     static constexpr int CPT = SPLIT ? 2 : 1;
-    static constexpr int NFA = 2 * WT * KC * NP;         // A fragments per chunk
-    static constexpr int NFB = V == 2 ? 2 * WS * CPT : 2 * WS * KC * NC;
+    static constexpr int NFA = BT * KC * NP;             // A fragments per chunk
+    static constexpr int NFB = CODES ? BS * CPT : BS * KC * NC;
     static constexpr int NF = NFA + NFB;                 // 1 KB copies per chunk
     // ring of R chunk slots of NF copies (64 lanes x 16 bytes each)
-    static constexpr int R = V == 2 ? (RING_BYTES / (NF * kWave * 16) < 8
-                                           ? RING_BYTES / (NF * kWave * 16) : 8)
-                                    : (NF * kWave * 16 * 4 <= RING_BYTES ? 4 : 3);
+    static constexpr int R = CODES ? (RING_BYTES / (NF * kWave * 16) < 8
+                                          ? RING_BYTES / (NF * kWave * 16) : 8)
+                                   : (NF * kWave * 16 * 4 <= RING_BYTES ? 4 : 3);
     static constexpr int RING_USED = R * NF * kWave * 16;
 };
 
@@ -126,12 +135,12 @@ __device__ inline uint32_t i8_ind(uint32_t w, int k) {
 // enough, else the launch adds dynamic LDS.
 template <int FORM, bool SPLIT, int V>
 __host__ __device__ inline bool tiled_scratch_in_ring(int K) {
-    return (int64_t)kWavesPerBlock * coop_lds_entries(K) * (int64_t)sizeof(int16_t) <=
+    return (int64_t)TiledShape<FORM, SPLIT, V>::NW * coop_lds_entries(K) * (int64_t)sizeof(int16_t) <=
            TiledShape<FORM, SPLIT, V>::RING_USED;
 }
 
 template <int E, int FORM, int MODE, bool SPLIT, int V>
-__global__ __launch_bounds__(256)
+__global__ __launch_bounds__((TiledShape<FORM, SPLIT, V>::NW * 64))
 __attribute__((amdgpu_waves_per_eu(TiledShape<FORM, SPLIT, V>::WPE_MIN, 2)))
 void scan_tiled(ScanArgs a, TiledArgs ta) {
     using T_ = ET<E>;
@@ -143,24 +152,27 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
     constexpr int NP = SH::NP;                         // A planes
     constexpr int KC = SH::KC;                         // k-steps per chunk
     constexpr int WT = SH::WT;                         // trait tiles per wave
-    constexpr int BT = 2 * WT;                         // trait tiles per block
-    constexpr int BS = 2 * WS;                         // SNP tiles per block
+    constexpr int NW = SH::NW;                         // waves per block
+    constexpr int GSW = SH::GSW;                       // waves per trait group
+    constexpr int BT = SH::BT;                         // trait tiles per block
+    constexpr int BS = SH::BS;                         // SNP tiles per block
     constexpr int NFA = BT * KC * NP;                  // A fragments per chunk
     constexpr int NFB = SH::NFB;                       // B fragments (or code copies) per chunk
     constexpr int NF = NFA + NFB;
     static_assert(NFA == SH::NFA && NF == SH::NF, "fragment count");
-    constexpr bool CODES = V == 2;
+    constexpr bool CODES = SH::CODES;
     static_assert(!CODES || (WS == 1 && FORM == PLAIN && SPLIT == (E == I8)),
-                  "the codes shape builds the PLAIN indicator columns of one SNP tile per wave");
-    // copies per wave per chunk: a contiguous run of NF / 4 copies, or (codes
-    // shape) copies wave, wave + 4, ..., which leaves some waves one fewer
-    constexpr int FPW = (NF + kWavesPerBlock - 1) / kWavesPerBlock;
-    constexpr int FPW_MIN = NF / kWavesPerBlock;
-    static_assert(CODES || NF % kWavesPerBlock == 0, "every wave copies the same number of fragments");
+                  "the codes shapes build the PLAIN indicator columns of one SNP tile per wave");
+    // copies per wave per chunk: a contiguous run of NF / NW copies, or
+    // (codes shapes) copies wave, wave + NW, ..., which leaves some waves one
+    // fewer
+    constexpr int FPW = (NF + NW - 1) / NW;
+    constexpr int FPW_MIN = NF / NW;
+    static_assert(CODES || NF % NW == 0, "every wave copies the same number of fragments");
     constexpr bool QUEUE = FORM == MISS3;
     // ring of R chunk slots filled D = R - 1 chunks ahead by LDS-DMA copies
     constexpr int R = SH::R;
-    static_assert(NF * kWave * 16 * R <= 128 * 1024, "ring fits the LDS budget");
+    static_assert(NF * kWave * 16 * R <= 140 * 1024, "ring fits the LDS budget");
     constexpr int D = R - 1;
     // a wave with FPW copies per chunk waits for D - 1 more of its copies
     // than it needs to (still exact for the chunk it is about to read)
@@ -168,8 +180,8 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
     static_assert(kWaitVm <= 63, "wait count fits the vmcnt field");
 
     __shared__ frag s_buf[R][NF][kWave];
-    __shared__ int4 s_queue[QUEUE ? kWavesPerBlock : 1][QUEUE ? kQueueCap : 1];
-    __shared__ uint4 s_stage[MODE == SCREEN ? kWavesPerBlock : 1][kStageCap];
+    __shared__ int4 s_queue[QUEUE ? NW : 1][QUEUE ? kQueueCap : 1];
+    __shared__ uint4 s_stage[MODE == SCREEN ? NW : 1][kStageCap];
     __shared__ ScanArgs s_args;
     extern __shared__ __attribute__((aligned(16))) int16_t s_qbuf[];
     if (threadIdx.x == 0) s_args = a;
@@ -235,7 +247,7 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
         bool any = false;
 #pragma unroll
         for (int j = 0; j < WS; ++j) {
-            stl[j] = sb * BS + (wave & 1) * WS + j;
+            stl[j] = sb * BS + (wave % GSW) * WS + j;
             act[j] = stl[j] < a.n_snp_tiles &&
                      (a.want_flag < 0 || a.tile_flags[stl[j]] == a.want_flag);
             any = any || act[j];
@@ -255,7 +267,7 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
         // (the codes shape copies the B side straight from the packed
         // genotype rows: lane l takes 16 codes of SNP l % 32 of the tile, the
         // first or second half of the chunk's samples per k-step part)
-        auto copy_of = [&](int i) { return CODES ? wave + kWavesPerBlock * i : wave * FPW + i; };
+        auto copy_of = [&](int i) { return CODES ? wave + NW * i : wave * FPW + i; };
         const uint8_t* cp[FPW];
         int cstride[FPW];                              // bytes per chunk
 #pragma unroll
@@ -332,11 +344,11 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
                 for (int p = 0; p < NP; ++p)
 #pragma unroll
                     for (int ti = 0; ti < WT; ++ti)
-                        fa[p][ti] = s_buf[buf][p * BT * KC + ((wave >> 1) * WT + ti) * KC + kk][lane];
+                        fa[p][ti] = s_buf[buf][p * BT * KC + ((wave / GSW) * WT + ti) * KC + kk][lane];
                 if constexpr (CODES) {
                     // indicator columns of classes 1 and 2 from this lane's codes
                     // of the k-step
-                    const uint8_t* cb = (const uint8_t*)&s_buf[buf][NFA + (wave & 1) * SH::CPT][0];
+                    const uint8_t* cb = (const uint8_t*)&s_buf[buf][NFA + (wave % GSW) * SH::CPT][0];
                     if constexpr (E == F16) {
                         // samples 8 (lane / 32) .. + 7 of k-step kk: copy lane
                         // l % 32 + 32 kk, bytes 8 (lane / 32) .. + 7
@@ -369,7 +381,7 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
                     for (int j = 0; j < WS; ++j)
 #pragma unroll
                         for (int c = 0; c < NC; ++c)
-                            fb[j][c] = s_buf[buf][NFA + ((wave & 1) * WS + j) * KC * NC + kk * NC + c][lane];
+                            fb[j][c] = s_buf[buf][NFA + ((wave % GSW) * WS + j) * KC * NC + kk * NC + c][lane];
                 }
 #pragma unroll
                 for (int p = 0; p < NP; ++p)
@@ -400,7 +412,7 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
             const LaneK lk = lane_constants(inf, a.K, a.inv_hc);
             static_for<WT>([&](auto tic) {
                 constexpr int ti = decltype(tic)::value;
-                const int64_t tt = tb * BT + (wave >> 1) * WT + ti;
+                const int64_t tt = tb * BT + (wave / GSW) * WT + ti;
                 if (tt >= n_tiles) return;
                 const int64_t rb = tt * kTile + 4 * (lane >> 5);
                 auto colv = [&](auto cc, auto rc) -> float {
@@ -524,30 +536,36 @@ __global__ __launch_bounds__(256) void expand_columns(const int8_t* __restrict__
     }
 }
 
-template <int E, int FORM, int MODE, bool SPLIT>
-inline hipError_t launch_tiled(const ScanArgs& a, const TiledArgs& ta, int grid, hipStream_t st) {
-    // the codes shape (2) covers the complete-SNP screen (the host runs
-    // PLAIN in place of DIAG there); the missing-genotype form keeps the
-    // expanded columns of shape 1 (built from codes its registers overflow)
-    constexpr int V2 = FORM == PLAIN ? 2 : 1;
-    const bool in_ring = ta.shape == 2   ? tiled_scratch_in_ring<FORM, SPLIT, V2>(a.K)
-                         : ta.shape == 1 ? tiled_scratch_in_ring<FORM, SPLIT, 1>(a.K)
-                                         : tiled_scratch_in_ring<FORM, SPLIT, 0>(a.K);
-    size_t lds = FORM == MISS3 && !in_ring
-                     ? (size_t)kWavesPerBlock * coop_lds_entries(a.K) * sizeof(int16_t) : 0;
-    auto kern = ta.shape == 2   ? scan_tiled<E, FORM, MODE, SPLIT, V2>
-                : ta.shape == 1 ? scan_tiled<E, FORM, MODE, SPLIT, 1>
-                                : scan_tiled<E, FORM, MODE, SPLIT, 0>;
+template <int E, int FORM, int MODE, bool SPLIT, int V>
+inline hipError_t launch_tiled_v(const ScanArgs& a, const TiledArgs& ta, int grid, hipStream_t st) {
+    using SH = TiledShape<FORM, SPLIT, V>;
+    const size_t lds = FORM == MISS3 && !tiled_scratch_in_ring<FORM, SPLIT, V>(a.K)
+                           ? (size_t)SH::NW * coop_lds_entries(a.K) * sizeof(int16_t) : 0;
+    auto kern = scan_tiled<E, FORM, MODE, SPLIT, V>;
     int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 256, lds) != hipSuccess || occ < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, SH::NW * 64, lds) != hipSuccess ||
+        occ < 1)
         occ = 1;
     int dev = 0, n_cu = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
     int64_t resident = (int64_t)n_cu * occ;
     int g = (int)(grid < resident ? grid : resident);
-    hipLaunchKernelGGL(kern, dim3(g), dim3(256), lds, st, a, ta);
+    hipLaunchKernelGGL(kern, dim3(g), dim3(SH::NW * 64), lds, st, a, ta);
     return hipGetLastError();
+}
+
+// The codes shapes (2, 3) cover the complete-SNP screen (the host runs PLAIN
+// in place of DIAG there); the missing-genotype form keeps the expanded
+// columns of shape 1 (built from codes its registers overflow).
+template <int E, int FORM, int MODE, bool SPLIT>
+inline hipError_t launch_tiled(const ScanArgs& a, const TiledArgs& ta, int grid, hipStream_t st) {
+    if constexpr (FORM == PLAIN) {
+        if (ta.shape == 3) return launch_tiled_v<E, FORM, MODE, SPLIT, 3>(a, ta, grid, st);
+        if (ta.shape == 2) return launch_tiled_v<E, FORM, MODE, SPLIT, 2>(a, ta, grid, st);
+    }
+    if (ta.shape == 0) return launch_tiled_v<E, FORM, MODE, SPLIT, 0>(a, ta, grid, st);
+    return launch_tiled_v<E, FORM, MODE, SPLIT, 1>(a, ta, grid, st);
 }
 
 }  // namespace kx

@@ -41,7 +41,7 @@ def test_autotune_choice_persists_and_keeps_results(tmp_path, K, prec, pm):
         if K <= 128:
             assert chosen["ring"] in (0, 1, 2, 3, 4) and chosen["range_kb"] in (640, 1280, 2560, 5120)
         else:
-            assert chosen["grouped"] in (0, 1) and chosen["shape"] in (0, 1, 2)
+            assert chosen["grouped"] in (0, 1) and chosen["shape"] in (0, 1, 2, 3)
         res = ctx.test(r, ts, gd, p_c=0.01, precision=prec, hit_capacity=1 << 14, min_p=True)
         torch.cuda.synchronize()
         n, h = krux.unpack_hits(res)
@@ -100,7 +100,7 @@ def test_every_pipeline_matches_oracle(tmp_path, ring, prec, K, M):
 _TILE_ORACLE = {}
 
 
-@pytest.mark.parametrize("shape", [0, 1, 2])
+@pytest.mark.parametrize("shape", [0, 1, 2, 3])
 @pytest.mark.parametrize("prec", ["fp16", "int8"])
 @pytest.mark.parametrize("K,T,M,pm", [(233, 300, 19000, 0.0001), (500, 520, 12000, 0.0),
                                       (150, 64, 40000, 0.001)])
@@ -138,7 +138,7 @@ def test_every_tile_shape_matches_oracle(tmp_path, shape, prec, K, T, M, pm):
         ctx.close()
 
 
-@pytest.mark.parametrize("shape", [0, 1, 2])
+@pytest.mark.parametrize("shape", [0, 1, 2, 3])
 @pytest.mark.parametrize("prec", ["fp16", "int8"])
 @pytest.mark.parametrize("K,pm", [(233, 0.02), (1000, 0.02), (300, 0.0)])
 def test_every_tile_shape_full_and_sums(tmp_path, shape, prec, K, pm):
