@@ -69,15 +69,17 @@ __device__ inline float screen_value(const LaneK& c, float th, float v0, float v
 //        permutes), so that a chunk is 18 KB instead of 24 KB, the LDS ring
 //        holds four chunks instead of three, and no expanded columns are
 //        built;
-//  V = 3 ("codes, one block per CU", PLAIN form): eight waves per block
-//        (two per SIMD) as 2 trait groups x 4 SNP tiles, so that a chunk
-//        (16 KB of A, 4 KB of codes) feeds 128 MFMAs instead of 64 and one
-//        140 KB ring holds seven chunks.
+//  V = 3 ("one block per CU"): eight waves per block (two per SIMD) as 2
+//        trait groups x 4 SNP tiles, the B side from the codes in the PLAIN
+//        form (a chunk of 16 KB of A and 4 KB of codes feeds 128 MFMAs
+//        instead of 64, and one 140 KB ring holds seven chunks) and expanded
+//        in the missing-genotype form (32 KB per 96 MFMAs instead of 20 KB
+//        per 48, four chunks).
 template <int FORM, bool SPLIT, int V>
 struct TiledShape {
     static constexpr int NC = FORM == MISS3 ? 3 : 2;
     static constexpr int NP = SPLIT ? 2 : 1;
-    static constexpr bool CODES = V >= 2;
+    static constexpr bool CODES = V >= 2 && FORM == PLAIN;
     static constexpr int NW = V == 3 ? 8 : 4;            // waves per block
     static constexpr int GSW = NW / 2;                   // SNP groups (waves per trait group)
     static constexpr int WS = V == 0 ? ((NC == 2 && !SPLIT) ? 2 : 1) : 1;
@@ -556,13 +558,16 @@ inline hipError_t launch_tiled_v(const ScanArgs& a, const TiledArgs& ta, int gri
 }
 
 // The codes shapes (2, 3) cover the complete-SNP screen (the host runs PLAIN
-// in place of DIAG there); the missing-genotype form keeps the expanded
-// columns of shape 1 (built from codes its registers overflow).
+// in place of DIAG there); the missing-genotype form keeps expanded columns
+// (built from codes its registers overflow), in eight-wave blocks for shape
+// 3 and in the four-wave tiles of shape 1 for shape 2.
 template <int E, int FORM, int MODE, bool SPLIT>
 inline hipError_t launch_tiled(const ScanArgs& a, const TiledArgs& ta, int grid, hipStream_t st) {
     if constexpr (FORM == PLAIN) {
         if (ta.shape == 3) return launch_tiled_v<E, FORM, MODE, SPLIT, 3>(a, ta, grid, st);
         if (ta.shape == 2) return launch_tiled_v<E, FORM, MODE, SPLIT, 2>(a, ta, grid, st);
+    } else if constexpr (FORM == MISS3) {
+        if (ta.shape == 3) return launch_tiled_v<E, FORM, MODE, SPLIT, 3>(a, ta, grid, st);
     }
     if (ta.shape == 0) return launch_tiled_v<E, FORM, MODE, SPLIT, 0>(a, ta, grid, st);
     return launch_tiled_v<E, FORM, MODE, SPLIT, 1>(a, ta, grid, st);

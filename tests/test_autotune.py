@@ -103,7 +103,7 @@ _TILE_ORACLE = {}
 @pytest.mark.parametrize("shape", [0, 1, 2, 3])
 @pytest.mark.parametrize("prec", ["fp16", "int8"])
 @pytest.mark.parametrize("K,T,M,pm", [(233, 300, 19000, 0.0001), (500, 520, 12000, 0.0),
-                                      (150, 64, 40000, 0.001)])
+                                      (150, 64, 40000, 0.001), (1000, 64, 40000, 0.00002)])
 def test_every_tile_shape_matches_oracle(tmp_path, shape, prec, K, T, M, pm):
     # each tile shape of the K > 128 kernel (wide, two waves per SIMD, B side
     # from the packed codes) forced through a cache entry, with more work
