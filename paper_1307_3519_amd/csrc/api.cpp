@@ -260,8 +260,8 @@ krux_status pack_snps(krux_ctx* c, const int8_t* geno, int64_t M, int64_t ld, in
     // packed rows cover every sample the kernels read (k-steps x samples per step)
     out->gstride = (int)ceil_div(std::max<int64_t>(K, row_bytes), 32) * 32;
     out->n_snp_tiles = ceil_div(M, kx::kTile);
-    // rounded to whole blocks of 4 SNP tiles: the tiled kernel reads them
-    int64_t m_pad = std::max<int64_t>(ceil_div(out->n_snp_tiles, 4) * 4, 4) * kx::kTile;
+    // rounded to whole blocks of 8 SNP tiles: the tiled kernel reads them
+    int64_t m_pad = std::max<int64_t>(ceil_div(out->n_snp_tiles, 8) * 8, 8) * kx::kTile;
     out->G = (int8_t*)ws(c, S_PACKED, (size_t)m_pad * out->gstride, &s);
     out->info = (kx::SnpInfo*)ws(c, S_INFO, (size_t)m_pad * sizeof(kx::SnpInfo), &s);
     out->flags = (int32_t*)ws(c, S_FLAGS, (size_t)(m_pad / kx::kTile + 1) * 4, &s);

@@ -81,15 +81,24 @@ struct TiledShape {
     static constexpr int NP = SPLIT ? 2 : 1;
     static constexpr bool CODES = V >= 2 && FORM == PLAIN;
     static constexpr int NW = V == 3 ? 8 : 4;            // waves per block
-    static constexpr int GSW = NW / 2;                   // SNP groups (waves per trait group)
+    // SNP groups (waves per trait group): eight-wave blocks take one trait
+    // group of eight SNP tiles in the fp16 codes form (codes are the small
+    // side; K = 500 3.68 -> 3.62 ms, K = 1000 6.72 -> 6.51 ms against 2 x 4),
+    // two of four in the int8 one (its A side has two planes; 1 x 8 4.17 ->
+    // 4.38 ms) and four trait groups of two SNP tiles in the missing-genotype
+    // form (its three expanded columns are the large side; K = 1000 17.9 ->
+    // 17.5 ms)
+    static constexpr int GSW = V == 3 ? (FORM == MISS3 ? 2 : SPLIT ? 4 : 8) : 2;
+    static constexpr int GTW = NW / GSW;                 // trait groups
     static constexpr int WS = V == 0 ? ((NC == 2 && !SPLIT) ? 2 : 1) : 1;
     static constexpr int WT = V == 0 ? ((FORM != MISS3 && NP * 4 * WS * NC * 16 <= 256) ? 4 : 2)
                                      : (NP * NC <= 2 ? 4 : 2);
-    static constexpr int BT = 2 * WT;                    // trait tiles per block
+    static constexpr int BT = GTW * WT;                  // trait tiles per block
     static constexpr int BS = GSW * WS;                  // SNP tiles per block
     static constexpr int ACC = NP * WT * WS * NC * 16;   // accumulator registers
     static constexpr int WPE_MIN = (V != 0 && ACC <= 128) ? 2 : 1;
-    static constexpr int RING_BYTES = V == 0 ? 128 * 1024 : V == 3 ? 140 * 1024 : 72 * 1024;
+    static constexpr int RING_BYTES =
+        V == 0 ? 128 * 1024 : V == 3 ? (FORM == MISS3 ? 128 * 1024 : 140 * 1024) : 72 * 1024;
     static constexpr int KC = 2;                         // k-steps per chunk
     // codes shapes: 1 KB copies of codes per SNP tile and chunk (64 lanes x
     // 16 codes: 32 fp16 samples or 64 int8 samples of 32 SNPs)
@@ -98,9 +107,9 @@ struct TiledShape {
     static constexpr int NFB = CODES ? BS * CPT : BS * KC * NC;
     static constexpr int NF = NFA + NFB;                 // 1 KB copies per chunk
     // ring of R chunk slots of NF copies (64 lanes x 16 bytes each)
-    static constexpr int R = CODES ? (RING_BYTES / (NF * kWave * 16) < 8
-                                          ? RING_BYTES / (NF * kWave * 16) : 8)
-                                   : (NF * kWave * 16 * 4 <= RING_BYTES ? 4 : 3);
+    static constexpr int R = (CODES || V == 3) ? (RING_BYTES / (NF * kWave * 16) < 8
+                                                      ? RING_BYTES / (NF * kWave * 16) : 8)
+                                               : (NF * kWave * 16 * 4 <= RING_BYTES ? 4 : 3);
     static constexpr int RING_USED = R * NF * kWave * 16;
 };
 
@@ -166,11 +175,12 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
     static_assert(!CODES || (WS == 1 && FORM == PLAIN && SPLIT == (E == I8)),
                   "the codes shapes build the PLAIN indicator columns of one SNP tile per wave");
     // copies per wave per chunk: a contiguous run of NF / NW copies, or
-    // (codes shapes) copies wave, wave + NW, ..., which leaves some waves one
-    // fewer
+    // (codes shapes and eight-wave blocks) copies wave, wave + NW, ..., which
+    // leaves some waves one fewer
+    constexpr bool SPREAD = CODES || V == 3;
     constexpr int FPW = (NF + NW - 1) / NW;
     constexpr int FPW_MIN = NF / NW;
-    static_assert(CODES || NF % NW == 0, "every wave copies the same number of fragments");
+    static_assert(SPREAD || NF % NW == 0, "every wave copies the same number of fragments");
     constexpr bool QUEUE = FORM == MISS3;
     // ring of R chunk slots filled D = R - 1 chunks ahead by LDS-DMA copies
     constexpr int R = SH::R;
@@ -269,7 +279,7 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
         // (the codes shape copies the B side straight from the packed
         // genotype rows: lane l takes 16 codes of SNP l % 32 of the tile, the
         // first or second half of the chunk's samples per k-step part)
-        auto copy_of = [&](int i) { return CODES ? wave + NW * i : wave * FPW + i; };
+        auto copy_of = [&](int i) { return SPREAD ? wave + NW * i : wave * FPW + i; };
         const uint8_t* cp[FPW];
         int cstride[FPW];                              // bytes per chunk
 #pragma unroll
@@ -289,7 +299,7 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
                         16 * (lane >> 5);
                 cstride[i] = KC * T_::kps;
             } else {
-                const int g = f - NFA;
+                const int g = f < NF ? f - NFA : 0;
                 const int s2 = g / (KC * NC), r = g % (KC * NC);
                 const int kk = r / NC, c = r % NC;
                 const int64_t st = sb * BS + s2;
@@ -303,7 +313,7 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
 #pragma unroll
             for (int i = 0; i < FPW; ++i) {
                 const int f = copy_of(i);
-                if (CODES && f >= NF) continue;        // uniform per wave
+                if (SPREAD && f >= NF) continue;       // uniform per wave
                 const uint32_t dst = sbase + (uint32_t)(f * kWave * 16);
                 asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
                              :
