@@ -538,7 +538,8 @@ krux_status run_screen(krux_ctx* c, kx::ScanArgs a, const Variant& v, const Colu
     // pairs of SNPs with missing genotypes that pass the bound: up to 1/16 of
     // the pairs, at most 2^27 entries (2 GB of the 288 GB); the rest are
     // evaluated in the scan kernel itself, which is several times slower (at
-    // the 64/M screen level of a min-p run, a few percent of the pairs pass)
+    // the 16/M-64/M screen level of a min-p run, a few percent of the pairs
+    // pass)
     a.mcand_cap = pair_limit(
         std::min<int64_t>(std::max<int64_t>(n_rows_max * a.M / 16, 1 << 16), 1LL << 27),
         c->mcand_limit);
@@ -570,12 +571,17 @@ krux_status run_screen(krux_ctx* c, kx::ScanArgs a, const Variant& v, const Colu
 
 // Main-pass screen level when per-row minima are wanted.  The chi-square
 // p-values of the test are conservative in the far tail (a trait's smallest p
-// over M null SNPs is typically several times 1/M), so the level is 64/M:
-// then nearly every row has an exactly evaluated pair below it and the
-// fix-up passes see few rows (at 8/M a quarter of the rows stayed open at
-// K = 48 and an eighth at K = 102).
-double screen_level_for_min_p(double p_c, int64_t M) {
-    return std::max(p_c, std::min(1.0, 64.0 / (double)std::max<int64_t>(M, 1)));
+// over M null SNPs is typically several times 1/M), so the level is a
+// multiple of 1/M: then nearly every row has an exactly evaluated pair below
+// it and the fix-up passes see few rows, while the pairs staged and evaluated
+// grow with the level.  At 8/M a quarter of the rows stayed open at K = 48
+// and an eighth at K = 102; at K = 102, 16/M against 64/M took the
+// 200-permutation step from 156 to 140 ms and the paper-scale hit step from
+// 3.44 to 3.39 ms (8/M: 155 and 4.13 ms).  Below 96 samples, where the tail
+// is coarser, the level stays 64/M.
+double screen_level_for_min_p(double p_c, int64_t M, int K) {
+    const double per_m = K >= 96 ? 16.0 : 64.0;
+    return std::max(p_c, std::min(1.0, per_m / (double)std::max<int64_t>(M, 1)));
 }
 
 int bit_length(int64_t v) {
@@ -749,7 +755,7 @@ krux_status test_impl(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum,
     // p_screen >= p_c (hits are still only the pairs beyond H_c(p_c)); p_screen
     // is set so that a row of M SNPs almost surely has an exact candidate, and
     // the few rows without one get the looser passes of resolve_min_p.
-    const double p_screen = min_p ? screen_level_for_min_p(p_c, M) : p_c;
+    const double p_screen = min_p ? screen_level_for_min_p(p_c, M, K) : p_c;
     set_screen(&a, p_screen);
     a.cand_cap = pair_limit(candidate_capacity(T, M, p_screen), c->cand_limit);
     if ((s = run_screen(c, a, v, col, rk.A_hi, st, T, true)) != KRUX_OK) return s;
@@ -1015,7 +1021,7 @@ krux_status permute_impl(krux_ctx* c, const int16_t* ranks2, const int64_t* ties
     a.minp_bits = min_p ? minp : nullptr;
     set_levels(&a, p_cs, n_thr);
     double loosest = *std::max_element(p_cs, p_cs + n_thr);
-    if (min_p) loosest = screen_level_for_min_p(loosest, M);
+    if (min_p) loosest = screen_level_for_min_p(loosest, M, K);
     set_screen(&a, loosest);
     a.cand_cap = pair_limit(candidate_capacity(V, M, loosest), c->cand_limit);
     if ((s = run_screen(c, a, v, col, rk.A_hi, st, V, true)) != KRUX_OK) return s;
@@ -1366,7 +1372,7 @@ krux_status krux_test_multi(krux_ctx* c, const int16_t* ranks2, const int64_t* t
             a.tiles_per_range = trait_range(v, T, a.n_snp_tiles, c->n_cu);
             a.nan_flag = ns.flag;
             a.n_nan = ns.n;
-            const double p_screen = min_p ? screen_level_for_min_p(p_c, M) : p_c;
+            const double p_screen = min_p ? screen_level_for_min_p(p_c, M, K) : p_c;
             for (int df = 1; df < n_classes; ++df) {
                 // 1/H_c(df) capped: at p_screen = 1 (H_c = 0) every pair with
                 // a non-zero class sum passes, and no 0 * inf appears
