@@ -3,16 +3,16 @@
 //
 // Same computation as scan_kernel (eq. (1), eq. (2) with the tie factor, the
 // chi-square screen and exact evaluation of candidates), organised as a
-// classic two-operand tiled GEMM: a block computes 128 or 256 traits x 64 or
-// 128 SNPs, each wave 2 or 4 trait tiles x 1 or 2 SNP tiles (see TiledShape:
-// either as many accumulators as fit in 256 registers, one wave per SIMD, or
-// half as many with two waves per SIMD, whose epilogues then overlap the other
-// wave's MFMAs; the second is the faster one measured).  The K loop runs over chunks of two
-// 16-sample (fp16) or 32-sample (int8) k-steps whose A (centred ranks) and B
-// (genotype columns, expanded once into MFMA fragment order) fragments are
-// copied into an LDS ring by LDS-DMA loads, with one block barrier per chunk.
-// With int8 and K > 127 the centred rank is split into bytes,
-// c = 128 h + l, and two accumulator sets give D = 128 D_h + D_l exactly.
+// classic two-operand tiled GEMM: each wave computes 2 or 4 trait tiles x 1
+// or 2 SNP tiles, in blocks of four waves (one or two blocks per CU) or of
+// eight (one per CU); see TiledShape for the four shapes.  The K loop runs
+// over chunks of two 16-sample (fp16) or 32-sample (int8) k-steps whose A
+// (centred ranks) fragments and B side (genotype columns expanded once into
+// MFMA fragment order, or the packed genotype codes themselves, from which
+// the fragments are built in registers) are copied into an LDS ring by
+// LDS-DMA loads, with one block barrier per chunk.  With int8 and K > 127
+// the centred rank is split into bytes, c = 128 h + l, and two accumulator
+// sets give D = 128 D_h + D_l exactly.
 #pragma once
 #include "scan_kernel.h"
 
