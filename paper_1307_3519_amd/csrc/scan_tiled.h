@@ -445,6 +445,56 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
                                                               NC == 3 ? colv(CL{}, rc) : 0.0f));
                     });
                     if (!__any(gmax > 0.0f)) return;
+                    if constexpr (QUEUE && V == 3) {
+                        // The rows with a passing pair (per lane, then over the
+                        // wave), then one loop over those rows: the queue and
+                        // staging code (and the drains and fallbacks inlined in
+                        // it) appear once instead of once per row, a quarter of
+                        // the instructions (K = 1000: 17.6 -> 16.3 ms).  In the
+                        // four-wave tiles the extra mask work outweighs it
+                        // (K = 233: 9.1 -> 10.3 ms), so they keep the unrolled
+                        // rows.
+                        uint32_t qm = 0, cm = 0;
+                        static_for<16>([&](auto rc) {
+                            constexpr int r = decltype(rc)::value;
+                            const bool pass = screen_value<FORM>(lk, th, colv(C0{}, rc), colv(C1{}, rc),
+                                                                 colv(CL{}, rc)) > 0.0f;
+                            qm |= (pass && lk.miss) ? (1u << r) : 0u;
+                            cm |= (pass && !lk.miss) ? (1u << r) : 0u;
+                        });
+                        uint32_t rows = qm | cm;
+#pragma unroll
+                        for (int o = 32; o > 0; o >>= 1) rows |= (uint32_t)__shfl_xor((int)rows, o, 64);
+                        rows = __builtin_amdgcn_readfirstlane(rows);
+                        while (rows) {
+                            const int r = __builtin_ctz(rows);      // uniform
+                            rows &= rows - 1u;
+                            const int64_t row = rb + 8 * (r >> 2) + (r & 3);
+                            // the row's column values, selected with compile-time
+                            // register indices
+                            float v1 = 0.0f, v2 = 0.0f;
+                            static_for<16>([&](auto rc) {
+                                constexpr int rr = decltype(rc)::value;
+                                if (r == rr) {
+                                    v1 = colv(C1{}, rc);
+                                    v2 = colv(CL{}, rc);
+                                }
+                            });
+                            const bool qpush = (qm >> r) & 1u;
+                            const unsigned long long msk = __ballot(qpush);
+                            if (msk) {
+                                if (qn + 64 > kQueueCap) drain<MODE>(a, queue, qn, qbuf, lane);
+                                const unsigned long long lt =
+                                    (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+                                if (qpush)
+                                    queue[qn + __popcll(msk & lt)] =
+                                        make_int4((int)row, (int)m, (int)v1, (int)v2);
+                                qn += __popcll(msk);
+                            }
+                            const bool cand = (cm >> r) & 1u;
+                            stage_candidates(a, &s_args, stage, sn, lane, cand, row, m, v1, v2, kCandPlain);
+                        }
+                    } else {
                     static_for<16>([&](auto rc) {
                         constexpr int r = decltype(rc)::value;
                         const int64_t row = rb + 8 * (r >> 2) + (r & 3);
@@ -472,6 +522,7 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
                         else
                             stage_candidates(a, &s_args, stage, sn, lane, cand, row, m, v1, v2, kCandPlain);
                     });
+                    }
                     // the queue carries over to the next tile (drained when
                     // nearly full and at the end of the kernel)
                 } else if constexpr (FORM == MISS3) {
