@@ -350,9 +350,8 @@ krux_status krux_load_tuning(krux_ctx* ctx, const char* cache_path);
  * K > 128 kernel: grouped (XCD-grouped item order) and shape (0 wide tiles,
  * one wave per SIMD; 1 two waves per SIMD; 2 as 1 with the complete-SNP
  * screen reading the packed genotype codes, PLAIN form; 3 as 2 with
- * eight-wave blocks; under 2 and 3 the missing-genotype screen runs in
- * eight-wave blocks from K = 768 and as under 1 below).  -1 / 0 mean the
- * built-in rule.
+ * eight-wave blocks, also for the missing-genotype screen, which runs as
+ * under 1 in shape 2).  -1 / 0 mean the built-in rule.
  * Host outputs, each nullable. */
 krux_status krux_tuning_of(krux_ctx* ctx, int32_t K, int32_t precision, int32_t* ring,
                            int32_t* range_kb, int32_t* grouped, int32_t* shape);

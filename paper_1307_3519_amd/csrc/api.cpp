@@ -387,17 +387,20 @@ krux_status choose_variant(krux_ctx* c, int K, int precision, Variant* v) {
 
 // Tile shape of the tiled kernel for (K, precision): the tuned one, else,
 // where the complete-SNP screen is PLAIN (K > 400), the B side from the
-// packed codes, with eight-wave blocks in fp16 (shape 3) and four in int8
-// (shape 2), and shape 1 with the DIAG screen below.  Kernel times of one
-// A/B run, shapes 1 / 2 / 3: K = 500 fp16 3.87 / 3.77 / 3.53 ms, int8
-// 4.14 / 4.04 / 4.19 ms, K = 1000 fp16 8.66 / 7.27 / 6.27 ms, K = 200 fp16
-// 1.90 / 1.97 / 2.09 ms.
+// packed codes, with eight-wave blocks in fp16 (shape 3) and in int8 from
+// K = 768 (shape 2, four-wave blocks, below), and shape 1 with the DIAG
+// screen up to K = 400.  Complete-SNP kernel times of one A/B run, shapes
+// 1 / 2 / 3: K = 500 fp16 3.87 / 3.77 / 3.53 ms, int8 4.14 / 4.04 / 4.19
+// ms, K = 1000 fp16 8.66 / 7.27 / 6.27 ms, K = 200 fp16 1.90 / 1.97 / 2.09
+// ms.  The missing-genotype screen (shape 1 against 3): K = 1000 fp16 20.9
+// -> 17.9 ms and int8 12.3 -> 9.5 ms, K = 512 18.0 -> 16.9 ms, K = 380
+// 5.2 -> 5.6 ms.
 int tile_shape_for(krux_ctx* c, int K, int precision) {
     auto it = c->tuned.find({K, precision});
     const int t = it != c->tuned.end() ? it->second.shape : -1;
     if (t >= 0) return t;
     if (K <= 400) return 1;
-    return precision == KRUX_PREC_INT8 ? 2 : 3;
+    return precision == KRUX_PREC_INT8 && K < 768 ? 2 : 3;
 }
 
 // Expanded B columns of the tiled kernel; with the codes shapes (2, 3) the
@@ -439,11 +442,9 @@ krux_status launch_scan(krux_ctx* c, const kx::ScanArgs& a, const Variant& v, co
     ta.A_hi = A_hi;
     ta.ks = v.ks;
     ta.shape = a.tile_shape;
-    // the missing-genotype form under the codes shapes: eight-wave blocks
-    // from K = 768 (K = 1000 cohort, 12 145 x 200 000: 20.9 -> 17.9 ms fp16,
-    // int8 12.3 -> 9.5 ms at 100 000 SNPs), the four-wave tiles below
-    // (K = 233, 380, 512: 3-7 % slower in eight-wave blocks)
-    if (form == kx::MISS3 && ta.shape >= 2) ta.shape = a.K >= 768 ? 3 : 1;
+    // the missing-genotype form has no codes shape: shape 2 runs it in the
+    // four-wave tiles of shape 1, shape 3 in eight-wave blocks
+    if (form == kx::MISS3 && ta.shape == 2) ta.shape = 1;
     if (v.elem == kx::F16) HIP_TRY(c, kx_launch_tiled_f16(&a, &ta, form, mode, grid, st));
     else HIP_TRY(c, kx_launch_tiled_i8(&a, &ta, form, mode, grid, st));
     return KRUX_OK;

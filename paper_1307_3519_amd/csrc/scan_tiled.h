@@ -621,7 +621,7 @@ inline hipError_t launch_tiled_v(const ScanArgs& a, const TiledArgs& ta, int gri
 // The codes shapes (2, 3) cover the complete-SNP screen (the host runs PLAIN
 // in place of DIAG there); the missing-genotype form keeps expanded columns
 // (built from codes its registers overflow), in eight-wave blocks for shape
-// 3 and in the four-wave tiles of shape 1 for shape 2.
+// 3 (the host runs it as shape 1 under shape 2).
 template <int E, int FORM, int MODE, bool SPLIT>
 inline hipError_t launch_tiled(const ScanArgs& a, const TiledArgs& ta, int grid, hipStream_t st) {
     if constexpr (FORM == PLAIN) {
