@@ -21,7 +21,7 @@
 namespace {
 
 enum Slot {
-    S_PACKED, S_INFO, S_FLAGS, S_A, S_THETA, S_ROWV, S_A2, S_THETA2, S_ROWV2,
+    S_PACKED, S_INFO, S_FLAGS, S_MPOS, S_A, S_THETA, S_ROWV, S_A2, S_THETA2, S_ROWV2,
     S_LIST_A, S_LIST_B, S_COUNT_A, S_COUNT_B, S_MINP, S_STAGE, S_NHITS, S_KEYS, S_IDX,
     S_SORT_TMP, S_F64_R, S_F64_I, S_F64_S, S_COUNT_PREV, S_CAND, S_NCAND, S_MCAND, S_NMCAND,
     S_TUNE_HITS, S_TUNE_N,
@@ -250,6 +250,7 @@ struct SnpSide {
     int8_t* G = nullptr;
     kx::SnpInfo* info = nullptr;
     int32_t* flags = nullptr;
+    int16_t* mpos = nullptr;
     int gstride = 0;
     int64_t n_snp_tiles = 0;
 };
@@ -265,12 +266,13 @@ krux_status pack_snps(krux_ctx* c, const int8_t* geno, int64_t M, int64_t ld, in
     out->G = (int8_t*)ws(c, S_PACKED, (size_t)m_pad * out->gstride, &s);
     out->info = (kx::SnpInfo*)ws(c, S_INFO, (size_t)m_pad * sizeof(kx::SnpInfo), &s);
     out->flags = (int32_t*)ws(c, S_FLAGS, (size_t)(m_pad / kx::kTile + 1) * 4, &s);
+    out->mpos = (int16_t*)ws(c, S_MPOS, (size_t)m_pad * kx::kLaneMiss * sizeof(int16_t), &s);
     if (s != KRUX_OK) return s;
     // one wave per SNP row, enough blocks to cover every row at once (the
     // kernel is latency-bound when waves loop over many rows)
     int grid = (int)std::min<int64_t>(ceil_div(m_pad, 4), (int64_t)INT32_MAX / 4);
     HIP_TRY(c, kx_launch_pack(geno, M, ld, K, m_pad, out->gstride, diag_ok ? 1 : 0, out->G,
-                              out->info, out->flags, std::max(grid, 1), st));
+                              out->info, out->flags, out->mpos, std::max(grid, 1), st));
     return KRUX_OK;
 }
 
@@ -724,6 +726,7 @@ krux_status test_impl(krux_ctx* c, const int16_t* ranks2, const int64_t* tiesum,
     a.A = rk.A; a.theta = rk.theta; a.row_v = rk.row_v; a.d_nrows = nullptr; a.n_rows = T;
     a.T = std::max<int64_t>(T, 1); a.tiesum = tiesum; a.ranks2 = ranks2; a.perms = nullptr;
     a.G = sn.G; a.gstride = sn.gstride; a.info = sn.info; a.tile_flags = sn.flags;
+    a.mpos = sn.mpos;
     a.M = M; a.n_snp_tiles = sn.n_snp_tiles; a.K = K;
     apply_tuning(c, K, precision, v, T, sn.n_snp_tiles, &a);
     a.snp_base = snp_base;
@@ -1015,6 +1018,7 @@ krux_status permute_impl(krux_ctx* c, const int16_t* ranks2, const int64_t* ties
     a.A = rk.A; a.theta = rk.theta; a.row_v = rk.row_v; a.d_nrows = nullptr; a.n_rows = V;
     a.T = std::max<int64_t>(T, 1); a.tiesum = tiesum; a.ranks2 = ranks2; a.perms = perms;
     a.G = sn.G; a.gstride = sn.gstride; a.info = sn.info; a.tile_flags = sn.flags;
+    a.mpos = sn.mpos;
     a.M = M; a.n_snp_tiles = sn.n_snp_tiles; a.K = K;
     apply_tuning(c, K, KRUX_PREC_FP16, v, V, sn.n_snp_tiles, &a);
     a.hits = stage; a.hit_cap = n_hits ? hit_capacity : 0; a.n_hits = nh;

@@ -31,6 +31,7 @@ enum { SCREEN = 0, FULL = 1, SUMS = 2 };
 enum { F16 = 0, I8 = 1 };
 
 constexpr int kQueueCap = 128;     // per-wave queue of pairs needing a re-rank
+constexpr int kLaneMiss = 32;      // missing-sample positions listed per SNP (int16 each)
 
 struct ScanArgs {
     const void* A;            // operand tiles in fragment order
@@ -81,6 +82,10 @@ struct ScanArgs {
     int4* mcand;
     int64_t mcand_cap;
     unsigned long long* n_mcand;
+    // [m_pad][kLaneMiss] positions of the missing samples of each SNP with 1
+    // to kLaneMiss of them, ascending (written by pack_snps); other entries
+    // are unused
+    const int16_t* mpos;
 };
 
 // Multi-allelic scan (classes 0..n_classes-1, at most kMaxClasses).

@@ -21,7 +21,7 @@ hipError_t kx_launch_rank(const float* expr, int64_t T, int K, int64_t ld, int16
                           int64_t* tiesum, int32_t* nvalid, int max_blocks, hipStream_t st);
 hipError_t kx_launch_pack(const int8_t* geno, int64_t M, int64_t ld, int K, int64_t m_pad,
                           int gstride, int diag_ok, int8_t* gp, kx::SnpInfo* info,
-                          int32_t* tile_flags, int grid, hipStream_t st);
+                          int32_t* tile_flags, int16_t* mpos, int grid, hipStream_t st);
 hipError_t kx_launch_prep(const kx::PrepArgs* a, int is_i8, int grid, hipStream_t st);
 hipError_t kx_launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 hipError_t kx_launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v,

@@ -5,7 +5,9 @@
 //   become kMissingCode, (b) per-SNP constants (group sizes N_i, df, the
 //   integer coefficients of the MFMA columns and the weights of the
 //   statistic numerator), (c) a per-32-SNP-tile flag "has a missing
-//   genotype".  Counting N_i is the paper's N_i = sum_k I_i(m,k) (eq. (1)).
+//   genotype", (d) the positions of the missing samples of each SNP that has
+//   at most kLaneMiss of them.  Counting N_i is the paper's
+//   N_i = sum_k I_i(m,k) (eq. (1)).
 //
 // prep_ranks: doubled midranks -> the MFMA A operand in fragment order,
 //   centred c = a - (K+1) (an integer in [-(K-1), K-1], exact in fp16 for
@@ -72,7 +74,8 @@ __global__ __launch_bounds__(256) void pack_snps(const int8_t* __restrict__ geno
                                                  int64_t ld, int K, int64_t m_pad, int gstride,
                                                  int diag_ok, int8_t* __restrict__ gp,
                                                  SnpInfo* __restrict__ info,
-                                                 int32_t* __restrict__ tile_flags) {
+                                                 int32_t* __restrict__ tile_flags,
+                                                 int16_t* __restrict__ mpos) {
     __shared__ uint32_t s_rows[kPackRows * kPackLds / 4];
     uint8_t* s_bytes = (uint8_t*)s_rows;
     const int tid = threadIdx.x;
@@ -114,11 +117,26 @@ __global__ __launch_bounds__(256) void pack_snps(const int8_t* __restrict__ geno
         const int valid = K - col0 < w ? (K - col0 > 0 ? K - col0 : 0) : w;
         const uint32_t* row = s_rows + tid * (kPackLds / 4);
         const int full = valid >> 2;
-        for (int q = 0; q < full; ++q) count_codes(row[q], c0, c1, c2, c3);
+        // counts of the word's codes, and the positions of its missing ones
+        // while the row has at most kLaneMiss of them
+        auto word = [&](uint32_t w, int col) {
+            uint32_t mb = w & (w >> 1) & 0x01010101u;
+            if (mpos && m_me < M) {
+                int j = c3;
+                while (mb) {
+                    if (j < kLaneMiss)
+                        mpos[m_me * kLaneMiss + j] = (int16_t)(col + (__builtin_ctz(mb) >> 3));
+                    mb &= mb - 1u;
+                    ++j;
+                }
+            }
+            count_codes(w, c0, c1, c2, c3);
+        };
+        for (int q = 0; q < full; ++q) word(row[q], col0 + 4 * q);
         if (valid & 3) {
             const uint32_t keep = (1u << (8 * (valid & 3))) - 1u;
             // masked-off bytes read as code 0: subtract them afterwards
-            count_codes(row[full] & keep, c0, c1, c2, c3);
+            word(row[full] & keep, col0 + 4 * full);
             c0 -= 4 - (valid & 3);
         }
         __syncthreads();
@@ -328,14 +346,14 @@ extern "C" {
 
 hipError_t kx_launch_pack(const int8_t* geno, int64_t M, int64_t ld, int K, int64_t m_pad,
                           int gstride, int diag_ok, int8_t* gp, kx::SnpInfo* info,
-                          int32_t* tile_flags, int grid, hipStream_t st) {
+                          int32_t* tile_flags, int16_t* mpos, int grid, hipStream_t st) {
     int64_t n_tiles = m_pad / 32;
     hipLaunchKernelGGL(kx::fill_i32, dim3(64), dim3(256), 0, st, tile_flags, n_tiles + 1, 0);
     (void)grid;
     const int64_t blocks = (m_pad + kx::kPackRows - 1) / kx::kPackRows;
     if (blocks > 0)
         hipLaunchKernelGGL(kx::pack_snps, dim3((unsigned)blocks), dim3(256), 0, st, geno, M, ld,
-                           K, m_pad, gstride, diag_ok, gp, info, tile_flags);
+                           K, m_pad, gstride, diag_ok, gp, info, tile_flags, mpos);
     return hipGetLastError();
 }
 

@@ -11,15 +11,96 @@ namespace kx {
 // missing sample q, s_i(q) = #{kept k in group i above q} - #{kept k in group i
 // below q}.  At most L_q = (a_q - 2) / 2 samples lie below q and at most
 // G_q = K - a_q / 2 above it (a_q: doubled midrank, its tie group holds q), so
-// s_i(q) lies in [-min(N_i, L_q), min(N_i, G_q)].  The kept samples'
+// s_i(q) lies in [-min(N_i, L_q), min(N_i, G_q)].  Counting q's tie partners
+// (t_q - 1 of them) too, 2 #below + (t_q - 1) = a_q - 2 and
+// 2 #above + (t_q - 1) = 2K - a_q exactly; with #above_i + #below_i <= N_i and
+// the tied members of group i at most t_q - 1, s_i(q) <= 2K - a_q - N_i and
+// s_i(q) >= N_i - (a_q - 2), which is tighter for a q near either end of
+// the ranks (a q at the top has nearly all of group i below it).  The kept samples'
 // re-centred ranks sum to zero, so the shifts also satisfy
 // sum_i sum_q s_i(q) = -(sum of the missing samples' centred ranks).  The
 // largest f over these intervals and that plane (at a vertex of the polygon
 // they cut, f being convex), with E' >= K'^3 - K' - sumT, bounds H'.
-// Returns false when the
-// bound stays below the pass's screen level (never for a level of 0), or when
-// the pair can only matter for its row's minimum p and cannot lower it.  All
-// lanes of the wave take part; the result is uniform.
+// missing_bound returns false when the bound stays below the pass's screen
+// level (never for a level of 0), or when the pair can only matter for its
+// row's minimum p and cannot lower it.  nq, sq, lo and hi are the pair's
+// count of missing samples, the sum of their centred ranks and the summed
+// per-sample shift intervals of the three groups.
+__device__ inline bool missing_bound(const ScanArgs& a, int64_t v, int64_t trait,
+                                     const SnpInfo& inf, int nq, int sq, const int (&lo)[3],
+                                     const int (&hi)[3], int d1, int d2) {
+    const int K = a.K;
+    const int n[3] = {inf.n0, inf.n1, inf.n2};
+    const int df = snp_df(inf);
+    if (df <= 0) return false;                  // never recorded
+    const int64_t kp = K - nq;
+    const int64_t E = cube_minus(kp) - a.tiesum[trait];
+    if (kp < 2 || E <= 0) return true;          // no bound: evaluate
+    const int64_t D[3] = {-(int64_t)d1 - d2 - sq, d1, d2};
+    // D'_i = D_i - s_i with s_i in [lo_i, hi_i], and the kept samples'
+    // re-centred ranks sum to zero: sum_i s_i = sum_i D_i = -sq.  f is convex,
+    // so its largest value over the box cut by that plane is at a vertex (two
+    // shifts at an end of their interval, the third from the sum and within
+    // its own); the box alone (each |D'_i| at its largest) is the fallback
+    double f = -1.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int o1 = j == 0 ? 1 : 0, o2 = j == 2 ? 1 : 2;
+#pragma unroll
+        for (int sg = 0; sg < 4; ++sg) {
+            const int64_t s1 = (sg & 1) ? hi[o1] : lo[o1];
+            const int64_t s2 = (sg & 2) ? hi[o2] : lo[o2];
+            const int64_t sj = -(int64_t)sq - s1 - s2;
+            if (sj < lo[j] || sj > hi[j]) continue;
+            const int64_t x[3] = {j == 0 ? D[0] - sj : o1 == 0 ? D[0] - s1 : D[0] - s2,
+                                  j == 1 ? D[1] - sj : o1 == 1 ? D[1] - s1 : D[1] - s2,
+                                  j == 2 ? D[2] - sj : o1 == 2 ? D[2] - s1 : D[2] - s2};
+            double fv = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                if (n[i]) fv += (double)(x[i] * x[i]) / (double)n[i];
+            f = fv > f ? fv : f;
+        }
+    }
+    if (f < 0.0) {
+        f = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            if (n[i] == 0) continue;
+            const int64_t x0 = D[i] - hi[i], x1 = D[i] - lo[i];
+            const int64_t x = max(x0 < 0 ? -x0 : x0, x1 < 0 ? -x1 : x1);
+            f += (double)(x * x) / (double)n[i];
+        }
+    }
+    const double Hup = 3.0 * (double)(kp - 1) * f / (double)E * (1.0 + 1e-9);
+    if (Hup < a.hc_screen[df]) return false;
+    // Below every count level and the hit level the pair matters only for
+    // its row's minimum p: skip it when even its bound cannot lower the
+    // minimum found so far (read without synchronisation: a stale, larger
+    // value only skips less)
+    bool counted = false;
+    for (int l = 0; l < a.n_lev; ++l) counted = counted || !(Hup < a.hc[l][df - 1]);
+    if (counted || !a.minp_bits) return true;
+    const double cur = __longlong_as_double((long long)a.minp_bits[v]);
+    return pvalue(Hup, df) < cur;
+}
+
+// One missing sample of doubled midrank aq: its centred rank joins sq and
+// its shift intervals join lo and hi.
+__device__ inline void add_missing_sample(int K, const int (&n)[3], int aq, int& sq,
+                                          int (&lo)[3], int (&hi)[3]) {
+    const int below = (aq - 2) >> 1, above = K - ((aq + 1) >> 1);
+    sq += aq - (K + 1);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        lo[i] -= min(min(n[i], below), aq - 2 - n[i]);
+        hi[i] += min(min(n[i], above), 2 * K - aq - n[i]);
+    }
+}
+
+// The bound of pair (v, m) by the whole wave, for a SNP with any number of
+// missing samples (found in its packed row).  All lanes take part; the
+// result is uniform.
 __device__ inline bool missing_pair_may_pass(const ScanArgs& a, int64_t v, int64_t m, int d1,
                                              int d2, int lane) {
     const int K = a.K;
@@ -31,14 +112,8 @@ __device__ inline bool missing_pair_may_pass(const ScanArgs& a, int64_t v, int64
     const int n[3] = {inf.n0, inf.n1, inf.n2};
     int nq = 0, sq = 0, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     auto add_missing = [&](int aq) {
-        const int below = (aq - 2) >> 1, above = K - ((aq + 1) >> 1);
         ++nq;
-        sq += aq - (K + 1);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            lo[i] -= min(n[i], below);
-            hi[i] += min(n[i], above);
-        }
+        add_missing_sample(K, n, aq, sq, lo, hi);
     };
     // each lane scans 16 consecutive codes per 16-byte load (the packed row
     // stride is a multiple of 32 bytes, so the load stays inside the row);
@@ -95,58 +170,7 @@ __device__ inline bool missing_pair_may_pass(const ScanArgs& a, int64_t v, int64
         lo[i] = wave_sum(lo[i]);
         hi[i] = wave_sum(hi[i]);
     }
-    const int df = snp_df(inf);
-    if (df <= 0) return false;                  // never recorded
-    const int64_t kp = K - nq;
-    const int64_t E = cube_minus(kp) - a.tiesum[trait];
-    if (kp < 2 || E <= 0) return true;          // no bound: evaluate
-    const int64_t D[3] = {-(int64_t)d1 - d2 - sq, d1, d2};
-    // D'_i = D_i - s_i with s_i in [lo_i, hi_i], and the kept samples'
-    // re-centred ranks sum to zero: sum_i s_i = sum_i D_i = -sq.  f is convex,
-    // so its largest value over the box cut by that plane is at a vertex (two
-    // shifts at an end of their interval, the third from the sum and within
-    // its own); the box alone (each |D'_i| at its largest) is the fallback
-    double f = -1.0;
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const int o1 = j == 0 ? 1 : 0, o2 = j == 2 ? 1 : 2;
-#pragma unroll
-        for (int sg = 0; sg < 4; ++sg) {
-            const int64_t s1 = (sg & 1) ? hi[o1] : lo[o1];
-            const int64_t s2 = (sg & 2) ? hi[o2] : lo[o2];
-            const int64_t sj = -(int64_t)sq - s1 - s2;
-            if (sj < lo[j] || sj > hi[j]) continue;
-            const int64_t x[3] = {j == 0 ? D[0] - sj : o1 == 0 ? D[0] - s1 : D[0] - s2,
-                                  j == 1 ? D[1] - sj : o1 == 1 ? D[1] - s1 : D[1] - s2,
-                                  j == 2 ? D[2] - sj : o1 == 2 ? D[2] - s1 : D[2] - s2};
-            double fv = 0.0;
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-                if (n[i]) fv += (double)(x[i] * x[i]) / (double)n[i];
-            f = fv > f ? fv : f;
-        }
-    }
-    if (f < 0.0) {
-        f = 0.0;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            if (n[i] == 0) continue;
-            const int64_t x0 = D[i] - hi[i], x1 = D[i] - lo[i];
-            const int64_t x = max(x0 < 0 ? -x0 : x0, x1 < 0 ? -x1 : x1);
-            f += (double)(x * x) / (double)n[i];
-        }
-    }
-    const double Hup = 3.0 * (double)(kp - 1) * f / (double)E * (1.0 + 1e-9);
-    if (Hup < a.hc_screen[df]) return false;
-    // Below every count level and the hit level the pair matters only for
-    // its row's minimum p: skip it when even its bound cannot lower the
-    // minimum found so far (read without synchronisation: a stale, larger
-    // value only skips less)
-    bool counted = false;
-    for (int l = 0; l < a.n_lev; ++l) counted = counted || !(Hup < a.hc[l][df - 1]);
-    if (counted || !a.minp_bits) return true;
-    const double cur = __longlong_as_double((long long)a.minp_bits[v]);
-    return pvalue(Hup, df) < cur;
+    return missing_bound(a, v, trait, inf, nq, sq, lo, hi, d1, d2);
 }
 
 // Exact evaluation of the candidates of complete SNPs, one lane each: exact
@@ -163,15 +187,48 @@ __global__ __launch_bounds__(256) void scan_exact(ScanArgs a) {
     }
 }
 
-// Pairs of SNPs with missing genotypes, one wave each: a rank-aware bound
-// (missing_pair_may_pass) drops most of them; for the rest the ranks are
-// re-derived over the kept samples (coop_exact), then as above.  The next
-// entry of the wave's stride is loaded one iteration ahead.  The pass is
-// bound by the latency of each pair's dependent gathers, so it runs at six
-// waves per SIMD (80 registers; the spills stay outside the sample loops;
-// measured on the cohort workload: 3 waves 19.5 ms, 4 16.3, 5 15.3, 6 14.9),
-// as a kernel of its own so that the complete-SNP path does not set its
-// register budget.
+// The same bound for one lane's pair, from the SNP's listed missing samples
+// (at most kLaneMiss of them): their ranks are gathered eight at a time.
+__device__ inline bool lane_pair_may_pass(const ScanArgs& a, int64_t v, int64_t m,
+                                          const SnpInfo& inf, int d1, int d2) {
+    const int K = a.K;
+    const int64_t trait = v % a.T, perm = v / a.T;
+    const int16_t* rk = a.ranks2 + trait * K;
+    const int32_t* pm = a.perms ? a.perms + perm * K : nullptr;
+    const int16_t* mp = a.mpos + m * kLaneMiss;
+    const int n[3] = {inf.n0, inf.n1, inf.n2};
+    const int nq = inf.nmiss;
+    int sq = 0, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int j0 = 0; j0 < nq; j0 += 8) {
+        // 8 positions per 16-byte load (a SNP's list is 64 bytes, 16-byte
+        // aligned); slots past nq load sample 0 and are not counted
+        const uint4 w = *(const uint4*)(mp + j0);
+        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+        int aq[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            int k = j0 + u < nq ? (int)((ws[u >> 1] >> (16 * (u & 1))) & 0xFFFFu) : 0;
+            if (pm) k = pm[k];
+            aq[u] = rk[k];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (j0 + u < nq) add_missing_sample(K, n, aq[u], sq, lo, hi);
+    }
+    return missing_bound(a, v, trait, inf, nq, sq, lo, hi, d1, d2);
+}
+
+// Pairs of SNPs with missing genotypes that passed the scan's bound.  A wave
+// takes up to 64 queued pairs at a time, one lane each: the lane bounds its
+// pair from the listed missing samples (missing_bound, a few gathers); then
+// the whole wave re-derives the ranks over the kept samples (coop_exact) of
+// each pair that the bound keeps, one after the other, and of a SNP with
+// more missing samples than the list holds it first takes the bound as a
+// wave (missing_pair_may_pass).  When there are fewer queued pairs than
+// lanes in the grid, each wave takes fewer of them so that every wave gets
+// some.  The pass is bound by the latency of the re-ranks' dependent loads,
+// so it runs at six waves per SIMD, as a kernel of its own so that the
+// complete-SNP path does not set its register budget.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6)))
 void scan_exact_missing(ScanArgs a) {
     extern __shared__ __attribute__((aligned(16))) int16_t s_buf[];   // per wave coop_lds_entries(K)
@@ -181,19 +238,37 @@ void scan_exact_missing(ScanArgs a) {
     int64_t nm = (int64_t)*a.n_mcand;
     if (nm > a.mcand_cap) nm = a.mcand_cap;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    int64_t e = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
-    int4 q = e < nm ? a.mcand[e] : make_int4(0, 0, 0, 0);
-    for (; e < nm; e += waves) {
-        const int4 qn = e + waves < nm ? a.mcand[e + waves] : make_int4(0, 0, 0, 0);
-        const int64_t v = a.row_v[q.x];
-        if (v >= 0 &&                    // padding row (uniform per wave)
-            missing_pair_may_pass(a, v, q.y, q.z, q.w, lane)) {
-            int df;
-            int64_t s[3];
-            const double H = coop_exact<4>(a, v, q.y, sb, lane, &df, s);
-            if (lane == 0) record(a, v, q.y, H, df);
+    const int64_t w_id = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    // pairs per wave and round: 1..64
+    const int per = (int)min((int64_t)kWave, max((int64_t)1, (nm + waves - 1) / waves));
+    for (int64_t base = w_id * per; base < nm; base += waves * per) {
+        const int64_t e = base + lane;
+        bool have = lane < per && e < nm;
+        const int4 q = have ? a.mcand[e] : make_int4(0, 0, 0, 0);
+        const int64_t v = have ? (int64_t)a.row_v[q.x] : -1;
+        have = have && v >= 0;            // padding rows can pass the scan's bound
+        bool listed = false, pass = false;
+        if (have) {
+            const SnpInfo inf = a.info[q.y];
+            listed = inf.nmiss <= kLaneMiss;
+            if (listed) pass = lane_pair_may_pass(a, v, q.y, inf, q.z, q.w);
         }
-        q = qn;
+        unsigned long long todo = __ballot(have && (pass || !listed));
+        while (todo) {
+            const int j = __builtin_ctzll(todo);
+            todo &= todo - 1ull;
+            // j is uniform: the pair's fields are read from its lane
+            const int64_t vj = __builtin_amdgcn_readlane((int)v, j);
+            const int mj = __builtin_amdgcn_readlane(q.y, j);
+            const bool lj = __builtin_amdgcn_readlane((int)listed, j) != 0;
+            if (!lj && !missing_pair_may_pass(a, vj, mj, __builtin_amdgcn_readlane(q.z, j),
+                                              __builtin_amdgcn_readlane(q.w, j), lane))
+                continue;
+            int df;
+            int64_t sums[3];
+            const double H = coop_exact<4>(a, vj, mj, sb, lane, &df, sums);
+            if (lane == 0) record(a, vj, mj, H, df);
+        }
     }
 }
 
