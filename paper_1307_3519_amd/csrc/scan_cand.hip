@@ -218,11 +218,113 @@ __device__ inline bool lane_pair_may_pass(const ScanArgs& a, int64_t v, int64_t 
     return missing_bound(a, v, trait, inf, nq, sq, lo, hi, d1, d2);
 }
 
+// Exact evaluation of pair (v, m) by the whole wave when the SNP's missing
+// samples are listed (1..kLaneMiss of them, K from 32 to 2047) and the trait
+// has every expression value: the re-ranked sums of coop_exact without its
+// staging pass.  The missing samples' ranks (one lane each) go into a bitmap
+// over the doubled ranks 0..2K with per-word prefix counts; every sample's
+// rank and code are then read from global memory, U per lane in flight
+// together, and for sample k the bitmap gives the number of missing ranks
+// below a_k (lt) and whether one equals it (eq): its re-ranked doubled rank
+// is a_k - 2 lt - eq.  Only groups 1 and 2 are summed: the kept samples'
+// re-ranked doubled ranks sum to K'(K' + 1).  A tie group of size t that
+// loses its one missing member takes 3 t (t - 1) off the tie term (t counted
+// per missing rank, the missing sample included).  Returns false, having
+// evaluated nothing, when two missing samples share a rank (coop_exact
+// handles that case).
+template <int U>
+__device__ inline bool coop_exact_listed(const ScanArgs& a, int64_t v, int64_t m,
+                                         int16_t* sbuf, int lane, double* H_out, int* df_out) {
+    const int K = a.K;
+    const int64_t trait = v % a.T, perm = v / a.T;
+    const int16_t* rk = a.ranks2 + trait * K;
+    const int32_t* pm = a.perms ? a.perms + perm * K : nullptr;
+    const int8_t* gr = a.G + m * (int64_t)a.gstride;
+    const SnpInfo inf = a.info[m];
+    const int nq = inf.nmiss;
+    int qa = 0;
+    if (lane < nq) {
+        int k = a.mpos[m * kLaneMiss + lane];
+        if (pm) k = pm[k];
+        qa = rk[k];
+    }
+    uint4* bm = (uint4*)(sbuf + coop_bitmap_offset(K));
+    int32_t* tc = (int32_t*)(sbuf + 2 * K + 64);
+    const int W = ((2 * K) >> 6) + 1;            // 64-bit words covering 0..2K
+    __builtin_amdgcn_wave_barrier();
+    if (lane < W) bm[lane] = make_uint4(0u, 0u, 0u, 0u);
+    tc[lane] = 0;
+    __builtin_amdgcn_wave_barrier();
+    bool dup = false;
+    if (lane < nq) {
+        const uint32_t bit = 1u << (qa & 31);
+        const uint32_t old = atomicOr((uint32_t*)&bm[qa >> 6] + ((qa >> 5) & 1), bit);
+        dup = (old & bit) != 0u;
+    }
+    if (__any(dup)) return false;
+    __builtin_amdgcn_wave_barrier();
+    {
+        const uint4 e = lane < W ? bm[lane] : make_uint4(0u, 0u, 0u, 0u);
+        const int c = __popc(e.x) + __popc(e.y);
+        const int incl = wave_incl_scan(c, lane);
+        if (lane < W) bm[lane].z = (uint32_t)(incl - c);
+    }
+    __builtin_amdgcn_wave_barrier();
+    const long long ts0 = a.tiesum[trait];
+    long long s1 = 0, s2 = 0;
+    for (int k0 = 0; k0 < K; k0 += U * kWave) {
+        // loads at clamped indices, all in flight together; samples past K
+        // are masked afterwards
+        int code[U], ak[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = min(k0 + u * kWave + lane, K - 1);
+            code[u] = (int)gr[k];
+            ak[u] = (int)rk[pm ? pm[k] : k];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool valid = k0 + u * kWave + lane < K;
+            const uint4 e = bm[ak[u] >> 6];
+            const int b = ak[u] & 63;
+            const unsigned long long bits = (unsigned long long)e.x |
+                                            ((unsigned long long)e.y << 32);
+            const int lt = (int)e.z + __popcll(bits & ((1ull << b) - 1ull));
+            const int eq = (int)((bits >> b) & 1ull);
+            const int ap = ak[u] - 2 * lt - eq;
+            s1 += (valid && code[u] == 1) ? ap : 0;
+            s2 += (valid && code[u] == 2) ? ap : 0;
+            if (ts0 != 0 && valid && eq) atomicAdd(&tc[lt], 1);
+        }
+    }
+    s1 = wave_sum64(s1);
+    s2 = wave_sum64(s2);
+    long long ts = ts0;
+    if (ts0 != 0) {
+        __builtin_amdgcn_wave_barrier();
+        long long corr = 0;
+        if (lane < nq) {
+            const long long t = tc[lane];
+            corr = 3 * t * (t - 1);
+        }
+        ts -= wave_sum64(corr);
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int64_t kp = K - nq;
+    const int64_t s0 = kp * (kp + 1) - s1 - s2;
+    const int df = snp_df(inf);
+    *df_out = df;
+    *H_out = exact_H(s0 - (int64_t)inf.n0 * (kp + 1), s1 - (int64_t)inf.n1 * (kp + 1),
+                     s2 - (int64_t)inf.n2 * (kp + 1), inf.n0, inf.n1, inf.n2, kp, ts, df);
+    return true;
+}
+
 // Pairs of SNPs with missing genotypes that passed the scan's bound.  A wave
 // takes up to 64 queued pairs at a time, one lane each: the lane bounds its
 // pair from the listed missing samples (missing_bound, a few gathers); then
-// the whole wave re-derives the ranks over the kept samples (coop_exact) of
-// each pair that the bound keeps, one after the other, and of a SNP with
+// the whole wave re-derives the ranks over the kept samples
+// (coop_exact_listed, else coop_exact) of each pair that the bound keeps,
+// one after the other, and of a SNP with
 // more missing samples than the list holds it first takes the bound as a
 // wave (missing_pair_may_pass).  When there are fewer queued pairs than
 // lanes in the grid, each wave takes fewer of them so that every wave gets
@@ -265,8 +367,15 @@ void scan_exact_missing(ScanArgs a) {
                                               __builtin_amdgcn_readlane(q.w, j), lane))
                 continue;
             int df;
-            int64_t sums[3];
-            const double H = coop_exact<4>(a, vj, mj, sb, lane, &df, sums);
+            double H;
+            bool done = false;
+            if (lj && a.K >= 32 && a.K <= 2047)
+                done = a.K > 256 ? coop_exact_listed<8>(a, vj, mj, sb, lane, &H, &df)
+                                 : coop_exact_listed<4>(a, vj, mj, sb, lane, &H, &df);
+            if (!done) {
+                int64_t sums[3];
+                H = coop_exact<4>(a, vj, mj, sb, lane, &df, sums);
+            }
             if (lane == 0) record(a, vj, mj, H, df);
         }
     }
