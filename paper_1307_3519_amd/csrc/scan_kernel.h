@@ -669,6 +669,9 @@ void scan_kernel(ScanArgs a) {
         const float qn0 = (float)inf.nmiss * inf.n0, qn1 = (float)inf.nmiss * inf.n1,
                     qn2 = (float)inf.nmiss * inf.n2;
         const float delta = (float)(cube_minus(a.K) - cube_minus(kp));
+        // MISS3: w_i (|D_i| + nmiss N_i)^2 as (|D_i| r_i + q_i)^2, r_i = sqrt(w_i)
+        const float r0 = sqrtf(w0), r1 = sqrtf(w1), r2 = sqrtf(w2);
+        const float q0 = qn0 * r0, q1 = qn1 * r1, q2 = qn2 * r2;
         // ZS: candidate iff Y^2 + Z^2 > theta * invc (inf when wy * fac = 0);
         // ZF: Y^2 + (zq Z)^2 with zq = sqrt(wz / wy) rounded up
         const float invc = (ZS || ZF) ? 1.0f / (inf.wy * fac) : 0.0f;
@@ -702,15 +705,15 @@ void scan_kernel(ScanArgs a) {
                 float d0 = -(d1 + d2);
                 return fmaf(w0 * d0, d0, fmaf(w1 * d1, d1, fmaf(w2 * d2, d2, -th)));
             } else {
-                float d0 = T_::val(acc[0], r), d1 = T_::val(acc[1], r),
-                      d2 = T_::val(acc[2], r);
-                if (lane_miss) {
-                    // |D'_i - D_i| <= nmiss * N_i and E' >= K'^3 - K' - sumT
-                    d0 = fabsf(d0) + qn0; d1 = fabsf(d1) + qn1; d2 = fabsf(d2) + qn2;
-                    float tl = delta - th * 0.99999905f;
-                    return fmaf(w0 * d0, d0, fmaf(w1 * d1, d1, fmaf(w2 * d2, d2, tl)));
-                }
-                return fmaf(w0 * d0, d0, fmaf(w1 * d1, d1, fmaf(w2 * d2, d2, -th)));
+                // |D'_i - D_i| <= nmiss * N_i and E' >= K'^3 - K' - sumT
+                // (complete SNPs: q_i = 0, delta = 0 and a threshold lowered
+                // by 1e-6, which only admits more candidates; the weights'
+                // 1e-5 slack covers the rounding of r_i and q_i)
+                const float e0 = fmaf(fabsf(T_::val(acc[0], r)), r0, q0);
+                const float e1 = fmaf(fabsf(T_::val(acc[1], r)), r1, q1);
+                const float e2 = fmaf(fabsf(T_::val(acc[2], r)), r2, q2);
+                const float tl = delta - th * 0.99999905f;
+                return fmaf(e0, e0, fmaf(e1, e1, fmaf(e2, e2, tl)));
             }
         };
         // the rare path: stage the pairs that pass the screen

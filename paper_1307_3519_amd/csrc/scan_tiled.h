@@ -19,9 +19,13 @@
 namespace kx {
 
 
-// Per-lane screen constants of one SNP column.
+// Per-lane screen constants of one SNP column.  The missing-genotype form
+// takes the square roots r_i of its weights and q_i = nmiss N_i r_i, so that
+// w_i (|D_i| + nmiss N_i)^2 = (|D_i| r_i + q_i)^2: one fma and one square per
+// column, the same for complete SNPs (q_i = 0, delta = 0).
 struct LaneK {
     float wy, wz, w0, w1, w2, qn0, qn1, qn2, delta;
+    float r0, r1, r2, q0, q1, q2;
     bool miss;
 };
 
@@ -35,6 +39,8 @@ __device__ inline LaneK lane_constants(const SnpInfo& inf, int K, const float* i
     c.qn0 = (float)inf.nmiss * inf.n0; c.qn1 = (float)inf.nmiss * inf.n1;
     c.qn2 = (float)inf.nmiss * inf.n2;
     c.delta = (float)(cube_minus(K) - cube_minus(kp));
+    c.r0 = sqrtf(c.w0); c.r1 = sqrtf(c.w1); c.r2 = sqrtf(c.w2);
+    c.q0 = c.qn0 * c.r0; c.q1 = c.qn1 * c.r1; c.q2 = c.qn2 * c.r2;
     return c;
 }
 
@@ -47,13 +53,15 @@ __device__ inline float screen_value(const LaneK& c, float th, float v0, float v
         const float d0 = -(v0 + v1);
         return fmaf(c.w0 * d0, d0, fmaf(c.w1 * v0, v0, fmaf(c.w2 * v1, v1, -th)));
     } else {
-        float d0 = v0, d1 = v1, d2 = v2;
-        if (c.miss) {
-            d0 = fabsf(d0) + c.qn0; d1 = fabsf(d1) + c.qn1; d2 = fabsf(d2) + c.qn2;
-            const float tl = c.delta - th * 0.99999905f;
-            return fmaf(c.w0 * d0, d0, fmaf(c.w1 * d1, d1, fmaf(c.w2 * d2, d2, tl)));
-        }
-        return fmaf(c.w0 * d0, d0, fmaf(c.w1 * d1, d1, fmaf(c.w2 * d2, d2, -th)));
+        // |D'_i - D_i| <= nmiss N_i and E' >= K'^3 - K' - sumT (complete SNPs:
+        // the plain screen, with a threshold lowered by 1e-6, which only
+        // admits more candidates); the weights' 1e-5 slack covers the
+        // rounding of r_i and q_i
+        const float e0 = fmaf(fabsf(v0), c.r0, c.q0);
+        const float e1 = fmaf(fabsf(v1), c.r1, c.q1);
+        const float e2 = fmaf(fabsf(v2), c.r2, c.q2);
+        const float tl = c.delta - th * 0.99999905f;
+        return fmaf(e0, e0, fmaf(e1, e1, fmaf(e2, e2, tl)));
     }
 }
 
@@ -439,12 +447,23 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
                 using CL = std::integral_constant<int, NC - 1>;
                 if constexpr (MODE == SCREEN) {
                     const float th = cload(a.theta + tt);
+                    // the missing-genotype form in eight-wave blocks: the rows
+                    // with a passing pair as a mask in the same pass (most of
+                    // its tiles have one); the others: the largest value
+                    uint32_t pm = 0;
                     float gmax = -__builtin_inff();
                     static_for<16>([&](auto rc) {
-                        gmax = fmaxf(gmax, screen_value<FORM>(lk, th, colv(C0{}, rc), colv(C1{}, rc),
-                                                              NC == 3 ? colv(CL{}, rc) : 0.0f));
+                        constexpr int r = decltype(rc)::value;
+                        const float sv = screen_value<FORM>(lk, th, colv(C0{}, rc), colv(C1{}, rc),
+                                                            NC == 3 ? colv(CL{}, rc) : 0.0f);
+                        if constexpr (QUEUE && V == 3) pm |= sv > 0.0f ? (1u << r) : 0u;
+                        else gmax = fmaxf(gmax, sv);
                     });
-                    if (!__any(gmax > 0.0f)) return;
+                    if constexpr (QUEUE && V == 3) {
+                        if (!__any(pm != 0u)) return;
+                    } else {
+                        if (!__any(gmax > 0.0f)) return;
+                    }
                     if constexpr (QUEUE && V == 3) {
                         // The rows with a passing pair (per lane, then over the
                         // wave), then one loop over those rows: the queue and
@@ -454,15 +473,8 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
                         // four-wave tiles the extra mask work outweighs it
                         // (K = 233: 9.1 -> 10.3 ms), so they keep the unrolled
                         // rows.
-                        uint32_t qm = 0, cm = 0;
-                        static_for<16>([&](auto rc) {
-                            constexpr int r = decltype(rc)::value;
-                            const bool pass = screen_value<FORM>(lk, th, colv(C0{}, rc), colv(C1{}, rc),
-                                                                 colv(CL{}, rc)) > 0.0f;
-                            qm |= (pass && lk.miss) ? (1u << r) : 0u;
-                            cm |= (pass && !lk.miss) ? (1u << r) : 0u;
-                        });
-                        uint32_t rows = qm | cm;
+                        const uint32_t qm = lk.miss ? pm : 0u, cm = lk.miss ? 0u : pm;
+                        uint32_t rows = pm;
 #pragma unroll
                         for (int o = 32; o > 0; o >>= 1) rows |= (uint32_t)__shfl_xor((int)rows, o, 64);
                         rows = __builtin_amdgcn_readfirstlane(rows);
