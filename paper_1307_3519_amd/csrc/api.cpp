@@ -407,21 +407,25 @@ int tile_shape_for(krux_ctx* c, int K, int precision) {
 
 // Expanded B columns of the tiled kernel; with the codes shapes (2, 3) the
 // complete-SNP screen reads the packed genotype rows, and only the
-// missing-genotype columns are built.
+// missing-genotype columns are built (none for fp16 in shape 3, whose
+// missing-genotype form reads the codes too).
 krux_status expand_columns(krux_ctx* c, const Variant& v, const SnpSide& sn, int shape,
                            hipStream_t st, Columns* out) {
     if (!v.tiled) return KRUX_OK;
     krux_status s = KRUX_OK;
     const int64_t n_pad = ceil_div(std::max<int64_t>(sn.n_snp_tiles, 1), 4) * 4;
     const size_t per_col = (size_t)n_pad * v.ks * kx::kWave * 16;
+    // fp16 in eight-wave blocks: the missing-genotype form reads the codes too
+    const bool miss_codes = shape == 3 && v.elem == kx::F16;
     if (shape < 2) out->Bf = ws(c, S_BF, per_col * 2, &s);
-    out->Bf3 = ws(c, S_BF3, per_col * 3, &s);
+    if (!miss_codes) out->Bf3 = ws(c, S_BF3, per_col * 3, &s);
     if (s != KRUX_OK) return s;
     int grid = (int)std::min<int64_t>(ceil_div(n_pad * v.ks * 3 * kx::kWave, 256), (int64_t)c->n_cu * 16);
     if (v.elem == kx::F16) {
         if (shape < 2)
             HIP_TRY(c, kx_launch_expand_f16(sn.G, sn.gstride, sn.info, n_pad, v.ks, v.form, out->Bf, grid, st));
-        HIP_TRY(c, kx_launch_expand_f16(sn.G, sn.gstride, sn.info, n_pad, v.ks, kx::MISS3, out->Bf3, grid, st));
+        if (!miss_codes)
+            HIP_TRY(c, kx_launch_expand_f16(sn.G, sn.gstride, sn.info, n_pad, v.ks, kx::MISS3, out->Bf3, grid, st));
     } else {
         if (shape < 2)
             HIP_TRY(c, kx_launch_expand_i8(sn.G, sn.gstride, sn.info, n_pad, v.ks, v.form, out->Bf, grid, st));
@@ -444,8 +448,9 @@ krux_status launch_scan(krux_ctx* c, const kx::ScanArgs& a, const Variant& v, co
     ta.A_hi = A_hi;
     ta.ks = v.ks;
     ta.shape = a.tile_shape;
-    // the missing-genotype form has no codes shape: shape 2 runs it in the
-    // four-wave tiles of shape 1, shape 3 in eight-wave blocks
+    // the missing-genotype form: shape 2 runs it in the four-wave tiles of
+    // shape 1 (expanded columns), shape 3 in eight-wave blocks (from the codes
+    // in fp16)
     if (form == kx::MISS3 && ta.shape == 2) ta.shape = 1;
     if (v.elem == kx::F16) HIP_TRY(c, kx_launch_tiled_f16(&a, &ta, form, mode, grid, st));
     else HIP_TRY(c, kx_launch_tiled_i8(&a, &ta, form, mode, grid, st));

@@ -77,26 +77,30 @@ __device__ inline float screen_value(const LaneK& c, float th, float v0, float v
 //        permutes), so that a chunk is 18 KB instead of 24 KB, the LDS ring
 //        holds four chunks instead of three, and no expanded columns are
 //        built;
-//  V = 3 ("one block per CU"): eight waves per block (two per SIMD) as 2
-//        trait groups x 4 SNP tiles, the B side from the codes in the PLAIN
-//        form (a chunk of 16 KB of A and 4 KB of codes feeds 128 MFMAs
-//        instead of 64, and one 140 KB ring holds seven chunks) and expanded
-//        in the missing-genotype form (32 KB per 96 MFMAs instead of 20 KB
-//        per 48, four chunks).
+//  V = 3 ("one block per CU"): eight waves per block (two per SIMD), the
+//        B side from the codes in the PLAIN form and in the fp16
+//        missing-genotype form (three indicator columns, classes 0..2, built
+//        in registers; a chunk of 8 KB of A and 4 KB of codes feeds 96 MFMAs
+//        where the expanded columns took 16 KB and 12 KB, and the ring holds
+//        eight chunks instead of four), expanded in the int8 missing-genotype
+//        form.
 template <int FORM, bool SPLIT, int V>
 struct TiledShape {
     static constexpr int NC = FORM == MISS3 ? 3 : 2;
     static constexpr int NP = SPLIT ? 2 : 1;
-    static constexpr bool CODES = V >= 2 && FORM == PLAIN;
+    // fp16 missing-genotype form in eight-wave blocks: codes as well (three
+    // indicator columns, classes 0..2)
+    static constexpr bool CODES = (V >= 2 && FORM == PLAIN) || (V == 3 && FORM == MISS3 && !SPLIT);
     static constexpr int NW = V == 3 ? 8 : 4;            // waves per block
     // SNP groups (waves per trait group): eight-wave blocks take one trait
     // group of eight SNP tiles in the fp16 codes form (codes are the small
     // side; K = 500 3.68 -> 3.62 ms, K = 1000 6.72 -> 6.51 ms against 2 x 4),
     // two of four in the int8 one (its A side has two planes; 1 x 8 4.17 ->
-    // 4.38 ms) and four trait groups of two SNP tiles in the missing-genotype
-    // form (its three expanded columns are the large side; K = 1000 17.9 ->
-    // 17.5 ms)
-    static constexpr int GSW = V == 3 ? (FORM == MISS3 ? 2 : SPLIT ? 4 : 8) : 2;
+    // 4.38 ms), two of four in the fp16 missing-genotype form (two trait
+    // tiles per wave; cohort step 53.5 ms against 52.8 with 1 x 8) and four
+    // trait groups of two SNP tiles in the int8 one (its three expanded
+    // columns are the large side; K = 1000 17.9 -> 17.5 ms)
+    static constexpr int GSW = V == 3 ? (FORM == MISS3 ? (CODES ? 4 : 2) : SPLIT ? 4 : 8) : 2;
     static constexpr int GTW = NW / GSW;                 // trait groups
     static constexpr int WS = V == 0 ? ((NC == 2 && !SPLIT) ? 2 : 1) : 1;
     static constexpr int WT = V == 0 ? ((FORM != MISS3 && NP * 4 * WS * NC * 16 <= 256) ? 4 : 2)
@@ -180,8 +184,8 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
     constexpr int NF = NFA + NFB;
     static_assert(NFA == SH::NFA && NF == SH::NF, "fragment count");
     constexpr bool CODES = SH::CODES;
-    static_assert(!CODES || (WS == 1 && FORM == PLAIN && SPLIT == (E == I8)),
-                  "the codes shapes build the PLAIN indicator columns of one SNP tile per wave");
+    static_assert(!CODES || (WS == 1 && FORM != DIAG && SPLIT == (E == I8)),
+                  "the codes shapes build the indicator columns of one SNP tile per wave");
     // copies per wave per chunk: a contiguous run of NF / NW copies, or
     // (codes shapes and eight-wave blocks) copies wave, wave + NW, ..., which
     // leaves some waves one fewer
@@ -379,7 +383,7 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
                         for (int q = 0; q < 4; ++q) sel[q] = f16_ind_sel(q < 2 ? w.x : w.y, 2 * (q & 1));
 #pragma unroll
                         for (int c = 0; c < NC; ++c) {
-                            const int k = c + 1;
+                            const int k = FORM == MISS3 ? c : c + 1;
                             const uint4 o = make_uint4(f16_ind(sel[0], k), f16_ind(sel[1], k),
                                                        f16_ind(sel[2], k), f16_ind(sel[3], k));
                             fb[0][c] = __builtin_bit_cast(frag, o);
@@ -390,7 +394,7 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
                         const uint4 w = *(const uint4*)(cb + kk * kWave * 16 + lane * 16);
 #pragma unroll
                         for (int c = 0; c < NC; ++c) {
-                            const int k = c + 1;
+                            const int k = FORM == MISS3 ? c : c + 1;
                             const uint4 o = make_uint4(i8_ind(w.x, k), i8_ind(w.y, k),
                                                        i8_ind(w.z, k), i8_ind(w.w, k));
                             fb[0][c] = __builtin_bit_cast(frag, o);
