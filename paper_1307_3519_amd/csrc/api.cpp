@@ -265,7 +265,7 @@ krux_status pack_snps(krux_ctx* c, const int8_t* geno, int64_t M, int64_t ld, in
     int64_t m_pad = std::max<int64_t>(ceil_div(out->n_snp_tiles, 8) * 8, 8) * kx::kTile;
     out->G = (int8_t*)ws(c, S_PACKED, (size_t)m_pad * out->gstride, &s);
     out->info = (kx::SnpInfo*)ws(c, S_INFO, (size_t)m_pad * sizeof(kx::SnpInfo), &s);
-    out->flags = (int32_t*)ws(c, S_FLAGS, (size_t)(m_pad / kx::kTile + 1) * 4, &s);
+    out->flags = (int32_t*)ws(c, S_FLAGS, (size_t)(m_pad / kx::kTile + 2) * 4, &s);
     out->mpos = (int16_t*)ws(c, S_MPOS, (size_t)m_pad * kx::kLaneMiss * sizeof(int16_t), &s);
     if (s != KRUX_OK) return s;
     // one wave per SNP row, enough blocks to cover every row at once (the

@@ -46,7 +46,8 @@ struct ScanArgs {
     const int8_t* G;          // packed genotypes [m_pad][gstride]
     int gstride;
     const SnpInfo* info;      // [m_pad]
-    const int32_t* tile_flags;// [n_snp_tiles] 1 = has a missing genotype
+    const int32_t* tile_flags;// [n_snp_tiles] 1 = has a missing genotype, then "some tile has
+                              // one" and "some tile has none"
     int64_t M;
     int64_t n_snp_tiles;
     int K;

@@ -5,7 +5,7 @@
 //   become kMissingCode, (b) per-SNP constants (group sizes N_i, df, the
 //   integer coefficients of the MFMA columns and the weights of the
 //   statistic numerator), (c) a per-32-SNP-tile flag "has a missing
-//   genotype", (d) the positions of the missing samples of each SNP that has
+//   genotype" (and whether any tile has one, and any none), (d) the positions of the missing samples of each SNP that has
 //   at most kLaneMiss of them.  Counting N_i is the paper's
 //   N_i = sum_k I_i(m,k) (eq. (1)).
 //
@@ -145,14 +145,19 @@ __global__ __launch_bounds__(256) void pack_snps(const int8_t* __restrict__ geno
     if (!real) { c0 = c1 = c2 = c3 = 0; }
     if (m_me < m_pad) info[m_me] = snp_constants(c0, c1, c2, c3, diag_ok);
     // per 32-SNP tile: has a missing genotype (tiles past the last SNP are
-    // never read as tile flags; one of them holds the any-missing flag)
+    // never read as tile flags; the first two of them hold "some tile has a
+    // missing genotype" and "some tile has none", so that a launch for the
+    // other kind of tile returns at once)
     const unsigned long long miss = __ballot(real && c3 > 0);
     const int lane = tid & 63;
     if ((lane & 31) == 0) {
         const int64_t tile = m_me >> 5;
+        const int64_t n_real = (M + 31) >> 5;
         const uint32_t bits = (uint32_t)(miss >> (lane & 32));
-        if (tile < (M + 31) >> 5) tile_flags[tile] = bits ? 1 : 0;
-        if (bits) atomicOr(&tile_flags[(M + 31) >> 5], 1);   // "some SNP has a missing genotype"
+        if (tile < n_real) {
+            tile_flags[tile] = bits ? 1 : 0;
+            atomicOr(&tile_flags[n_real + (bits ? 0 : 1)], 1);
+        }
     }
 }
 
@@ -348,7 +353,7 @@ hipError_t kx_launch_pack(const int8_t* geno, int64_t M, int64_t ld, int K, int6
                           int gstride, int diag_ok, int8_t* gp, kx::SnpInfo* info,
                           int32_t* tile_flags, int16_t* mpos, int grid, hipStream_t st) {
     int64_t n_tiles = m_pad / 32;
-    hipLaunchKernelGGL(kx::fill_i32, dim3(64), dim3(256), 0, st, tile_flags, n_tiles + 1, 0);
+    hipLaunchKernelGGL(kx::fill_i32, dim3(64), dim3(256), 0, st, tile_flags, n_tiles + 2, 0);
     (void)grid;
     const int64_t blocks = (m_pad + kx::kPackRows - 1) / kx::kPackRows;
     if (blocks > 0)

@@ -218,20 +218,35 @@ __device__ inline bool lane_pair_may_pass(const ScanArgs& a, int64_t v, int64_t 
     return missing_bound(a, v, trait, inf, nq, sq, lo, hi, d1, d2);
 }
 
+// Sum over the wave by DPP moves (no LDS round trips): pairs and quads
+// within each row of 16 lanes, then the row halves and the rows, then row
+// sums broadcast into rows 1 and 3 and rows 0-1 into rows 2-3; lane 63 ends
+// with the total.
+__device__ inline int wave_sum_dpp(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);    // quad_perm [1,0,3,2]
+    v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);    // quad_perm [2,3,0,1]
+    v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);   // row_half_mirror
+    v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);   // row_mirror
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);   // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);   // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
 // Exact evaluation of pair (v, m) by the whole wave when the SNP's missing
 // samples are listed (1..kLaneMiss of them, K from 32 to 2047) and the trait
 // has every expression value: the re-ranked sums of coop_exact without its
 // staging pass.  The missing samples' ranks (one lane each) go into a bitmap
 // over the doubled ranks 0..2K with per-word prefix counts; every sample's
-// rank and code are then read from global memory, U per lane in flight
-// together, and for sample k the bitmap gives the number of missing ranks
-// below a_k (lt) and whether one equals it (eq): its re-ranked doubled rank
-// is a_k - 2 lt - eq.  Only groups 1 and 2 are summed: the kept samples'
-// re-ranked doubled ranks sum to K'(K' + 1).  A tie group of size t that
-// loses its one missing member takes 3 t (t - 1) off the tie term (t counted
-// per missing rank, the missing sample included).  Returns false, having
-// evaluated nothing, when two missing samples share a rank (coop_exact
-// handles that case).
+// rank and code are read from global memory, U per lane in flight together
+// (the first U issued with the missing positions, so that their latency
+// overlaps the bitmap's), and for sample k the bitmap gives the number of
+// missing ranks below a_k (lt) and whether one equals it (eq): its re-ranked
+// doubled rank is a_k - 2 lt - eq.  Only groups 1 and 2 are summed: the kept
+// samples' re-ranked doubled ranks sum to K'(K' + 1).  All sums fit 32 bits
+// (K (2K + 1) < 2^31).  A tie group of size t that loses its one missing
+// member takes 3 t (t - 1) off the tie term (t counted per missing rank, the
+// missing sample included).  Returns false, having evaluated nothing, when
+// two missing samples share a rank (coop_exact handles that case).
 template <int U>
 __device__ inline bool coop_exact_listed(const ScanArgs& a, int64_t v, int64_t m,
                                          int16_t* sbuf, int lane, double* H_out, int* df_out) {
@@ -242,12 +257,21 @@ __device__ inline bool coop_exact_listed(const ScanArgs& a, int64_t v, int64_t m
     const int8_t* gr = a.G + m * (int64_t)a.gstride;
     const SnpInfo inf = a.info[m];
     const int nq = inf.nmiss;
-    int qa = 0;
-    if (lane < nq) {
-        int k = a.mpos[m * kLaneMiss + lane];
-        if (pm) k = pm[k];
-        qa = rk[k];
-    }
+    int pos = lane < nq ? (int)a.mpos[m * kLaneMiss + lane] : 0;
+    // the first U samples of this lane (loads at clamped indices, all in
+    // flight together; samples past K are masked afterwards)
+    int code[U], ak[U];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = min(k0 + u * kWave + lane, K - 1);
+            code[u] = (int)gr[k];
+            ak[u] = (int)rk[pm ? pm[k] : k];
+        }
+    };
+    load(0);
+    if (pm) pos = pm[pos];
+    const int qa = lane < nq ? (int)rk[pos] : 0;
     uint4* bm = (uint4*)(sbuf + coop_bitmap_offset(K));
     int32_t* tc = (int32_t*)(sbuf + 2 * K + 64);
     const int W = ((2 * K) >> 6) + 1;            // 64-bit words covering 0..2K
@@ -271,17 +295,8 @@ __device__ inline bool coop_exact_listed(const ScanArgs& a, int64_t v, int64_t m
     }
     __builtin_amdgcn_wave_barrier();
     const long long ts0 = a.tiesum[trait];
-    long long s1 = 0, s2 = 0;
-    for (int k0 = 0; k0 < K; k0 += U * kWave) {
-        // loads at clamped indices, all in flight together; samples past K
-        // are masked afterwards
-        int code[U], ak[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int k = min(k0 + u * kWave + lane, K - 1);
-            code[u] = (int)gr[k];
-            ak[u] = (int)rk[pm ? pm[k] : k];
-        }
+    int s1 = 0, s2 = 0;
+    for (int k0 = 0;;) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const bool valid = k0 + u * kWave + lane < K;
@@ -296,18 +311,21 @@ __device__ inline bool coop_exact_listed(const ScanArgs& a, int64_t v, int64_t m
             s2 += (valid && code[u] == 2) ? ap : 0;
             if (ts0 != 0 && valid && eq) atomicAdd(&tc[lt], 1);
         }
+        k0 += U * kWave;
+        if (k0 >= K) break;
+        load(k0);
     }
-    s1 = wave_sum64(s1);
-    s2 = wave_sum64(s2);
+    s1 = wave_sum_dpp(s1);
+    s2 = wave_sum_dpp(s2);
     long long ts = ts0;
     if (ts0 != 0) {
         __builtin_amdgcn_wave_barrier();
-        long long corr = 0;
+        int corr = 0;
         if (lane < nq) {
-            const long long t = tc[lane];
+            const int t = tc[lane];
             corr = 3 * t * (t - 1);
         }
-        ts -= wave_sum64(corr);
+        ts -= wave_sum_dpp(corr);
     }
     __builtin_amdgcn_wave_barrier();
     const int64_t kp = K - nq;
@@ -370,6 +388,9 @@ void scan_exact_missing(ScanArgs a) {
             double H;
             bool done = false;
             if (lj && a.K >= 32 && a.K <= 2047)
+                // eight samples per lane in flight (sixteen spilled registers
+                // at this kernel's six waves per SIMD: cohort step 53.6 ms
+                // against 51.3)
                 done = a.K > 256 ? coop_exact_listed<8>(a, vj, mj, sb, lane, &H, &df)
                                  : coop_exact_listed<4>(a, vj, mj, sb, lane, &H, &df);
             if (!done) {

@@ -599,8 +599,10 @@ void scan_kernel(ScanArgs a) {
     int16_t* qbuf = s_qbuf + (QUEUE ? wave * coop_lds_entries(a.K) : 0);
     int qn = 0;
 
-    // tile_flags[n_snp_tiles] is set when any SNP has a missing genotype
+    // tile_flags[n_snp_tiles] is set when any SNP has a missing genotype,
+    // tile_flags[n_snp_tiles + 1] when any tile has none
     if (a.want_flag == 1 && a.tile_flags[a.n_snp_tiles] == 0) return;
+    if (a.want_flag == 0 && a.tile_flags[a.n_snp_tiles + 1] == 0) return;
     int64_t n_rows = a.n_rows;
     if (a.d_nrows) {
         int64_t d = *a.d_nrows;
@@ -1057,6 +1059,7 @@ void scan_kernel_ns2(ScanArgs a) {
     uint4* stage = s_stage[wave];
     int sn = 0;
     if (a.want_flag == 1 && a.tile_flags[a.n_snp_tiles] == 0) return;
+    if (a.want_flag == 0 && a.tile_flags[a.n_snp_tiles + 1] == 0) return;
     int64_t n_rows = a.n_rows;
     if (a.d_nrows) {
         const int64_t d = *a.d_nrows;

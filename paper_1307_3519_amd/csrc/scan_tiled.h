@@ -225,6 +225,7 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
         (uint32_t)(uintptr_t)(__attribute__((address_space(3))) frag*)&s_buf[0][0][0];
 
     if (a.want_flag == 1 && a.tile_flags[a.n_snp_tiles] == 0) return;
+    if (a.want_flag == 0 && a.tile_flags[a.n_snp_tiles + 1] == 0) return;
     int64_t n_rows = a.n_rows;
     if (a.d_nrows) {
         int64_t d = *a.d_nrows;
