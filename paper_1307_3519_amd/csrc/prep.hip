@@ -148,16 +148,20 @@ __global__ __launch_bounds__(256) void pack_snps(const int8_t* __restrict__ geno
     // never read as tile flags; the first two of them hold "some tile has a
     // missing genotype" and "some tile has none", so that a launch for the
     // other kind of tile returns at once)
+    // (one read and at most one atomic per block and flag: every tile taking
+    // an atomic on the same word serialised them, 70 -> 200 us at 500 000 SNPs)
     const unsigned long long miss = __ballot(real && c3 > 0);
     const int lane = tid & 63;
-    if ((lane & 31) == 0) {
-        const int64_t tile = m_me >> 5;
-        const int64_t n_real = (M + 31) >> 5;
-        const uint32_t bits = (uint32_t)(miss >> (lane & 32));
-        if (tile < n_real) {
-            tile_flags[tile] = bits ? 1 : 0;
-            atomicOr(&tile_flags[n_real + (bits ? 0 : 1)], 1);
-        }
+    const int64_t n_real = (M + 31) >> 5;
+    const int64_t tile = m_me >> 5;
+    const uint32_t bits = (uint32_t)(miss >> (lane & 32));
+    const bool lead = (lane & 31) == 0 && tile < n_real;
+    if (lead) tile_flags[tile] = bits ? 1 : 0;
+    const int any_miss = __syncthreads_or(lead && bits != 0u);
+    const int any_full = __syncthreads_or(lead && bits == 0u);
+    if (tid == 0) {
+        if (any_miss && tile_flags[n_real] == 0) atomicOr(&tile_flags[n_real], 1);
+        if (any_full && tile_flags[n_real + 1] == 0) atomicOr(&tile_flags[n_real + 1], 1);
     }
 }
 
