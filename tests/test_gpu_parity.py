@@ -88,7 +88,8 @@ def _ranks(kx, x):
 
 # ---------------------------------------------------------------- full / sums
 CASES = [  # (K, T, M, p_missing)
-    (5, 40, 37, 0.0), (33, 70, 100, 0.0), (102, 70, 161, 0.0), (102, 33, 65, 0.05),
+    (5, 40, 37, 0.0), (20, 70, 100, 0.1), (33, 70, 100, 0.0), (102, 70, 161, 0.0),
+    (102, 33, 65, 0.05),
     (128, 65, 64, 0.0), (48, 64, 96, 0.1), (77, 31, 40, 0.03),
     # tiled large-K kernels: ragged trait blocks (T % 128) and SNP blocks (M % 128),
     # the DIAG / PLAIN boundary at K = 400 / 401, byte-split int8 ranks
@@ -266,13 +267,14 @@ def test_small_workload_full_matrices(kx):
 
 
 def test_heavy_missing_per_snp(kx):
-    # SNPs with 0 .. 150 missing samples: the sorted-rank re-rank (up to 64
-    # missing) and the pairwise one (more than 64), ties in every trait
+    # SNPs with 0 .. 200 missing samples: listed positions (up to 32) and the
+    # packed-row bound beyond, the sorted-rank re-rank (up to 64 missing) and
+    # the pairwise one (more than 64), ties in every trait
     say("heavy missing")
-    K, T, M = 233, 50, 40
+    K, T, M = 233, 50, 48
     x, g = _inputs(61, T, K, M, tie_frac=0.2)
     rs = datagen.streams(62)["missing"]
-    for m, nmiss in enumerate([0, 1, 5, 30, 63, 64, 65, 100, 150, 200] * 4):
+    for m, nmiss in enumerate([0, 1, 5, 30, 32, 33, 63, 64, 65, 100, 150, 200] * 4):
         idx = rs.choice(K, size=nmiss, replace=False)
         g[m, idx] = -1
     r, ts = _ranks(kx, x)
