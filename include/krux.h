@@ -164,7 +164,7 @@ krux_status krux_test(krux_ctx* ctx, const int16_t* ranks2, const int64_t* tiesu
  * working buffer is carved from a static device array of
  * KRUX_NOALLOC_SCRATCH_BYTES per GPU instead of the context's scratch; no
  * hipMalloc, hipFree or allocating library routine is called.  A call whose
- * working set (about 160 B per SNP at K <= 128, more for the tiled K > 128
+ * working set (about 224 B per SNP at K <= 128, more for the tiled K > 128
  * path; the A operand, twice with per-trait minimum p; 48 B per hit of
  * hit_capacity) exceeds the array returns KRUX_ERR_UNSUPPORTED before
  * anything is launched.  The screened-pair buffers are capped at a few MB
