@@ -6,7 +6,8 @@
 // classic two-operand tiled GEMM: each wave computes 2 or 4 trait tiles x 1
 // or 2 SNP tiles, in blocks of four waves (one or two blocks per CU) or of
 // eight (one per CU); see TiledShape for the four shapes.  The K loop runs
-// over chunks of two 16-sample (fp16) or 32-sample (int8) k-steps whose A
+// over chunks of two 16-sample (fp16) or 32-sample (int8) k-steps (four in
+// the fp16 eight-wave blocks when the k-step count allows) whose A
 // (centred ranks) fragments and B side (genotype columns expanded once into
 // MFMA fragment order, or the packed genotype codes themselves, from which
 // the fragments are built in registers) are copied into an LDS ring by
@@ -84,7 +85,7 @@ __device__ inline float screen_value(const LaneK& c, float th, float v0, float v
 //        where the expanded columns took 16 KB and 12 KB, and the ring holds
 //        eight chunks instead of four), expanded in the int8 missing-genotype
 //        form.
-template <int FORM, bool SPLIT, int V>
+template <int FORM, bool SPLIT, int V, int KCX = 2>
 struct TiledShape {
     static constexpr int NC = FORM == MISS3 ? 3 : 2;
     static constexpr int NP = SPLIT ? 2 : 1;
@@ -111,10 +112,11 @@ struct TiledShape {
     static constexpr int WPE_MIN = (V != 0 && ACC <= 128) ? 2 : 1;
     static constexpr int RING_BYTES =
         V == 0 ? 128 * 1024 : V == 3 ? (FORM == MISS3 ? 128 * 1024 : 140 * 1024) : 72 * 1024;
-    static constexpr int KC = 2;                         // k-steps per chunk
-    // codes shapes: 1 KB copies of codes per SNP tile and chunk (64 lanes x
-    // 16 codes: 32 fp16 samples or 64 int8 samples of 32 SNPs)
-    static constexpr int CPT = SPLIT ? 2 : 1;
+    static constexpr int KC = KCX;                       // k-steps per chunk (2 or 4)
+    // codes shapes: 1 KB copies of codes (64 lanes x 16 codes: 32 samples of
+    // 32 SNPs), KC / 2 per SNP tile and chunk in fp16 (16-sample k-steps),
+    // KC in int8 (32-sample k-steps)
+    static constexpr int CPT = SPLIT ? KC : KC / 2;
     static constexpr int NFA = BT * KC * NP;             // A fragments per chunk
     static constexpr int NFB = CODES ? BS * CPT : BS * KC * NC;
     static constexpr int NF = NFA + NFB;                 // 1 KB copies per chunk
@@ -156,20 +158,20 @@ __device__ inline uint32_t i8_ind(uint32_t w, int k) {
 // The missing-genotype form re-ranks pairs in its epilogue with per-wave LDS
 // scratch (coop_lds_entries); the ring is idle then and holds it when large
 // enough, else the launch adds dynamic LDS.
-template <int FORM, bool SPLIT, int V>
+template <int FORM, bool SPLIT, int V, int KCX = 2>
 __host__ __device__ inline bool tiled_scratch_in_ring(int K) {
-    return (int64_t)TiledShape<FORM, SPLIT, V>::NW * coop_lds_entries(K) * (int64_t)sizeof(int16_t) <=
-           TiledShape<FORM, SPLIT, V>::RING_USED;
+    return (int64_t)TiledShape<FORM, SPLIT, V, KCX>::NW * coop_lds_entries(K) * (int64_t)sizeof(int16_t) <=
+           TiledShape<FORM, SPLIT, V, KCX>::RING_USED;
 }
 
-template <int E, int FORM, int MODE, bool SPLIT, int V>
-__global__ __launch_bounds__((TiledShape<FORM, SPLIT, V>::NW * 64))
-__attribute__((amdgpu_waves_per_eu(TiledShape<FORM, SPLIT, V>::WPE_MIN, 2)))
+template <int E, int FORM, int MODE, bool SPLIT, int V, int KCX = 2>
+__global__ __launch_bounds__((TiledShape<FORM, SPLIT, V, KCX>::NW * 64))
+__attribute__((amdgpu_waves_per_eu(TiledShape<FORM, SPLIT, V, KCX>::WPE_MIN, 2)))
 void scan_tiled(ScanArgs a, TiledArgs ta) {
     using T_ = ET<E>;
     using frag = typename T_::frag;
     using acc_t = typename T_::acc;
-    using SH = TiledShape<FORM, SPLIT, V>;
+    using SH = TiledShape<FORM, SPLIT, V, KCX>;
     constexpr int NC = SH::NC;
     constexpr int WS = SH::WS;                         // SNP tiles per wave
     constexpr int NP = SH::NP;                         // A planes
@@ -216,7 +218,7 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
     int4* queue = s_queue[QUEUE ? wave : 0];
     uint4* stage = s_stage[MODE == SCREEN ? wave : 0];
     int sn = 0, qn = 0;
-    int16_t* qbuf = (QUEUE && tiled_scratch_in_ring<FORM, SPLIT, V>(a.K) ? (int16_t*)&s_buf[0][0][0]
+    int16_t* qbuf = (QUEUE && tiled_scratch_in_ring<FORM, SPLIT, V, KCX>(a.K) ? (int16_t*)&s_buf[0][0][0]
                                                                           : s_qbuf) +
                     (QUEUE ? wave * coop_lds_entries(a.K) : 0);
 
@@ -308,7 +310,7 @@ void scan_tiled(ScanArgs a, TiledArgs ta) {
                 const int g = f < NF ? f - NFA : 0;
                 const int s2 = g / SH::CPT, part = g % SH::CPT;
                 const int64_t m = (sb * BS + s2) * kTile + (lane & 31);
-                cp[i] = (const uint8_t*)a.G + m * (int64_t)a.gstride + part * T_::kps +
+                cp[i] = (const uint8_t*)a.G + m * (int64_t)a.gstride + part * 32 +
                         16 * (lane >> 5);
                 cstride[i] = KC * T_::kps;
             } else {
@@ -616,12 +618,12 @@ __global__ __launch_bounds__(256) void expand_columns(const int8_t* __restrict__
     }
 }
 
-template <int E, int FORM, int MODE, bool SPLIT, int V>
+template <int E, int FORM, int MODE, bool SPLIT, int V, int KCX = 2>
 inline hipError_t launch_tiled_v(const ScanArgs& a, const TiledArgs& ta, int grid, hipStream_t st) {
-    using SH = TiledShape<FORM, SPLIT, V>;
-    const size_t lds = FORM == MISS3 && !tiled_scratch_in_ring<FORM, SPLIT, V>(a.K)
+    using SH = TiledShape<FORM, SPLIT, V, KCX>;
+    const size_t lds = FORM == MISS3 && !tiled_scratch_in_ring<FORM, SPLIT, V, KCX>(a.K)
                            ? (size_t)SH::NW * coop_lds_entries(a.K) * sizeof(int16_t) : 0;
-    auto kern = scan_tiled<E, FORM, MODE, SPLIT, V>;
+    auto kern = scan_tiled<E, FORM, MODE, SPLIT, V, KCX>;
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, SH::NW * 64, lds) != hipSuccess ||
         occ < 1)
@@ -636,15 +638,23 @@ inline hipError_t launch_tiled_v(const ScanArgs& a, const TiledArgs& ta, int gri
 }
 
 // The codes shapes (2, 3) cover the complete-SNP screen (the host runs PLAIN
-// in place of DIAG there); the missing-genotype form keeps expanded columns
-// (built from codes its registers overflow), in eight-wave blocks for shape
-// 3 (the host runs it as shape 1 under shape 2).
+// in place of DIAG there); the missing-genotype form reads the codes in the
+// fp16 eight-wave blocks of shape 3 and keeps expanded columns otherwise
+// (the host runs it as shape 1 under shape 2).  The fp16 eight-wave blocks
+// take four k-steps per ring chunk when the k-step count allows (half the
+// block barriers and waits per MFMA).
 template <int E, int FORM, int MODE, bool SPLIT>
 inline hipError_t launch_tiled(const ScanArgs& a, const TiledArgs& ta, int grid, hipStream_t st) {
     if constexpr (FORM == PLAIN) {
+        if constexpr (!SPLIT)
+            if (ta.shape == 3 && ta.ks % 4 == 0)
+                return launch_tiled_v<E, FORM, MODE, SPLIT, 3, 4>(a, ta, grid, st);
         if (ta.shape == 3) return launch_tiled_v<E, FORM, MODE, SPLIT, 3>(a, ta, grid, st);
         if (ta.shape == 2) return launch_tiled_v<E, FORM, MODE, SPLIT, 2>(a, ta, grid, st);
     } else if constexpr (FORM == MISS3) {
+        if constexpr (!SPLIT)
+            if (ta.shape == 3 && ta.ks % 4 == 0)
+                return launch_tiled_v<E, FORM, MODE, SPLIT, 3, 4>(a, ta, grid, st);
         if (ta.shape == 3) return launch_tiled_v<E, FORM, MODE, SPLIT, 3>(a, ta, grid, st);
     }
     if (ta.shape == 0) return launch_tiled_v<E, FORM, MODE, SPLIT, 0>(a, ta, grid, st);
